@@ -1,0 +1,371 @@
+"""Pins of the oracle's convolutions, setup network and solve network against
+library routines, textbook multigrid operators and special cases (CPU only)."""
+import numpy as np
+import pytest
+import scipy.signal as sg
+import scipy.sparse as sps
+
+import datagen
+from oracle import network as net
+from oracle import operator as op
+from oracle import solve as sv
+
+
+def _rand(rng, *shape):
+    return rng.standard_normal(shape)
+
+
+# ----------------------------------------------------------------------------------------------
+# convolution primitives vs scipy.signal
+# ----------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 3, 7, 12])
+def test_conv_same_vs_scipy(n):
+    rng = np.random.default_rng(n)
+    W = _rand(rng, 3, 2, 3, 3)
+    x = _rand(rng, 2, n, n)
+    got = net.conv_same(W, x)
+    for o in range(3):
+        ref = sum(sg.correlate2d(x[c], W[o, c], mode="same", boundary="fill", fillvalue=0) for c in range(2))
+        np.testing.assert_allclose(got[o], ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("m", [3, 7, 15, 31])
+def test_conv_s2_vs_scipy(m):
+    rng = np.random.default_rng(m)
+    W = _rand(rng, 2, 3, 3, 3)
+    x = _rand(rng, 3, m, m)
+    got = net.conv_s2(W, x)
+    mc = (m - 1) // 2
+    assert got.shape == (2, mc, mc)
+    for o in range(2):
+        ref = sum(sg.correlate2d(x[c], W[o, c], mode="valid")[::2, ::2] for c in range(3))
+        np.testing.assert_allclose(got[o], ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("mc", [1, 3, 7])
+def test_convT_s2_vs_scipy(mc):
+    """Transposed stride-2 conv = zero-upsampling followed by a full convolution."""
+    rng = np.random.default_rng(mc)
+    W = _rand(rng, 3, 2, 3, 3)             # (C_in, C_out, 3, 3)
+    x = _rand(rng, 3, mc, mc)
+    got = net.convT_s2(W, x)
+    assert got.shape == (2, 2 * mc + 1, 2 * mc + 1)
+    for o in range(2):
+        ref = np.zeros((2 * mc + 1, 2 * mc + 1))
+        for c in range(3):
+            up = np.zeros((2 * mc - 1, 2 * mc - 1)); up[::2, ::2] = x[c]
+            ref += sg.convolve2d(up, W[c, o], mode="full")
+        np.testing.assert_allclose(got[o], ref, rtol=1e-12, atol=1e-12)
+
+
+def test_stride2_adjoint_identity():
+    rng = np.random.default_rng(11)
+    W = _rand(rng, 4, 4, 3, 3)
+    x = _rand(rng, 4, 15, 15)
+    y = _rand(rng, 4, 7, 7)
+    lhs = np.sum(net.conv_s2(W, x) * y)
+    rhs = np.sum(x * net.convT_s2(W, y))
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+def _P1(mc):
+    m = 2 * mc + 1
+    P = np.zeros((m, mc))
+    for I in range(mc):
+        P[2 * I + 1, I] = 1.0
+        P[2 * I, I] += 0.5
+        P[2 * I + 2, I] += 0.5
+    return P
+
+
+def test_full_weighting_and_bilinear_are_textbook():
+    """Channel-diagonal FW kernel [1 2 1; 2 4 2; 1 2 1]/16 in the stride-2 conv and
+    bilinear kernel [1 2 1; 2 4 2; 1 2 1]/4 in the transposed conv equal the
+    vertex-centred operators R = P^T / 4 and P = kron(P1, P1)."""
+    mc = 7
+    m = 2 * mc + 1
+    k = np.outer([1, 2, 1], [1, 2, 1]).astype(float)
+    W_R = np.zeros((2, 2, 3, 3)); W_T = np.zeros((2, 2, 3, 3))
+    for c in range(2):
+        W_R[c, c] = k / 16
+        W_T[c, c] = k / 4
+    P = sps.kron(_P1(mc), _P1(mc)).toarray()
+    rng = np.random.default_rng(2)
+    x = _rand(rng, 2, m, m)
+    y = _rand(rng, 2, mc, mc)
+    for c in range(2):
+        np.testing.assert_allclose(net.conv_s2(W_R, x)[c].ravel(), 0.25 * P.T @ x[c].ravel(), rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(net.convT_s2(W_T, y)[c].ravel(), P @ y[c].ravel(), rtol=1e-13, atol=1e-14)
+
+
+# ----------------------------------------------------------------------------------------------
+# weights
+# ----------------------------------------------------------------------------------------------
+
+def test_weight_layout_roundtrip():
+    for C in (4, 8, 16):
+        w = datagen.xavier_weights(C, 0)
+        assert w.size == 81 * C * C + 58 * C == datagen.num_weights(C)
+        P = net.unpack_weights(w, C)
+        np.testing.assert_array_equal(net.pack_weights(P, C), w.astype(np.float64))
+        assert all(np.all(P[f"beta_k{k}"] == 0) for k in range(4))
+    assert datagen.num_weights(16) == 21664
+
+
+def _zero_net(C):
+    return {k: np.zeros_like(v) for k, v in net.unpack_weights(np.zeros(81 * C * C + 58 * C), C).items()}
+
+
+# ----------------------------------------------------------------------------------------------
+# setup network special cases
+# ----------------------------------------------------------------------------------------------
+
+def test_setup_special_cases():
+    C, n = 3, 15
+    L = net.num_levels(n)
+    rng = np.random.default_rng(4)
+    F = rng.uniform(0, 1, (4, n, n))
+    P = _zero_net(C)
+    P["W_sc"] = rng.standard_normal((C, 4, 3, 3))
+    P["W_sr"] = rng.standard_normal((C, C, 3, 3)) * 0.3
+    # zero ResNet layers: s_l = c_l
+    s = net.setup(P, F, L)
+    c = net.conv_same(P["W_sc"], F)
+    for l in range(L):
+        np.testing.assert_allclose(s[l], c, rtol=1e-13, atol=1e-13)
+        if l < L - 1:
+            c = net.conv_s2(P["W_sr"], c)
+    # bias-only layers: s_l = c_l + sum_k tanh(beta_k), per channel, in layer order
+    betas = [rng.standard_normal(C) for _ in range(4)]
+    for k in range(4):
+        P[f"beta_k{k}"] = betas[k]
+    s = net.setup(P, F, L)
+    shift = sum(np.tanh(bk) for bk in betas)
+    c = net.conv_same(P["W_sc"], F)
+    np.testing.assert_allclose(s[0], c + shift[:, None, None], rtol=1e-13, atol=1e-13)
+    # centre-tap channel-diagonal layers act pointwise: z <- z + tanh(w_k z + beta_k)
+    for k in range(4):
+        Wk = np.zeros((C, C, 3, 3))
+        wk = rng.standard_normal(C)
+        for ch in range(C):
+            Wk[ch, ch, 1, 1] = wk[ch]
+        P[f"W_k{k}"] = Wk
+    s = net.setup(P, F, L)
+    z = net.conv_same(P["W_sc"], F)
+    for k in range(4):
+        wk = np.array([P[f"W_k{k}"][ch, ch, 1, 1] for ch in range(C)])
+        z = z + np.tanh(wk[:, None, None] * z + betas[k][:, None, None])
+    np.testing.assert_allclose(s[0], z, rtol=1e-12, atol=1e-12)
+    # setup does not depend on the right-hand side: it only sees F
+    assert len(s) == L and s[-1].shape == (C, 1, 1)
+
+
+# ----------------------------------------------------------------------------------------------
+# solve network special cases
+# ----------------------------------------------------------------------------------------------
+
+def _jacobi_weights(C, omega):
+    P = _zero_net(C)
+    P["W_in"][0, 0, 1, 1] = 1.0
+    P["W_out"][0, 0, 1, 1] = omega
+    return net.pack_weights(P, C)
+
+
+def test_jacobi_special_case_is_weighted_jacobi():
+    """W_in = delta on channel 0, W_out = omega delta, all smoother/transfer
+    weights zero: the solve network is omega * I on r/D, so one iteration is
+    exactly weighted Jacobi u + omega D^-1 (f - A u)."""
+    C, n, omega = 4, 15, 0.8
+    rng = np.random.default_rng(8)
+    a = np.exp(rng.standard_normal((n, n)))
+    b = (1.0, -0.5)
+    f = rng.uniform(-1, 1, (n, n))
+    S = sv.Solver(_jacobi_weights(C, omega), a, b)
+    A = op.assemble_A(a, b)
+    d = A.diagonal()
+    u = rng.standard_normal((n, n))
+    ref = u.ravel() + omega * (f.ravel() - A @ u.ravel()) / d
+    np.testing.assert_allclose(S.step(f, u).ravel(), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_jacobi_residual_l1_monotone_and_converges_to_direct_solve():
+    """||I - omega A D^-1||_1 <= 1 by column diagonal dominance, so the l1 residual
+    never grows; on a tiny grid the iteration reaches the direct solution."""
+    import scipy.sparse.linalg as spla
+    C, n = 2, 7
+    rng = np.random.default_rng(9)
+    a = 10.0 ** rng.uniform(-1, 1, (n, n))
+    b = (1.0, 1.0)
+    f = rng.uniform(-1, 1, (n, n))
+    for omega in (0.5, 1.0):
+        S = sv.Solver(_jacobi_weights(C, omega), a, b)
+        u = np.zeros((n, n))
+        prev = np.abs(S.residual(f, u)).sum()
+        for _ in range(60):
+            u = S.step(f, u)
+            cur = np.abs(S.residual(f, u)).sum()
+            assert cur <= prev * (1 + 1e-12)
+            prev = cur
+    S = sv.Solver(_jacobi_weights(C, 1.0), a, b)
+    u, status, iters, rho, _ = S.solve(f, 1e-12, 5000)
+    assert status == sv.OK
+    u_ref = spla.spsolve(op.assemble_A(a, b).tocsc(), f.ravel()).reshape(n, n)
+    np.testing.assert_allclose(u, u_ref, rtol=1e-8, atol=1e-10 * np.abs(u_ref).max())
+
+
+def test_additive_special_case_is_sum_of_transfers():
+    """Zero smoothers, full-weighting restriction, bilinear prolongation and
+    channel-0 identities in/out: B = omega * sum_{l=0}^{L-1} P^l R^l on r/D
+    (pins stride, padding and the order of the up loop)."""
+    C, n, omega = 2, 15, 0.7
+    L = net.num_levels(n)
+    P = _zero_net(C)
+    k = np.outer([1, 2, 1], [1, 2, 1]).astype(float)
+    P["W_in"][0, 0, 1, 1] = 1.0
+    P["W_out"][0, 0, 1, 1] = omega
+    P["W_R"][0, 0] = k / 16
+    P["W_T"][0, 0] = k / 4
+    w = net.pack_weights(P, C)
+    rng = np.random.default_rng(12)
+    a = np.exp(rng.standard_normal((n, n)))
+    b = (0.3, 0.2)
+    r = rng.standard_normal((n, n))
+    S = sv.Solver(w, a, b)
+    got = S.correction(r)
+    # textbook matrices, level by level
+    Ps = []
+    m = n
+    while m > 1:
+        mc = (m - 1) // 2
+        Ps.append(sps.kron(_P1(mc), _P1(mc)).tocsr())
+        m = mc
+    rt = (r / op.diagonal(a, b)).ravel()
+    acc = np.zeros_like(rt)
+    for l in range(L):
+        v = rt.copy()
+        for j in range(l):
+            v = 0.25 * (Ps[j].T @ v)
+        for j in range(l - 1, -1, -1):
+            v = Ps[j] @ v
+        acc += v
+    np.testing.assert_allclose(got.ravel(), omega * acc, rtol=1e-12, atol=1e-13)
+
+
+def test_linearity_in_rhs():
+    """Principle P2: u_K is linear in f for u_0 = 0."""
+    C, n, K = 4, 15, 3
+    rng = np.random.default_rng(13)
+    w = datagen.xavier_weights(C, 1)
+    a = np.exp(rng.standard_normal((n, n)))
+    b = (1.0, 1.0)
+    f, g = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    al, be = 0.7, -1.3
+    S = sv.Solver(w, a, b)
+    lhs = S.forward(al * f + be * g, K)
+    rhs = al * S.forward(f, K) + be * S.forward(g, K)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-11 * np.abs(rhs).max())
+
+
+def test_level_shapes_and_coarsest_centre_tap():
+    C, n = 3, 31
+    rng = np.random.default_rng(14)
+    w = datagen.xavier_weights(C, 2)
+    a = np.exp(rng.standard_normal((n, n)))
+    S = sv.Solver(w, a, (1.0, 1.0))
+    assert S.L == 5
+    assert [sl.shape[1] for sl in S.s] == [31, 15, 7, 3, 1]
+    # on a 1x1 grid only the centre tap of a same-size conv acts
+    W = rng.standard_normal((2, 2, 3, 3))
+    x = rng.standard_normal((2, 1, 1))
+    np.testing.assert_allclose(net.conv_same(W, x)[:, 0, 0], W[:, :, 1, 1] @ x[:, 0, 0], rtol=1e-14)
+
+
+def test_non_power_of_two_rejected():
+    with pytest.raises(ValueError):
+        net.num_levels(30)
+
+
+def test_pointwise_smoothers_multilevel_closed_form():
+    """Centre-tap channel-0 smoothers act pointwise, x <- (1 + alpha s_l) x on the
+    way down and (1 + beta s_l) x on the way up; with full weighting / bilinear
+    transfers the whole network is a product of textbook sparse matrices and
+    diagonal scalings by the setup tensors of the matching level (pins where the
+    setup tensor multiplies, which kernel each loop uses, and the order
+    smoother -> restrict and prolong-add -> smoother)."""
+    C, n, omega, alpha, beta = 2, 15, 0.9, 0.37, -0.21
+    L = net.num_levels(n)
+    rng = np.random.default_rng(31)
+    P = _zero_net(C)
+    k = np.outer([1, 2, 1], [1, 2, 1]).astype(float)
+    P["W_in"][0, 0, 1, 1] = 1.0
+    P["W_out"][0, 0, 1, 1] = omega
+    P["W_R"][0, 0] = k / 16
+    P["W_T"][0, 0] = k / 4
+    P["W_dn"][0, 0, 1, 1] = alpha
+    P["W_up"][0, 0, 1, 1] = beta
+    P["W_sc"] = rng.standard_normal((C, 4, 3, 3))
+    P["W_sr"] = 0.5 * rng.standard_normal((C, C, 3, 3))
+    w = net.pack_weights(P, C)
+    a = np.exp(rng.standard_normal((n, n)))
+    b = (0.5, -1.0)
+    S = sv.Solver(w, a, b)
+    r = rng.standard_normal((n, n))
+    got = S.correction(r)
+    # reference: s_l channel 0 from the (scipy-pinned) setup convs, textbook transfers
+    F = op.features(a, b)
+    c = net.conv_same(P["W_sc"], F)
+    s0 = []
+    for l in range(L):
+        s0.append(c[0].ravel())
+        if l < L - 1:
+            c = net.conv_s2(P["W_sr"], c)
+    Ps, m = [], n
+    while m > 1:
+        mc = (m - 1) // 2
+        Ps.append(sps.kron(_P1(mc), _P1(mc)).tocsr())
+        m = mc
+    x = (r / op.diagonal(a, b)).ravel()
+    xdn = []
+    for l in range(L):
+        x = (1 + alpha * s0[l]) * x
+        xdn.append(x)
+        if l < L - 1:
+            x = 0.25 * (Ps[l].T @ x)
+    xup = (1 + beta * s0[L - 1]) * xdn[L - 1]
+    for l in range(L - 2, -1, -1):
+        v = xdn[l] + Ps[l] @ xup
+        xup = (1 + beta * s0[l]) * v
+    np.testing.assert_allclose(got.ravel(), omega * xup, rtol=1e-12, atol=1e-13)
+
+
+def test_shifted_smoothers_order():
+    """One level (transfers zero): a down smoother reading the east neighbour and an
+    up smoother reading the north neighbour do not commute, so the result pins
+    that the down smoother runs first and that each multiplies s before the conv."""
+    C, n, alpha, beta = 2, 7, 0.6, -0.4
+    rng = np.random.default_rng(32)
+    P = _zero_net(C)
+    P["W_in"][0, 0, 1, 1] = 1.0
+    P["W_out"][0, 0, 1, 1] = 1.0
+    P["W_dn"][0, 0, 1, 2] = alpha       # tap (p, q) = (1, 2): x[i, j+1]
+    P["W_up"][0, 0, 2, 1] = beta        # tap (2, 1): x[i+1, j]
+    P["W_sc"] = rng.standard_normal((C, 4, 3, 3))
+    w = net.pack_weights(P, C)
+    a = np.exp(rng.standard_normal((n, n)))
+    b = (1.0, 1.0)
+    S = sv.Solver(w, a, b)
+    r = rng.standard_normal((n, n))
+    got = S.correction(r)
+    s0 = net.conv_same(P["W_sc"], op.features(a, b))[0]
+
+    def east(z):
+        out = np.zeros_like(z); out[:, :-1] = z[:, 1:]; return out
+
+    def north(z):
+        out = np.zeros_like(z); out[:-1, :] = z[1:, :]; return out
+    # level 1 only contributes to the output when the coarse levels see zero
+    x = r / op.diagonal(a, b)
+    xdn = x + alpha * east(s0 * x)
+    xup = xdn + beta * north(s0 * xdn)
+    np.testing.assert_allclose(got, xup, rtol=1e-12, atol=1e-13)
