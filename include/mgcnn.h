@@ -1,0 +1,133 @@
+/*
+ * mgcnn.h -- C interface of the MI355X (gfx950) MGCNN solver library (libmgcnn.so).
+ *
+ * MGCNN (Xie, Lv, Zhang, "MGCNN: a learnable multigrid solver for sparse linear systems
+ * from PDEs on structured grids") solves A(a,b) u = f, the zero-Dirichlet discretisation of
+ *     -div(a grad u) + b . grad u = f   on the unit square, n x n interior nodes,
+ * with the stationary iteration u_{k+1} = u_k + B(f - A u_k) (Sec. 2.2, Eq. (1)), where B is
+ * a learned, linear multilevel convolutional network (the "decoder" of Sec. 2.1).  B is
+ * built once per problem from a (setup phase, Sec. 3.2, Alg. 2) and applied every iteration
+ * (solve phase, Sec. 3.3, Alg. 3).  Training minimises the residual loss (Sec. 3.4, Eq. (19)).
+ *
+ * Conventions shared by every entry point
+ *   - Grid: n = 2^L - 1 (3 <= n <= 4095), h = 1/(n+1), L = log2(n+1) levels, level l has
+ *     2^(L-l+1) - 1 points per side, the coarsest is 1 x 1.
+ *   - Fields are row-major [batch][n][n] (index i*n + j, j along +x, i along +y), contiguous,
+ *     16-byte aligned, in DEVICE memory owned by the caller.  `b` (the constant velocity of
+ *     each problem, [batch][2] = (bx, by)) is in HOST memory.
+ *   - Operator: divergence-form 5-point diffusion with harmonic-mean face coefficients (a
+ *     boundary face uses the interior node's a) plus first-order upwind convection (Sec. 2.5,
+ *     Eqs. (8)-(12)); physical scaling 1/h^2 and 1/h.  D = diag(A).  The network acts on the
+ *     row-scaled residual (f - A u) / D.
+ *   - Weights: one flat float32 host vector of mgcnn_num_weights(16) = 21664 entries in the
+ *     order: setup reChannel [16][4][3][3]; 4 x (setup ResNet conv [16][16][3][3], bias [16]);
+ *     setup restriction [16][16][3][3]; solve reChannel-in [16][1][3][3]; down smoother, up
+ *     smoother, restriction [16][16][3][3]; prolongation (transposed conv, [C_in][C_out][3][3]);
+ *     reChannel-out [1][16][3][3].  Convolutions are cross-correlations with zero padding 1
+ *     (same size) or no padding (stride 2, n -> (n-1)/2 and back to 2m+1).
+ *   - Streams: every call enqueues on the context's HIP stream and returns without a host
+ *     synchronisation unless stated.  A context is not thread-safe; contexts are independent.
+ *   - Errors: every call returns a status (never aborts).  Argument errors are detected before
+ *     any launch.  mgcnn_last_error() gives a message for the last failure of a context.
+ */
+#ifndef MGCNN_H
+#define MGCNN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgcnn_ctx mgcnn_ctx;
+
+/* Status codes. */
+enum {
+  MGCNN_OK = 0,
+  MGCNN_NOT_CONVERGED = 1,   /* maxit reached (solve) */
+  MGCNN_E_ARG = -1,          /* invalid argument (null pointer, tol <= 0, maxit < 0, ...) */
+  MGCNN_E_SIZE = -2,         /* n not of the form 2^L - 1, or outside [3, 4095], batch < 1 */
+  MGCNN_E_STATE = -3,        /* call order violated (e.g. solve before setup) */
+  MGCNN_E_NOMEM = -4,        /* device allocation failed */
+  MGCNN_E_HIP = -5,          /* a HIP runtime call failed; see mgcnn_last_error */
+  MGCNN_E_DIVERGED = -6,     /* relative residual non-finite or > 1e10 (solve) */
+  MGCNN_E_NORECORD = -7      /* backward without a recorded forward */
+};
+
+/* Precision of the network state, setup tensors and conv weights. */
+enum { MGCNN_F32 = 0, MGCNN_BF16 = 1 };
+/* Precision of u, of the residual arithmetic and of the stopping test. */
+enum { MGCNN_U_F32 = 0, MGCNN_U_F64 = 1 };
+
+typedef struct {
+  int channels;     /* hidden channels; must be 16 */
+  int state_dtype;  /* MGCNN_F32 or MGCNN_BF16 (bf16 storage, MFMA with f32 accumulation) */
+  int u_dtype;      /* MGCNN_U_F32: u float32, residual in f32 arithmetic;
+                       MGCNN_U_F64: u float64, residual in f64 arithmetic */
+  int use_graph;    /* 1: capture each block of check_every iterations in a hipGraph */
+  int check_every;  /* iterations between host convergence checks in mgcnn_solve (>= 1) */
+} mgcnn_opts;
+
+/* Default options: 16 channels, f32 state, f64 u, graphs on, check every 4 iterations. */
+void mgcnn_default_opts(mgcnn_opts *opts);
+
+/* Number of weights for `channels` hidden channels: 81 C^2 + 58 C. */
+size_t mgcnn_num_weights(int channels);
+
+/* Create a context.  `weights_host` (may be NULL: all zero) is copied.  `hip_stream` is a
+ * hipStream_t (NULL = default stream).  The context owns all device workspace. */
+int mgcnn_create(mgcnn_ctx **ctx, const mgcnn_opts *opts, const float *weights_host,
+                 void *hip_stream);
+
+/* Replace the weights (copied from host).  The setup tensors of the current problem set are
+ * NOT recomputed: call mgcnn_setup again. */
+int mgcnn_set_weights(mgcnn_ctx *ctx, const float *weights_host);
+
+/* Change the stream used by subsequent calls. */
+int mgcnn_set_stream(mgcnn_ctx *ctx, void *hip_stream);
+
+/* Setup phase (Sec. 3.2, Alg. 2) for `batch` problems of side n: a [batch][n][n] device
+ * (a > 0), b [batch][2] host.  The library copies a and b; `a` need not outlive the call.
+ * Computes and keeps the per-level setup tensors. */
+int mgcnn_setup(mgcnn_ctx *ctx, const float *a, const float *b_host, int n, int batch);
+
+/* Tolerance-driven solve (Sec. 2.2, Eq. (1); stop on the relative residual as in Sec. 4.1).
+ * f: [batch][n][n] float32 device.  u: [batch][n][n] device, float32 or float64 per
+ * opts.u_dtype; on entry the initial guess, on exit the last iterate.
+ * Per problem, at iterate k: rho_k = ||f - A u_k||_2 / ||f||_2; stop with OK if rho_k <= tol
+ * (iters = k), NOT_CONVERGED if k == maxit, DIVERGED if rho_k is not finite or > 1e10;
+ * otherwise apply one V-cycle.  A zero f gives u = 0, iters = 0, OK.
+ * iters_host [batch], relres_host [batch], status_host [batch] (each may be NULL) receive the
+ * per-problem results.  Return: OK if every problem converged, else E_DIVERGED if any
+ * diverged, else NOT_CONVERGED.  Blocks the host until the solve has finished. */
+int mgcnn_solve(mgcnn_ctx *ctx, const float *f, void *u, double tol, int maxit,
+                int *iters_host, double *relres_host, int *status_host);
+
+/* K unrolled iterations, no stopping test (training / timing): u <- K applications of
+ * u + B((f - A u)/D).  If record != 0 the iterates u_0..u_{K-1} are checkpointed for
+ * mgcnn_backward (state must be MGCNN_F32 and u MGCNN_U_F32). */
+int mgcnn_forward(mgcnn_ctx *ctx, const float *f, void *u, int K, int record);
+
+/* Apply the network once: z = B(r / D) for a residual r [batch][n][n] float32 device;
+ * z float32 device.  This is the linear preconditioner of Sec. 2.2 for Krylov methods. */
+int mgcnn_apply(mgcnn_ctx *ctx, const float *r, float *z);
+
+/* Relative residuals ||f - A u|| / ||f|| per problem (u per opts.u_dtype); relres_host
+ * [batch].  Blocks the host. */
+int mgcnn_residual_norms(mgcnn_ctx *ctx, const float *f, const void *u, double *relres_host);
+
+/* Copy the level-l setup tensor (l = 1..L) into `out` [batch][n_l][n_l][16] float32 device. */
+int mgcnn_get_setup_tensor(mgcnn_ctx *ctx, int level, float *out);
+
+/* Number of levels of the current problem set (0 before setup). */
+int mgcnn_levels(const mgcnn_ctx *ctx);
+
+const char *mgcnn_status_string(int status);
+const char *mgcnn_last_error(const mgcnn_ctx *ctx);
+void mgcnn_destroy(mgcnn_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGCNN_H */

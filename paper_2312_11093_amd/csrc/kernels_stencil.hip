@@ -1,0 +1,420 @@
+// Point-wise and 5-point stencil kernels of the MGCNN solver on CDNA4 (gfx950):
+// setup features, residual + norm partials, stopping test, reChannel convolutions
+// (1 -> 16, 4 -> 16, 16 -> 1) and small utilities.
+//
+// Layouts: scalar fields [B][n][n] (x fastest); channel-last tensors [B][n][n][C].
+#include "mgcnn_internal.h"
+#include "mgcnn_device.h"
+
+namespace mg {
+
+// ------------------------------------------------------------------------------------------
+// Operator helpers (divergence form, harmonic face coefficients, first-order upwind).
+// The discrete operator follows Sec. 2.5: 5-point diffusion (Eq. (8)) written for the
+// divergence form of Eq. (12), upwind convection split by the sign of the velocity
+// (Eqs. (9)-(11)); zero Dirichlet values outside the grid; a boundary face uses the
+// interior node's coefficient.
+// ------------------------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R harm(R p, R q) { return (R(2) * p * q) / (p + q); }
+
+// ------------------------------------------------------------------------------------------
+// features: F = [-A_W, -A_E, -A_S, -A_N] / D, zero where the neighbour is outside.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void features_kernel(const float* __restrict__ a,
+                                                       const float* __restrict__ bvec,
+                                                       float* __restrict__ F, int n, int tiles_x,
+                                                       int tiles_per_prob) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
+  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
+  if (i >= n || j >= n) return;
+  const float* A = a + (size_t)b * n * n;
+  const double ac = A[(size_t)i * n + j];
+  const double aE = (j + 1 < n) ? harm<double>(ac, A[(size_t)i * n + j + 1]) : ac;
+  const double aW = (j > 0) ? harm<double>(ac, A[(size_t)i * n + j - 1]) : ac;
+  const double aN = (i + 1 < n) ? harm<double>(ac, A[(size_t)(i + 1) * n + j]) : ac;
+  const double aS = (i > 0) ? harm<double>(ac, A[(size_t)(i - 1) * n + j]) : ac;
+  const double ih = (double)(n + 1), ih2 = ih * ih;
+  const double bx = bvec[2 * b], by = bvec[2 * b + 1];
+  const double bxp = bx > 0 ? bx : 0, bxm = bx < 0 ? bx : 0;
+  const double byp = by > 0 ? by : 0, bym = by < 0 ? by : 0;
+  const double D = (aE + aW + aN + aS) * ih2 + (fabs(bx) + fabs(by)) * ih;
+  float4 o;
+  o.x = (j > 0) ? (float)((aW * ih2 + bxp * ih) / D) : 0.f;
+  o.y = (j + 1 < n) ? (float)((aE * ih2 - bxm * ih) / D) : 0.f;
+  o.z = (i > 0) ? (float)((aS * ih2 + byp * ih) / D) : 0.f;
+  o.w = (i + 1 < n) ? (float)((aN * ih2 - bym * ih) / D) : 0.f;
+  reinterpret_cast<float4*>(F)[((size_t)b * n + i) * n + j] = o;
+}
+
+void launch_features(const float* a, const float* b, float* F, int n, int B, hipStream_t st) {
+  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  hipLaunchKernelGGL(features_kernel, dim3(tx * ty * B), dim3(256), 0, st, a, b, F, n, tx, tx * ty);
+}
+
+// ------------------------------------------------------------------------------------------
+// residual: r = f - A u ; rt = r / D ; per-workgroup partial sum of r^2 in f64.
+// ------------------------------------------------------------------------------------------
+int residual_tiles(int n) { return ((n + 63) / 64) * ((n + 3) / 4); }
+
+template <typename R, typename UT, bool HAS_U>
+__global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__ a,
+                                                       const float* __restrict__ bvec,
+                                                       const float* __restrict__ f,
+                                                       const UT* __restrict__ u,
+                                                       float* __restrict__ rt,
+                                                       double* __restrict__ partial, int n,
+                                                       int tiles_x, int tiles_per_prob,
+                                                       const int* __restrict__ active) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
+  if (active != nullptr && active[b] == 0) return;
+  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
+  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
+  double r2 = 0.0;
+  if (i < n && j < n) {
+    const size_t base = (size_t)b * n * n;
+    const size_t c = base + (size_t)i * n + j;
+    R r = (R)f[c];
+    if constexpr (HAS_U) {
+      const float* A = a + base;
+      const size_t ij = (size_t)i * n + j;
+      const R ac = (R)A[ij];
+      const R aE = (j + 1 < n) ? harm<R>(ac, (R)A[ij + 1]) : ac;
+      const R aW = (j > 0) ? harm<R>(ac, (R)A[ij - 1]) : ac;
+      const R aN = (i + 1 < n) ? harm<R>(ac, (R)A[ij + n]) : ac;
+      const R aS = (i > 0) ? harm<R>(ac, (R)A[ij - n]) : ac;
+      const UT* U = u + base;
+      const R uc = (R)U[ij];
+      const R uE = (j + 1 < n) ? (R)U[ij + 1] : R(0);
+      const R uW = (j > 0) ? (R)U[ij - 1] : R(0);
+      const R uN = (i + 1 < n) ? (R)U[ij + n] : R(0);
+      const R uS = (i > 0) ? (R)U[ij - n] : R(0);
+      const R ih = (R)(n + 1), ih2 = ih * ih;
+      const R bx = (R)bvec[2 * b], by = (R)bvec[2 * b + 1];
+      const R bxp = bx > R(0) ? bx : R(0), bxm = bx < R(0) ? bx : R(0);
+      const R byp = by > R(0) ? by : R(0), bym = by < R(0) ? by : R(0);
+      const R sa = aE + aW + aN + aS;
+      const R Au = (sa * uc - aE * uE - aW * uW - aN * uN - aS * uS) * ih2 +
+                   (bxp * (uc - uW) + bxm * (uE - uc) + byp * (uc - uS) + bym * (uN - uc)) * ih;
+      const R D = sa * ih2 + (fabs(bx) + fabs(by)) * ih;
+      r = r - Au;
+      if (rt != nullptr) rt[c] = (float)(r / D);
+    } else {
+      (void)a; (void)bvec; (void)u;
+    }
+    r2 = (double)r * (double)r;
+  }
+  r2 = block_sum_256(r2);
+  if (threadIdx.x == 0) partial[(size_t)b * tiles_per_prob + tile] = r2;
+}
+
+void launch_residual(const float* a, const float* b, const float* f, const void* u, bool u_f64,
+                     float* rt, double* partial, int n, int B, const int* active, hipStream_t st) {
+  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  const dim3 grid(tx * ty * B), blk(256);
+  if (u == nullptr) {
+    hipLaunchKernelGGL((residual_kernel<double, double, false>), grid, blk, 0, st, a, b, f,
+                       (const double*)nullptr, rt, partial, n, tx, tx * ty, active);
+  } else if (u_f64) {
+    hipLaunchKernelGGL((residual_kernel<double, double, true>), grid, blk, 0, st, a, b, f,
+                       (const double*)u, rt, partial, n, tx, tx * ty, active);
+  } else {
+    hipLaunchKernelGGL((residual_kernel<float, float, true>), grid, blk, 0, st, a, b, f,
+                       (const float*)u, rt, partial, n, tx, tx * ty, active);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// per-problem reductions and the stopping rule
+// ------------------------------------------------------------------------------------------
+__device__ double sum_partials_block(const double* p, int tiles) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < tiles; k += 256) s += p[k];
+  return block_sum_256(s);
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partial,
+                                                           int tiles, double* __restrict__ out) {
+  const int b = blockIdx.x;
+  const double s = sum_partials_block(partial + (size_t)b * tiles, tiles);
+  if (threadIdx.x == 0) out[b] = s;
+}
+
+void launch_sum_partials(const double* partial, int tiles, double* out, int B, hipStream_t st) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(B), dim3(256), 0, st, partial, tiles, out);
+}
+
+// Stopping rule at iterate k = iters[b] (relative residual rho_k = ||r_k|| / ||f||):
+//   rho_k <= tol          -> OK, stop (iters = k)
+//   k == maxit            -> NOT_CONVERGED, stop
+//   rho_k not finite or > 1e10 -> DIVERGED, stop
+//   otherwise one more V-cycle is applied and iters becomes k + 1.
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ partial,
+                                                       int tiles, const double* __restrict__ nf2,
+                                                       double tol, int maxit, int* active,
+                                                       int* status, int* iters, double* relres) {
+  const int b = blockIdx.x;
+  if (active[b] == 0) return;
+  const double s = sum_partials_block(partial + (size_t)b * tiles, tiles);
+  if (threadIdx.x != 0) return;
+  const double rho = sqrt(s) / sqrt(nf2[b]);
+  const int k = iters[b];
+  relres[b] = rho;
+  if (rho <= tol) {
+    status[b] = 0;
+    active[b] = 0;
+  } else if (k >= maxit) {
+    status[b] = 1;
+    active[b] = 0;
+  } else if (!(rho <= 1e10)) {
+    status[b] = -6;
+    active[b] = 0;
+  } else {
+    iters[b] = k + 1;
+  }
+}
+
+void launch_finalize(const double* partial, int tiles, const double* nf2, double tol, int maxit,
+                     int* active, int* status, int* iters, double* relres, int B, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(B), dim3(256), 0, st, partial, tiles, nf2, tol, maxit,
+                     active, status, iters, relres);
+}
+
+__global__ void solve_init_kernel(const double* __restrict__ nf2, int* active, int* status,
+                                  int* iters, double* relres, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const bool live = nf2[b] > 0.0;
+  active[b] = live ? 1 : 0;
+  status[b] = live ? 1 : 0;
+  iters[b] = 0;
+  relres[b] = live ? 1.0 : 0.0;
+}
+
+void launch_solve_init(const double* nf2, int* active, int* status, int* iters, double* relres,
+                       int B, hipStream_t st) {
+  hipLaunchKernelGGL(solve_init_kernel, dim3((B + 255) / 256), dim3(256), 0, st, nf2, active,
+                     status, iters, relres, B);
+}
+
+// ------------------------------------------------------------------------------------------
+// reChannel convolutions with few channels on one side (VALU direct conv).
+// ------------------------------------------------------------------------------------------
+
+// out[px][o] = sum_{c,p,q} W[o][c][p][q] in[px + (p-1, q-1)][c], CIN in {1, 4}.
+template <int CIN, typename OT>
+__global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ in,
+                                                      const float* __restrict__ W,
+                                                      OT* __restrict__ out, int n, int tiles_x,
+                                                      int tiles_per_prob,
+                                                      const int* __restrict__ active) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
+  if (active != nullptr && active[b] == 0) return;
+  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
+  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
+  if (i >= n || j >= n) return;
+  const float* X = in + (size_t)b * n * n * CIN;
+  float v[9][CIN];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int ii = i + p - 1, jj = j + q - 1;
+      const bool ok = ii >= 0 && ii < n && jj >= 0 && jj < n;
+      if constexpr (CIN == 4) {
+        float4 z = ok ? reinterpret_cast<const float4*>(X)[(size_t)ii * n + jj]
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+        v[p * 3 + q][0] = z.x; v[p * 3 + q][1] = z.y; v[p * 3 + q][2] = z.z; v[p * 3 + q][3] = z.w;
+      } else {
+        v[p * 3 + q][0] = ok ? X[(size_t)ii * n + jj] : 0.f;
+      }
+    }
+  }
+  float acc[C];
+#pragma unroll
+  for (int o = 0; o < C; ++o) {
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < CIN; ++c)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) s = fmaf(W[(o * CIN + c) * 9 + k], v[k][c], s);
+    acc[o] = s;
+  }
+  store16(out + ((size_t)b * n * n + (size_t)i * n + j) * C, acc);
+}
+
+void launch_conv_in(int cin, const float* in, const float* W, void* out, StateType ot, int n,
+                    int B, const int* active, hipStream_t st) {
+  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  const dim3 grid(tx * ty * B), blk(256);
+  if (cin == 1) {
+    if (ot == ST_F32)
+      hipLaunchKernelGGL((conv_in_kernel<1, float>), grid, blk, 0, st, in, W, (float*)out, n, tx,
+                         tx * ty, active);
+    else
+      hipLaunchKernelGGL((conv_in_kernel<1, bf16_t>), grid, blk, 0, st, in, W, (bf16_t*)out, n,
+                         tx, tx * ty, active);
+  } else {
+    if (ot == ST_F32)
+      hipLaunchKernelGGL((conv_in_kernel<4, float>), grid, blk, 0, st, in, W, (float*)out, n, tx,
+                         tx * ty, active);
+    else
+      hipLaunchKernelGGL((conv_in_kernel<4, bf16_t>), grid, blk, 0, st, in, W, (bf16_t*)out, n,
+                         tx, tx * ty, active);
+  }
+}
+
+// u[px] += sum_{c,p,q} W[0][c][p][q] x[px + (p-1, q-1)][c]
+template <typename XT, typename UT>
+__global__ __launch_bounds__(256) void out_update_kernel(const XT* __restrict__ x,
+                                                         const float* __restrict__ W,
+                                                         UT* __restrict__ u, int n, int tiles_x,
+                                                         int tiles_per_prob,
+                                                         const int* __restrict__ active) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
+  if (active != nullptr && active[b] == 0) return;
+  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
+  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
+  if (i >= n || j >= n) return;
+  const XT* X = x + (size_t)b * n * n * C;
+  float acc = 0.f;
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int ii = i + p - 1, jj = j + q - 1;
+      if (ii < 0 || ii >= n || jj < 0 || jj >= n) continue;
+      float v[C];
+      load16(X + ((size_t)ii * n + jj) * C, v);
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc = fmaf(W[c * 9 + p * 3 + q], v[c], acc);
+    }
+  }
+  UT* U = u + (size_t)b * n * n + (size_t)i * n + j;
+  *U = *U + (UT)acc;
+}
+
+void launch_out_update(StateType t, const void* x, const float* Wout, void* u, bool u_f64, int n,
+                       int B, const int* active, hipStream_t st) {
+  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  const dim3 grid(tx * ty * B), blk(256);
+  if (t == ST_F32) {
+    if (u_f64)
+      hipLaunchKernelGGL((out_update_kernel<float, double>), grid, blk, 0, st, (const float*)x,
+                         Wout, (double*)u, n, tx, tx * ty, active);
+    else
+      hipLaunchKernelGGL((out_update_kernel<float, float>), grid, blk, 0, st, (const float*)x,
+                         Wout, (float*)u, n, tx, tx * ty, active);
+  } else {
+    if (u_f64)
+      hipLaunchKernelGGL((out_update_kernel<bf16_t, double>), grid, blk, 0, st, (const bf16_t*)x,
+                         Wout, (double*)u, n, tx, tx * ty, active);
+    else
+      hipLaunchKernelGGL((out_update_kernel<bf16_t, float>), grid, blk, 0, st, (const bf16_t*)x,
+                         Wout, (float*)u, n, tx, tx * ty, active);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// utilities
+// ------------------------------------------------------------------------------------------
+__global__ void f32_to_bf16_kernel(const float* __restrict__ in, bf16_t* __restrict__ out,
+                                   size_t count) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (size_t)gridDim.x * blockDim.x)
+    out[k] = f32_to_bf16_rne(in[k]);
+}
+
+void launch_f32_to_bf16(const float* in, bf16_t* out, size_t count, hipStream_t st) {
+  if (count == 0) return;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(f32_to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, in, out, count);
+}
+
+__global__ void zero_kernel(uint32_t* __restrict__ p, size_t words) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < words;
+       k += (size_t)gridDim.x * blockDim.x)
+    p[k] = 0u;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t words = bytes / 4;
+  if (words == 0) return;
+  size_t blocks = (words + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, words);
+}
+
+__global__ void bf16_to_f32_kernel(const bf16_t* __restrict__ in, float* __restrict__ out,
+                                   size_t count) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (size_t)gridDim.x * blockDim.x)
+    out[k] = bf16_to_f32(in[k]);
+}
+
+void launch_bf16_to_f32(const bf16_t* in, float* out, size_t count, hipStream_t st) {
+  if (count == 0) return;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(bf16_to_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, in, out, count);
+}
+
+// u = 0 for every problem whose right-hand side is zero (its solution is exactly zero).
+template <typename UT>
+__global__ void zero_if_zero_rhs_kernel(UT* __restrict__ u, const double* __restrict__ nf2,
+                                        size_t nn, int B) {
+  const size_t total = nn * (size_t)B;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (size_t)gridDim.x * blockDim.x)
+    if (nf2[k / nn] == 0.0) u[k] = UT(0);
+}
+
+void launch_zero_if_zero_rhs(void* u, bool u_f64, const double* nf2, int n, int B, hipStream_t st) {
+  const size_t nn = (size_t)n * n;
+  size_t blocks = (nn * B + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (u_f64)
+    hipLaunchKernelGGL(zero_if_zero_rhs_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (double*)u, nf2, nn, B);
+  else
+    hipLaunchKernelGGL(zero_if_zero_rhs_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (float*)u, nf2, nn, B);
+}
+
+// rt = r / D with D = diag A(a, b).
+__global__ __launch_bounds__(256) void scale_by_diag_kernel(const float* __restrict__ a,
+                                                            const float* __restrict__ bvec,
+                                                            const float* __restrict__ r,
+                                                            float* __restrict__ rt, int n,
+                                                            int tiles_x, int tiles_per_prob) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
+  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
+  if (i >= n || j >= n) return;
+  const float* A = a + (size_t)b * n * n;
+  const size_t ij = (size_t)i * n + j;
+  const double ac = A[ij];
+  const double aE = (j + 1 < n) ? harm<double>(ac, A[ij + 1]) : ac;
+  const double aW = (j > 0) ? harm<double>(ac, A[ij - 1]) : ac;
+  const double aN = (i + 1 < n) ? harm<double>(ac, A[ij + n]) : ac;
+  const double aS = (i > 0) ? harm<double>(ac, A[ij - n]) : ac;
+  const double ih = (double)(n + 1);
+  const double D = (aE + aW + aN + aS) * ih * ih + (fabs((double)bvec[2 * b]) + fabs((double)bvec[2 * b + 1])) * ih;
+  rt[(size_t)b * n * n + ij] = (float)((double)r[(size_t)b * n * n + ij] / D);
+}
+
+void launch_scale_by_diag(const float* a, const float* b, const float* r, float* rt, int n, int B,
+                          hipStream_t st) {
+  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  hipLaunchKernelGGL(scale_by_diag_kernel, dim3(tx * ty * B), dim3(256), 0, st, a, b, r, rt, n, tx,
+                     tx * ty);
+}
+
+}  // namespace mg

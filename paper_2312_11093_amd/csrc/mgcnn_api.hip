@@ -1,0 +1,447 @@
+// C-ABI of the MGCNN solver library: context, workspace, setup phase, solve loop.
+// The kernels live in kernels_*.hip; this file only validates arguments, owns device
+// memory and sequences launches on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mgcnn.h"
+#include "mgcnn_internal.h"
+
+using namespace mg;
+
+namespace mg {
+
+WeightOffsets weight_offsets() {
+  WeightOffsets w{};
+  size_t o = 0;
+  w.setup_in = o; o += C * 4 * 9;
+  for (int k = 0; k < NUM_SETUP_LAYERS; ++k) {
+    w.res_w[k] = o; o += C * C * 9;
+    w.res_b[k] = o; o += C;
+  }
+  w.setup_restrict = o; o += C * C * 9;
+  w.solve_in = o; o += C * 9;
+  w.smooth_down = o; o += C * C * 9;
+  w.smooth_up = o; o += C * C * 9;
+  w.restrict_ = o; o += C * C * 9;
+  w.prolong = o; o += C * C * 9;
+  w.solve_out = o; o += C * 9;
+  w.total = o;
+  return w;
+}
+
+void launch_bf16_to_f32(const bf16_t* in, float* out, size_t count, hipStream_t st);
+void launch_zero_if_zero_rhs(void* u, bool u_f64, const double* nf2, int n, int B, hipStream_t st);
+void launch_scale_by_diag(const float* a, const float* b, const float* r, float* rt, int n, int B,
+                          hipStream_t st);
+
+}  // namespace mg
+
+struct mgcnn_ctx {
+  mgcnn_opts opts{};
+  hipStream_t stream = nullptr;
+  WeightOffsets off{};
+  float* d_w = nullptr;
+  std::string err;
+
+  // problem set
+  int n = 0, B = 0, L = 0;
+  int alloc_n = 0, alloc_B = 0;
+  std::vector<int> nl;
+  float* d_a = nullptr;
+  float* d_b = nullptr;
+  std::vector<void*> s, xin, xdn;
+  float* d_rt = nullptr;
+  double* d_partial = nullptr;
+  int tiles = 0;
+  double* d_nf2 = nullptr;
+  int* d_active = nullptr;
+  int* d_status = nullptr;
+  int* d_iters = nullptr;
+  double* d_relres = nullptr;
+  bool ready = false;
+
+  size_t state_bytes() const { return opts.state_dtype == MGCNN_BF16 ? 2 : 4; }
+  StateType st() const { return opts.state_dtype == MGCNN_BF16 ? ST_BF16 : ST_F32; }
+  bool u64() const { return opts.u_dtype == MGCNN_U_F64; }
+  const float* W(size_t o) const { return d_w + o; }
+};
+
+namespace {
+
+int fail(mgcnn_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int hip_fail(mgcnn_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, MGCNN_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, call)                                            \
+  do {                                                                \
+    hipError_t e_ = (call);                                           \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);          \
+  } while (0)
+
+#define LAUNCH_CHECK(ctx)                                             \
+  do {                                                                \
+    hipError_t e_ = hipGetLastError();                                \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, "kernel launch"); \
+  } while (0)
+
+bool valid_n(int n) {
+  if (n < 3 || n > 4095) return false;
+  return ((n + 1) & n) == 0;
+}
+
+int level_count(int n) {
+  int L = 0;
+  while ((1 << L) - 1 < n) ++L;
+  return L;
+}
+
+void free_problem(mgcnn_ctx* c) {
+  auto fr = [](void* p) { if (p) (void)hipFree(p); };
+  fr(c->d_a); fr(c->d_b); fr(c->d_rt); fr(c->d_partial); fr(c->d_nf2);
+  fr(c->d_active); fr(c->d_status); fr(c->d_iters); fr(c->d_relres);
+  for (auto p : c->s) fr(p);
+  for (auto p : c->xin) fr(p);
+  for (auto p : c->xdn) fr(p);
+  c->s.clear(); c->xin.clear(); c->xdn.clear();
+  c->d_a = c->d_b = c->d_rt = nullptr;
+  c->d_partial = c->d_nf2 = c->d_relres = nullptr;
+  c->d_active = c->d_status = c->d_iters = nullptr;
+  c->alloc_n = c->alloc_B = 0;
+  c->ready = false;
+}
+
+int alloc(mgcnn_ctx* c, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes < 256 ? 256 : bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, MGCNN_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return MGCNN_OK;
+}
+
+int ensure_problem(mgcnn_ctx* c, int n, int B) {
+  if (c->alloc_n == n && c->alloc_B == B) return MGCNN_OK;
+  free_problem(c);
+  const int L = level_count(n);
+  c->nl.assign(L, 0);
+  int m = n;
+  for (int l = 0; l < L; ++l) { c->nl[l] = m; m = (m - 1) / 2; }
+  const size_t nn = (size_t)n * n * B;
+  int r;
+  if ((r = alloc(c, (void**)&c->d_a, nn * 4))) return r;
+  if ((r = alloc(c, (void**)&c->d_b, (size_t)B * 2 * 4))) return r;
+  if ((r = alloc(c, (void**)&c->d_rt, nn * 4))) return r;
+  c->tiles = residual_tiles(n);
+  if ((r = alloc(c, (void**)&c->d_partial, (size_t)c->tiles * B * 8))) return r;
+  if ((r = alloc(c, (void**)&c->d_nf2, (size_t)B * 8))) return r;
+  if ((r = alloc(c, (void**)&c->d_active, (size_t)B * 4))) return r;
+  if ((r = alloc(c, (void**)&c->d_status, (size_t)B * 4))) return r;
+  if ((r = alloc(c, (void**)&c->d_iters, (size_t)B * 4))) return r;
+  if ((r = alloc(c, (void**)&c->d_relres, (size_t)B * 8))) return r;
+  c->s.assign(L, nullptr); c->xin.assign(L, nullptr); c->xdn.assign(L, nullptr);
+  for (int l = 0; l < L; ++l) {
+    const size_t bytes = (size_t)c->nl[l] * c->nl[l] * B * C * c->state_bytes();
+    if ((r = alloc(c, &c->s[l], bytes))) return r;
+    if ((r = alloc(c, &c->xin[l], bytes))) return r;
+    if ((r = alloc(c, &c->xdn[l], bytes))) return r;
+  }
+  c->alloc_n = n;
+  c->alloc_B = B;
+  c->L = L;
+  return MGCNN_OK;
+}
+
+// One application of the solve network (Alg. 3) to c->d_rt, added into u (u += B(rt)).
+int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active) {
+  const StateType st = c->st();
+  const int L = c->L, B = c->B;
+  hipStream_t s = c->stream;
+  launch_conv_in(1, c->d_rt, c->W(c->off.solve_in), c->xin[0], st, c->n, B, active, s);
+  for (int l = 0; l < L; ++l) {
+    launch_conv16(CM_SMOOTH, st, c->xin[l], c->s[l], c->W(c->off.smooth_down), nullptr, c->xdn[l],
+                  c->nl[l], B, active, s);
+    if (l < L - 1)
+      launch_conv16(CM_RESTRICT, st, c->xdn[l], nullptr, c->W(c->off.restrict_), nullptr,
+                    c->xin[l + 1], c->nl[l], B, active, s);
+  }
+  launch_conv16(CM_SMOOTH, st, c->xdn[L - 1], c->s[L - 1], c->W(c->off.smooth_up), nullptr,
+                c->xin[L - 1], c->nl[L - 1], B, active, s);
+  for (int l = L - 2; l >= 0; --l) {
+    launch_prolong_add(st, c->xin[l + 1], c->W(c->off.prolong), c->xdn[l], c->nl[l + 1], B, active,
+                       s);
+    launch_conv16(CM_SMOOTH, st, c->xdn[l], c->s[l], c->W(c->off.smooth_up), nullptr, c->xin[l],
+                  c->nl[l], B, active, s);
+  }
+  launch_out_update(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, active, s);
+  LAUNCH_CHECK(c);
+  return MGCNN_OK;
+}
+
+// residual of the current iterate, stopping test, then one V-cycle for live problems
+int solve_step(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit) {
+  launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->B, c->d_active,
+                  c->stream);
+  launch_finalize(c->d_partial, c->tiles, c->d_nf2, tol, maxit, c->d_active, c->d_status,
+                  c->d_iters, c->d_relres, c->B, c->stream);
+  return vcycle(c, u, c->u64(), c->d_active);
+}
+
+}  // namespace
+
+extern "C" {
+
+void mgcnn_default_opts(mgcnn_opts* o) {
+  if (!o) return;
+  o->channels = 16;
+  o->state_dtype = MGCNN_F32;
+  o->u_dtype = MGCNN_U_F64;
+  o->use_graph = 0;
+  o->check_every = 4;
+}
+
+size_t mgcnn_num_weights(int channels) {
+  if (channels <= 0) return 0;
+  return (size_t)81 * channels * channels + (size_t)58 * channels;
+}
+
+int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_host,
+                 void* hip_stream) {
+  if (!out) return MGCNN_E_ARG;
+  *out = nullptr;
+  mgcnn_opts o;
+  if (opts) o = *opts; else mgcnn_default_opts(&o);
+  if (o.channels != C) return MGCNN_E_ARG;
+  if (o.state_dtype != MGCNN_F32 && o.state_dtype != MGCNN_BF16) return MGCNN_E_ARG;
+  if (o.u_dtype != MGCNN_U_F32 && o.u_dtype != MGCNN_U_F64) return MGCNN_E_ARG;
+  if (o.check_every < 1) return MGCNN_E_ARG;
+  mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
+  if (!c) return MGCNN_E_NOMEM;
+  c->opts = o;
+  c->stream = (hipStream_t)hip_stream;
+  c->off = weight_offsets();
+  if (alloc(c, (void**)&c->d_w, c->off.total * 4)) { delete c; return MGCNN_E_NOMEM; }
+  int r = mgcnn_set_weights(c, weights_host);
+  if (r) { (void)hipFree(c->d_w); delete c; return r; }
+  *out = c;
+  return MGCNN_OK;
+}
+
+int mgcnn_set_weights(mgcnn_ctx* c, const float* w) {
+  if (!c) return MGCNN_E_ARG;
+  if (w == nullptr) {
+    launch_zero(c->d_w, c->off.total * 4, c->stream);
+    LAUNCH_CHECK(c);
+    return MGCNN_OK;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->d_w, w, c->off.total * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return MGCNN_OK;
+}
+
+int mgcnn_set_stream(mgcnn_ctx* c, void* s) {
+  if (!c) return MGCNN_E_ARG;
+  c->stream = (hipStream_t)s;
+  return MGCNN_OK;
+}
+
+int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B) {
+  if (!c) return MGCNN_E_ARG;
+  if (!a || !b_host) return fail(c, MGCNN_E_ARG, "setup: null a or b");
+  if (!valid_n(n)) return fail(c, MGCNN_E_SIZE, "setup: n must be 2^L - 1 in [3, 4095]");
+  if (B < 1) return fail(c, MGCNN_E_SIZE, "setup: batch must be >= 1");
+  for (int i = 0; i < 2 * B; ++i)
+    if (!std::isfinite(b_host[i])) return fail(c, MGCNN_E_ARG, "setup: non-finite velocity");
+  c->ready = false;
+  int r = ensure_problem(c, n, B);
+  if (r) return r;
+  c->n = n;
+  c->B = B;
+  hipStream_t s = c->stream;
+  const size_t nn = (size_t)n * n * B;
+  HIP_TRY(c, hipMemcpyAsync(c->d_a, a, nn * 4, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(c->d_b, b_host, (size_t)B * 2 * 4, hipMemcpyHostToDevice, s));
+  // setup temporaries (f32): features, coefficient tensor (current, next), two ping-pong
+  float *F = nullptr, *cc = nullptr, *cn = nullptr, *za = nullptr, *zb = nullptr;
+  const size_t t16 = nn * C * 4;
+  HIP_TRY(c, hipMallocAsync((void**)&F, nn * 16, s));
+  HIP_TRY(c, hipMallocAsync((void**)&cc, t16, s));
+  HIP_TRY(c, hipMallocAsync((void**)&cn, t16, s));
+  HIP_TRY(c, hipMallocAsync((void**)&za, t16, s));
+  HIP_TRY(c, hipMallocAsync((void**)&zb, t16, s));
+  launch_features(c->d_a, c->d_b, F, n, B, s);
+  launch_conv_in(4, F, c->W(c->off.setup_in), cc, ST_F32, n, B, nullptr, s);
+  for (int l = 0; l < c->L; ++l) {
+    const int m = c->nl[l];
+    const size_t cnt = (size_t)m * m * B * C;
+    const float* zin = cc;
+    float* ping[2] = {za, zb};
+    for (int k = 0; k < NUM_SETUP_LAYERS; ++k) {
+      float* zout = (k == NUM_SETUP_LAYERS - 1 && c->st() == ST_F32) ? (float*)c->s[l] : ping[k & 1];
+      launch_conv16(CM_TANH, ST_F32, zin, nullptr, c->W(c->off.res_w[k]), c->W(c->off.res_b[k]), zout,
+                    m, B, nullptr, s);
+      zin = zout;
+    }
+    if (c->st() == ST_BF16) launch_f32_to_bf16(zin, (bf16_t*)c->s[l], cnt, s);
+    if (l < c->L - 1) {
+      launch_conv16(CM_RESTRICT, ST_F32, cc, nullptr, c->W(c->off.setup_restrict), nullptr, cn, m, B,
+                    nullptr, s);
+      float* t = cc; cc = cn; cn = t;
+    }
+  }
+  LAUNCH_CHECK(c);
+  HIP_TRY(c, hipFreeAsync(F, s));
+  HIP_TRY(c, hipFreeAsync(cc, s));
+  HIP_TRY(c, hipFreeAsync(cn, s));
+  HIP_TRY(c, hipFreeAsync(za, s));
+  HIP_TRY(c, hipFreeAsync(zb, s));
+  c->ready = true;
+  return MGCNN_OK;
+}
+
+int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int* iters_host,
+                double* relres_host, int* status_host) {
+  if (!c) return MGCNN_E_ARG;
+  if (!c->ready) return fail(c, MGCNN_E_STATE, "solve: call mgcnn_setup first");
+  if (!f || !u) return fail(c, MGCNN_E_ARG, "solve: null f or u");
+  if (!(tol > 0.0) || maxit < 0) return fail(c, MGCNN_E_ARG, "solve: need tol > 0 and maxit >= 0");
+  hipStream_t s = c->stream;
+  const int B = c->B;
+  // ||f||^2 per problem
+  launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, c->n, B, nullptr, s);
+  launch_sum_partials(c->d_partial, c->tiles, c->d_nf2, B, s);
+  launch_solve_init(c->d_nf2, c->d_active, c->d_status, c->d_iters, c->d_relres, B, s);
+  launch_zero_if_zero_rhs(u, c->u64(), c->d_nf2, c->n, B, s);
+  LAUNCH_CHECK(c);
+  std::vector<int> act(B);
+  int steps = 0;
+  const int max_steps = maxit + 1;
+  while (steps < max_steps) {
+    const int chunk = std::min(c->opts.check_every, max_steps - steps);
+    for (int k = 0; k < chunk; ++k) {
+      int r = solve_step(c, f, u, tol, maxit);
+      if (r) return r;
+    }
+    steps += chunk;
+    HIP_TRY(c, hipMemcpyAsync(act.data(), c->d_active, (size_t)B * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    bool any = false;
+    for (int b = 0; b < B; ++b) any |= act[b] != 0;
+    if (!any) break;
+  }
+  std::vector<int> st(B), it(B);
+  std::vector<double> rr(B);
+  HIP_TRY(c, hipMemcpyAsync(st.data(), c->d_status, (size_t)B * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(it.data(), c->d_iters, (size_t)B * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(rr.data(), c->d_relres, (size_t)B * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  bool diverged = false, notconv = false;
+  for (int b = 0; b < B; ++b) {
+    if (iters_host) iters_host[b] = it[b];
+    if (relres_host) relres_host[b] = rr[b];
+    if (status_host) status_host[b] = st[b];
+    diverged |= st[b] == MGCNN_E_DIVERGED;
+    notconv |= st[b] == MGCNN_NOT_CONVERGED;
+  }
+  if (diverged) return fail(c, MGCNN_E_DIVERGED, "solve: a problem diverged");
+  if (notconv) return MGCNN_NOT_CONVERGED;
+  return MGCNN_OK;
+}
+
+int mgcnn_forward(mgcnn_ctx* c, const float* f, void* u, int K, int record) {
+  if (!c) return MGCNN_E_ARG;
+  if (!c->ready) return fail(c, MGCNN_E_STATE, "forward: call mgcnn_setup first");
+  if (!f || !u || K < 0) return fail(c, MGCNN_E_ARG, "forward: bad argument");
+  if (record) return fail(c, MGCNN_E_ARG, "forward: recording is not available in this build");
+  for (int k = 0; k < K; ++k) {
+    launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->B, nullptr,
+                    c->stream);
+    int r = vcycle(c, u, c->u64(), nullptr);
+    if (r) return r;
+  }
+  LAUNCH_CHECK(c);
+  return MGCNN_OK;
+}
+
+int mgcnn_apply(mgcnn_ctx* c, const float* r, float* z) {
+  if (!c) return MGCNN_E_ARG;
+  if (!c->ready) return fail(c, MGCNN_E_STATE, "apply: call mgcnn_setup first");
+  if (!r || !z) return fail(c, MGCNN_E_ARG, "apply: null pointer");
+  launch_scale_by_diag(c->d_a, c->d_b, r, c->d_rt, c->n, c->B, c->stream);
+  launch_zero(z, (size_t)c->n * c->n * c->B * 4, c->stream);
+  return vcycle(c, z, false, nullptr);
+}
+
+int mgcnn_residual_norms(mgcnn_ctx* c, const float* f, const void* u, double* relres_host) {
+  if (!c) return MGCNN_E_ARG;
+  if (!c->ready) return fail(c, MGCNN_E_STATE, "residual: call mgcnn_setup first");
+  if (!f || !u || !relres_host) return fail(c, MGCNN_E_ARG, "residual: null pointer");
+  hipStream_t s = c->stream;
+  const int B = c->B;
+  launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, c->n, B, nullptr, s);
+  launch_sum_partials(c->d_partial, c->tiles, c->d_nf2, B, s);
+  launch_residual(c->d_a, c->d_b, f, u, c->u64(), nullptr, c->d_partial, c->n, B, nullptr, s);
+  launch_sum_partials(c->d_partial, c->tiles, c->d_relres, B, s);
+  LAUNCH_CHECK(c);
+  std::vector<double> nf(B), rr(B);
+  HIP_TRY(c, hipMemcpyAsync(nf.data(), c->d_nf2, (size_t)B * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(rr.data(), c->d_relres, (size_t)B * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  for (int b = 0; b < B; ++b) relres_host[b] = nf[b] > 0 ? std::sqrt(rr[b]) / std::sqrt(nf[b]) : 0.0;
+  return MGCNN_OK;
+}
+
+int mgcnn_get_setup_tensor(mgcnn_ctx* c, int level, float* out) {
+  if (!c) return MGCNN_E_ARG;
+  if (!c->ready) return fail(c, MGCNN_E_STATE, "get_setup_tensor: no setup");
+  if (level < 1 || level > c->L || !out) return fail(c, MGCNN_E_ARG, "get_setup_tensor: bad level");
+  const int m = c->nl[level - 1];
+  const size_t cnt = (size_t)m * m * c->B * C;
+  if (c->st() == ST_F32)
+    HIP_TRY(c, hipMemcpyAsync(out, c->s[level - 1], cnt * 4, hipMemcpyDeviceToDevice, c->stream));
+  else
+    launch_bf16_to_f32((const bf16_t*)c->s[level - 1], out, cnt, c->stream);
+  LAUNCH_CHECK(c);
+  return MGCNN_OK;
+}
+
+int mgcnn_levels(const mgcnn_ctx* c) { return (c && c->ready) ? c->L : 0; }
+
+const char* mgcnn_status_string(int s) {
+  switch (s) {
+    case MGCNN_OK: return "ok";
+    case MGCNN_NOT_CONVERGED: return "not converged (maxit reached)";
+    case MGCNN_E_ARG: return "invalid argument";
+    case MGCNN_E_SIZE: return "invalid size";
+    case MGCNN_E_STATE: return "invalid call order";
+    case MGCNN_E_NOMEM: return "out of device memory";
+    case MGCNN_E_HIP: return "HIP runtime error";
+    case MGCNN_E_DIVERGED: return "diverged";
+    case MGCNN_E_NORECORD: return "no recorded forward";
+    default: return "unknown status";
+  }
+}
+
+const char* mgcnn_last_error(const mgcnn_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void mgcnn_destroy(mgcnn_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+  free_problem(c);
+  if (c->d_w) (void)hipFree(c->d_w);
+  delete c;
+}
+
+}  // extern "C"

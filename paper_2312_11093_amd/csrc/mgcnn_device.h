@@ -1,0 +1,84 @@
+// Device-side helpers shared by the MGCNN kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mg {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup w runs on XCD w % 8).
+// Remap so that every XCD receives one contiguous range of logical tiles: neighbouring
+// tiles, which share halo rows, then hit the same L2.
+__device__ __forceinline__ int xcd_remap(int wg, int nwg) {
+  const int q = nwg >> 3, r = nwg & 7;
+  const int xcd = wg & 7, local = wg >> 3;
+  return (xcd < r) ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+// Sum over a 256-thread workgroup (4 waves); deterministic order; valid in thread 0.
+__device__ __forceinline__ double block_sum_256(double v) {
+  __shared__ double red[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return s;
+}
+
+// bf16 (round to nearest even; NaN stays NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu) != 0u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// 16 contiguous channels of one pixel.
+__device__ __forceinline__ void load16(const float* p, float* v) {
+  const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float4 z = q[k];
+    v[4 * k] = z.x; v[4 * k + 1] = z.y; v[4 * k + 2] = z.z; v[4 * k + 3] = z.w;
+  }
+}
+__device__ __forceinline__ void load16(const uint16_t* p, float* v) {
+  const uint4* q = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    uint4 z = q[k];
+    const uint32_t w[4] = {z.x, z.y, z.z, z.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[8 * k + 2 * e] = __uint_as_float(w[e] << 16);
+      v[8 * k + 2 * e + 1] = __uint_as_float(w[e] & 0xffff0000u);
+    }
+  }
+}
+__device__ __forceinline__ void store16(float* p, const float* v) {
+  float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+}
+__device__ __forceinline__ void store16(uint16_t* p, const float* v) {
+  uint4* q = reinterpret_cast<uint4*>(p);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    uint32_t w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      w[e] = (uint32_t)f32_to_bf16_rne(v[8 * k + 2 * e]) |
+             ((uint32_t)f32_to_bf16_rne(v[8 * k + 2 * e + 1]) << 16);
+    q[k] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+}  // namespace mg

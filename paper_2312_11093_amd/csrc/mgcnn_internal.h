@@ -1,0 +1,79 @@
+// Internal declarations shared by the MGCNN HIP kernels and the C-ABI layer.
+// Not part of the public interface (see include/mgcnn.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace mg {
+
+constexpr int C = 16;                 // hidden channels of every state / setup tensor
+constexpr int NUM_SETUP_LAYERS = 4;   // tanh ResNet layers of the setup network
+
+// State storage type of the solve network (x, s).
+enum StateType : int { ST_F32 = 0, ST_BF16 = 1 };
+
+// Offsets (in floats) of every parameter tensor inside the flat weight vector.
+struct WeightOffsets {
+  size_t setup_in, res_w[NUM_SETUP_LAYERS], res_b[NUM_SETUP_LAYERS], setup_restrict;
+  size_t solve_in, smooth_down, smooth_up, restrict_, prolong, solve_out, total;
+};
+WeightOffsets weight_offsets();
+
+// bf16 storage: raw 16-bit pattern.
+typedef uint16_t bf16_t;
+
+// ---- launchers (all asynchronous on `st`) ------------------------------------------------
+
+// Setup: stencil features F [B][n][n][4] (f32) from a [B][n][n] and b [B][2].
+void launch_features(const float* a, const float* b, float* F, int n, int B, hipStream_t st);
+
+// Same-size 3x3 conv from CIN (1 or 4) channels to 16, zero padded.
+//   in  [B][n][n][CIN] f32, W [16][CIN][3][3] f32, out [B][n][n][16] (f32 or bf16).
+void launch_conv_in(int cin, const float* in, const float* W, void* out, StateType ot,
+                    int n, int B, const int* active, hipStream_t st);
+
+// C->C conv on MFMA.  mode: SMOOTH  y = x + W*(s.x)        (same size, s given)
+//                           TANH    y = x + tanh(W*x + bias) (same size, f32 only)
+//                           RESTRICT y = W *_{stride 2} x    (m -> (m-1)/2)
+enum ConvMode : int { CM_SMOOTH = 0, CM_TANH = 1, CM_RESTRICT = 2 };
+void launch_conv16(ConvMode mode, StateType t, const void* x, const void* s, const float* W,
+                   const float* bias, void* y, int m, int B, const int* active, hipStream_t st);
+
+// y_fine += convT_{stride 2}(W_T, x_coarse), fine side m = 2 mc + 1, in place on y_fine.
+void launch_prolong_add(StateType t, const void* xc, const float* WT, void* yf, int mc, int B,
+                        const int* active, hipStream_t st);
+
+// u += W_out * x (16 -> 1 same-size conv), u f32 or f64.
+void launch_out_update(StateType t, const void* x, const float* Wout, void* u, bool u_f64,
+                       int n, int B, const int* active, hipStream_t st);
+
+// r = f - A(a,b) u ; rt = r / D (f32) ; partial[b][tile] = sum r^2 (f64).
+// u == nullptr means u = 0.  mode64: u is f64 and the arithmetic is f64; otherwise u is f32 and
+// the stencil arithmetic is f32 (the partial sums stay f64).
+int residual_tiles(int n);
+void launch_residual(const float* a, const float* b, const float* f, const void* u, bool u_f64,
+                     float* rt, double* partial, int n, int B, const int* active, hipStream_t st);
+
+// Per-problem stop test (one workgroup per problem).  On entry iters[b] = k of the current
+// iterate.  Computes rho_k = sqrt(sum partial)/sqrt(nf2).  If nf2 is zero, rho = 0.
+// Sets active/status/iters/relres following the solver's stopping rule.
+void launch_finalize(const double* partial, int tiles, const double* nf2, double tol, int maxit,
+                     int* active, int* status, int* iters, double* relres, int B, hipStream_t st);
+
+// nf2[b] = sum of partials (the squared norm of f), deterministic order.
+void launch_sum_partials(const double* partial, int tiles, double* out, int B, hipStream_t st);
+
+// Convert f32 -> bf16 (round to nearest even), count elements.
+void launch_f32_to_bf16(const float* in, bf16_t* out, size_t count, hipStream_t st);
+
+// Zero fill (kernel, graph-capture safe).
+void launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// Solve init: active[b] = (nf2[b] > 0), status = NOT_CONVERGED, iters = 0, relres = 0;
+// problems with a zero right-hand side get u = 0 (zeroed by the caller), status OK.
+void launch_solve_init(const double* nf2, int* active, int* status, int* iters, double* relres,
+                       int B, hipStream_t st);
+
+}  // namespace mg

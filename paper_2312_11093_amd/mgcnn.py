@@ -1,0 +1,200 @@
+"""ctypes binding of libmgcnn.so (argument marshalling only).
+
+PyTorch supplies device memory and the HIP stream; every step of the solver runs in
+the library's HIP kernels.  Importing this module without a built library raises.
+
+Low-level: ``lib()`` returns the ctypes handle with the C signatures of
+``include/mgcnn.h`` declared (``mgcnn_create``, ``mgcnn_setup``, ``mgcnn_solve``, ...).
+High-level: ``Solver`` wraps one context; its methods carry the C names without the
+``mgcnn_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmgcnn.so")
+
+OK, NOT_CONVERGED = 0, 1
+E_ARG, E_SIZE, E_STATE, E_NOMEM, E_HIP, E_DIVERGED, E_NORECORD = -1, -2, -3, -4, -5, -6, -7
+F32, BF16 = 0, 1
+U_F32, U_F64 = 0, 1
+
+_lib = None
+
+
+class mgcnn_opts(ctypes.Structure):
+    _fields_ = [("channels", ctypes.c_int), ("state_dtype", ctypes.c_int), ("u_dtype", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "mgcnn_default_opts": (None, [ctypes.POINTER(mgcnn_opts)]),
+    "mgcnn_num_weights": (ctypes.c_size_t, [ctypes.c_int]),
+    "mgcnn_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(mgcnn_opts),
+                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "mgcnn_set_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mgcnn_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mgcnn_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_int]),
+    "mgcnn_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mgcnn_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.c_int]),
+    "mgcnn_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mgcnn_residual_norms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
+    "mgcnn_get_setup_tensor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "mgcnn_levels": (ctypes.c_int, [ctypes.c_void_p]),
+    "mgcnn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "mgcnn_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "mgcnn_destroy": (None, [ctypes.c_void_p]),
+}
+
+
+def lib():
+    """Load libmgcnn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_11093_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MGCNNError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"mgcnn status {status}: {msg}")
+        self.status = status
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _check_dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Solver:
+    """One library context (weights + workspace for one problem set)."""
+
+    def __init__(self, weights, state: str = "f32", u: str = "f64", use_graph: bool = False,
+                 check_every: int = 4, stream=None):
+        import torch
+        self._L = lib()
+        o = mgcnn_opts()
+        self._L.mgcnn_default_opts(ctypes.byref(o))
+        o.channels = 16
+        o.state_dtype = {"f32": F32, "bf16": BF16}[state]
+        o.u_dtype = {"f32": U_F32, "f64": U_F64}[u]
+        o.use_graph = int(bool(use_graph))
+        o.check_every = int(check_every)
+        self.opts = o
+        self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        if w.size != self._L.mgcnn_num_weights(16):
+            raise ValueError(f"expected {self._L.mgcnn_num_weights(16)} weights, got {w.size}")
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        st = self._L.mgcnn_create(ctypes.byref(h), ctypes.byref(o), w.ctypes.data, ctypes.c_void_p(self._stream.cuda_stream))
+        if st != OK:
+            raise MGCNNError(st, self._L.mgcnn_status_string(st).decode())
+        self._h = h
+        self.n = 0
+        self.batch = 0
+
+    # -- helpers ---------------------------------------------------------------------------
+    def _raise(self, st):
+        if st not in (OK, NOT_CONVERGED):
+            raise MGCNNError(st, self._L.mgcnn_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mgcnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- API (names of the C entry points without the prefix) --------------------------------
+    def set_weights(self, weights):
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        return self._raise(self._L.mgcnn_set_weights(self._h, w.ctypes.data))
+
+    def setup(self, a, b):
+        """a: (B, n, n) float32 device tensor; b: (B, 2) host array."""
+        import torch
+        _check_dev(a, torch.float32, "a")
+        B, n, n2 = a.shape
+        bh = np.ascontiguousarray(np.asarray(b, dtype=np.float32).reshape(B, 2))
+        self._raise(self._L.mgcnn_setup(self._h, _ptr(a), bh.ctypes.data, n, B))
+        self.n, self.batch = n, B
+
+    def solve(self, f, u, tol: float, maxit: int):
+        """Returns (status, iters[B], relres[B], per-problem status[B]); u updated in place."""
+        import torch
+        _check_dev(f, torch.float32, "f")
+        _check_dev(u, self.u_dtype, "u")
+        it = np.zeros(self.batch, np.int32)
+        rr = np.zeros(self.batch, np.float64)
+        ps = np.zeros(self.batch, np.int32)
+        st = self._L.mgcnn_solve(self._h, _ptr(f), _ptr(u), float(tol), int(maxit), it.ctypes.data,
+                                 rr.ctypes.data, ps.ctypes.data)
+        if st not in (OK, NOT_CONVERGED, E_DIVERGED):
+            self._raise(st)
+        return st, it, rr, ps
+
+    def forward(self, f, u, K: int, record: bool = False):
+        import torch
+        _check_dev(f, torch.float32, "f")
+        _check_dev(u, self.u_dtype, "u")
+        return self._raise(self._L.mgcnn_forward(self._h, _ptr(f), _ptr(u), int(K), int(record)))
+
+    def apply(self, r, z=None):
+        import torch
+        _check_dev(r, torch.float32, "r")
+        if z is None:
+            z = torch.empty_like(r)
+        self._raise(self._L.mgcnn_apply(self._h, _ptr(r), _ptr(z)))
+        return z
+
+    def residual_norms(self, f, u):
+        import torch
+        _check_dev(f, torch.float32, "f")
+        _check_dev(u, self.u_dtype, "u")
+        rr = np.zeros(self.batch, np.float64)
+        self._raise(self._L.mgcnn_residual_norms(self._h, _ptr(f), _ptr(u), rr.ctypes.data))
+        return rr
+
+    def get_setup_tensor(self, level: int):
+        import torch
+        m = self.n
+        for _ in range(level - 1):
+            m = (m - 1) // 2
+        out = torch.empty((self.batch, m, m, 16), dtype=torch.float32, device="cuda")
+        self._raise(self._L.mgcnn_get_setup_tensor(self._h, int(level), _ptr(out)))
+        return out
+
+    @property
+    def levels(self) -> int:
+        return self._L.mgcnn_levels(self._h)

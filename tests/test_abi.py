@@ -1,0 +1,63 @@
+"""The C-ABI library builds for gfx950, loads on the host and exports every entry point
+declared in include/mgcnn.h (no compute calls: those need a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgcnn.h")
+LIB = os.path.join(ROOT, "paper_2312_11093_amd", "libmgcnn.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mgcnn_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2312_11093_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("mgcnn_create", "mgcnn_setup", "mgcnn_solve", "mgcnn_forward", "mgcnn_apply",
+                 "mgcnn_destroy", "mgcnn_num_weights"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_every_export():
+    from paper_2312_11093_amd import mgcnn
+    assert set(declared()) <= set(mgcnn.EXPORTS), set(declared()) - set(mgcnn.EXPORTS)
+
+
+def test_host_only_calls(lib):
+    lib.mgcnn_num_weights.restype = ctypes.c_size_t
+    assert lib.mgcnn_num_weights(16) == 21664
+    assert lib.mgcnn_num_weights(8) == 81 * 64 + 58 * 8
+    lib.mgcnn_status_string.restype = ctypes.c_char_p
+    assert lib.mgcnn_status_string(-6) == b"diverged"
+    assert lib.mgcnn_status_string(0) == b"ok"
+    # argument checking before any device work
+    assert lib.mgcnn_create(None, None, None, None) == -1
+
+
+def test_no_oracle_in_product_path():
+    """The product package never imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_2312_11093_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in src and "from oracle" not in src, fn

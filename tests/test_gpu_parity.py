@@ -1,0 +1,242 @@
+"""GPU parity: the HIP library (through the C-ABI) against the FP64 oracle on the same
+seeded float32 inputs.  Tolerance for the f32 state path: relative error <= 1e-5 on the
+solution at a fixed iteration count; bf16 state: reported, bounded loosely; converged
+solves: oracle-recomputed relative residual <= tol."""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import network as onet
+from oracle import operator as oop
+from oracle import solve as osv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # CPU container: the gpu-marked tests cannot run here
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_11093_amd import Solver  # noqa: E402  (raises if libmgcnn.so is missing)
+from paper_2312_11093_amd import mgcnn as M  # noqa: E402
+
+F32_TOL = 1e-5
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(x, y):
+    return float(np.linalg.norm(np.asarray(x, np.float64) - y) / max(np.linalg.norm(y), 1e-300))
+
+
+def dev(x, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype)
+
+
+def jacobi_weights(omega=1.0):
+    P = {k: np.zeros_like(v) for k, v in onet.unpack_weights(np.zeros(datagen.num_weights(16)), 16).items()}
+    P["W_in"][0, 0, 1, 1] = 1.0
+    P["W_out"][0, 0, 1, 1] = omega
+    return onet.pack_weights(P, 16).astype(np.float32)
+
+
+def batch(workload, n, B, seed=0):
+    return datagen.make_batch(workload, n, B, seed=seed)
+
+
+@pytest.mark.parametrize("n,B", [(31, 2), (127, 2)])
+def test_setup_tensors(n, B):
+    say("setup tensors", n, B)
+    a, b, f = batch("mixture127", n, B, seed=1)
+    w = datagen.xavier_weights(16, 0)
+    S = Solver(w, state="f32")
+    S.setup(dev(a), b)
+    L = S.levels
+    assert L == datagen.levels_for(n)
+    for p in range(B):
+        ref = osv.Solver(w, a[p], b[p])
+        for l in range(1, L + 1):
+            got = S.get_setup_tensor(l)[p].cpu().numpy().astype(np.float64)   # (m, m, 16)
+            exp = np.transpose(ref.s[l - 1], (1, 2, 0))
+            assert rel(got, exp) <= F32_TOL, (p, l, rel(got, exp))
+    S.close()
+
+
+@pytest.mark.parametrize("udt", ["f64", "f32"])
+def test_residual_norms(udt):
+    say("residual norms", udt)
+    n, B = 63, 3
+    a, b, f = batch("blocks1023", n, B, seed=2)
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal((B, n, n)) * 1e-3
+    S = Solver(datagen.xavier_weights(16, 0), u=udt)
+    S.setup(dev(a), b)
+    got = S.residual_norms(dev(f), dev(u, S.u_dtype))
+    for p in range(B):
+        uu = u[p] if udt == "f64" else u[p].astype(np.float32)
+        exp = osv.relres(a[p], b[p], f[p], uu)
+        tol = 1e-12 if udt == "f64" else 1e-5
+        assert abs(got[p] - exp) <= tol * exp, (p, got[p], exp)
+    S.close()
+
+
+@pytest.mark.parametrize("n,B", [(3, 1), (15, 2), (31, 1), (63, 2), (127, 2)])
+def test_apply_network(n, B):
+    """One application of the solve network z = B(r / D)."""
+    say("apply", n, B)
+    a, b, f = batch("mixture127", n, B, seed=3)
+    w = datagen.xavier_weights(16, 1)
+    rng = np.random.default_rng(n)
+    r = rng.standard_normal((B, n, n)).astype(np.float32)
+    S = Solver(w, state="f32")
+    S.setup(dev(a), b)
+    z = S.apply(dev(r)).cpu().numpy()
+    for p in range(B):
+        ref = osv.Solver(w, a[p], b[p])
+        exp = ref.correction(r[p].astype(np.float64))
+        assert rel(z[p], exp) <= F32_TOL, (p, rel(z[p], exp))
+    S.close()
+
+
+@pytest.mark.parametrize("K", [1, 2, 8])
+def test_forward_grf31(K):
+    """31x31 lognormal GRF, b = (1,1), f ~ U(-1,1), Xavier weights: K fixed iterations."""
+    say("forward grf31 K", K)
+    a, b, f = batch("grf31", 31, 1)
+    w = datagen.xavier_weights(16, 0)
+    for udt in ("f32", "f64"):
+        S = Solver(w, state="f32", u=udt)
+        S.setup(dev(a), b)
+        u = torch.zeros((1, 31, 31), dtype=S.u_dtype, device="cuda")
+        S.forward(dev(f), u, K)
+        exp = osv.Solver(w, a[0], b[0]).forward(f[0], K)
+        err = rel(u[0].cpu().numpy(), exp)
+        say("  u", udt, "rel err", err)
+        assert err <= F32_TOL
+        S.close()
+
+
+def test_forward_batched_ragged():
+    """Batch of 3 at 127 (two 64-wide column tiles, ragged last one): per-problem results equal
+    the unbatched oracle."""
+    say("forward batched 127x3")
+    n, B, K = 127, 3, 2
+    a, b, f = batch("mixture127", n, B, seed=4)
+    w = datagen.xavier_weights(16, 2)
+    S = Solver(w, state="f32", u="f64")
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    S.forward(dev(f), u, K)
+    got = u.cpu().numpy()
+    for p in range(B):
+        exp = osv.Solver(w, a[p], b[p]).forward(f[p], K)
+        assert rel(got[p], exp) <= F32_TOL, (p, rel(got[p], exp))
+    S.close()
+
+
+def test_forward_bf16_state_reported():
+    say("forward bf16 state")
+    n, B, K = 63, 2, 1
+    a, b, f = batch("mixture127", n, B, seed=5)
+    w = datagen.xavier_weights(16, 3)
+    S = Solver(w, state="bf16", u="f64")
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    S.forward(dev(f), u, K)
+    got = u.cpu().numpy()
+    errs = [rel(got[p], osv.Solver(w, a[p], b[p]).forward(f[p], K)) for p in range(B)]
+    say("  bf16 rel err", errs)
+    assert max(errs) < 5e-2
+    S.close()
+
+
+def test_solve_jacobi_matches_oracle_iterations():
+    """Weighted-Jacobi weights: a convergent stationary iteration; iteration count and final
+    residual match the oracle, and the returned u has oracle residual <= tol."""
+    say("solve jacobi")
+    n, B = 7, 2
+    a, b, f = batch("grf31", n, B, seed=6)
+    w = jacobi_weights(1.0)
+    tol = 1e-8
+    for state in ("f32", "bf16"):
+        S = Solver(w, state=state, u="f64", check_every=3)
+        S.setup(dev(a), b)
+        u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+        st, it, rr, ps = S.solve(dev(f), u, tol, 2000)
+        assert st == M.OK and (ps == 0).all()
+        for p in range(B):
+            _, ost, oit, orho, _ = osv.Solver(w, a[p], b[p]).solve(f[p], tol, 2000)
+            assert ost == osv.OK
+            if state == "f32":
+                assert abs(int(it[p]) - oit) <= 1, (p, it[p], oit)
+            assert osv.relres(a[p], b[p], f[p], u[p].cpu().numpy()) <= tol
+        S.close()
+
+
+def test_solve_status_codes():
+    say("solve status codes")
+    n, B = 15, 3
+    a, b, f = batch("grf31", n, B, seed=7)
+    f[1] = 0.0                       # zero right-hand side -> u = 0, iters 0, OK
+    w = jacobi_weights(1.0)
+    S = Solver(w, u="f64", check_every=2)
+    S.setup(dev(a), b)
+    u = torch.ones((B, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(f), u, 1e-8, 0)          # maxit = 0
+    assert st == M.NOT_CONVERGED
+    assert list(ps) == [1, 0, 1] and list(it) == [0, 0, 0]
+    assert (u[1] == 0).all()
+    # exploding weights -> DIVERGED, iterate count below maxit
+    S.set_weights(jacobi_weights(100.0))
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(f), u, 1e-8, 500)
+    assert st == M.E_DIVERGED
+    assert ps[0] == M.E_DIVERGED and ps[2] == M.E_DIVERGED and ps[1] == M.OK
+    for p in (0, 2):
+        _, ost, oit, orho, _ = osv.Solver(jacobi_weights(100.0), a[p], b[p]).solve(f[p], 1e-8, 500)
+        assert ost == osv.DIVERGED and oit == it[p]
+    # argument errors are detected before any launch
+    with pytest.raises(M.MGCNNError):
+        S.solve(dev(f), u, -1.0, 10)
+    S.close()
+
+
+def test_setup_rejects_bad_sizes():
+    say("bad sizes")
+    S = Solver(datagen.xavier_weights(16, 0))
+    a = torch.ones((1, 30, 30), dtype=torch.float32, device="cuda")
+    with pytest.raises(M.MGCNNError) as e:
+        S.setup(a, np.ones((1, 2)))
+    assert e.value.status == M.E_SIZE
+    u = torch.zeros((1, 31, 31), dtype=torch.float64, device="cuda")
+    f = torch.ones((1, 31, 31), dtype=torch.float32, device="cuda")
+    with pytest.raises(M.MGCNNError) as e:
+        S.solve(f, u, 1e-8, 10)
+    assert e.value.status == M.E_STATE
+    S.close()
+
+
+def test_full_size_blocks1023_sampled():
+    """The batched 64 x 1023^2 workload in the launch configuration the benchmark uses:
+    one fixed iteration for the whole batch, two sampled problems compared with the oracle."""
+    say("full-size 1023 x 64, K = 1")
+    n, B = 1023, 64
+    a, b, f = batch("blocks1023", n, B)
+    w = datagen.xavier_weights(16, 0)
+    S = Solver(w, state="f32", u="f64")
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    S.forward(dev(f), u, 1)
+    torch.cuda.synchronize()
+    for p in (0, 63):
+        say("  oracle problem", p)
+        exp = osv.Solver(w, a[p], b[p]).forward(f[p], 1)
+        err = rel(u[p].cpu().numpy(), exp)
+        say("  rel err", err)
+        assert err <= F32_TOL
+    S.close()
