@@ -108,6 +108,27 @@ int mgcnn_solve(mgcnn_ctx *ctx, const float *f, void *u, double tol, int maxit,
  * mgcnn_backward (state must be MGCNN_F32 and u MGCNN_U_F32). */
 int mgcnn_forward(mgcnn_ctx *ctx, const float *f, void *u, int K, int record);
 
+/* Training (loss of Sec. 3.4, Eq. (19), after K unrolled iterations, normalised per problem):
+ *   L = (1/batch) sum_i ||f_i - A_i u_i||^2 / ||f_i||^2.
+ * mgcnn_loss: loss_host (may be NULL) receives L; dloss_du (device [batch][n][n], may be NULL)
+ * receives dL/du = -2 A^T (f - A u) / (batch ||f||^2); dloss_df (may be NULL) receives the
+ * partial derivative of L in f through this expression (u held fixed).  u must be float32
+ * (opts.u_dtype = MGCNN_U_F32).  Blocks the host only when loss_host is given. */
+int mgcnn_loss(mgcnn_ctx *ctx, const float *f, const float *u, double *loss_host, float *dloss_du,
+               float *dloss_df);
+
+/* Reverse pass through the K iterations recorded by the last mgcnn_forward(record = 1) and
+ * through the setup network: given dL_du = dL/du_K (device [batch][n][n]), writes dL/dweights
+ * (device, mgcnn_num_weights(16) floats, same order as the weights) and, if dL_df != NULL,
+ * ADDS dL/df through the iterations into dL_df (device [batch][n][n]).  The right-hand side
+ * passed to the recorded forward must still be valid.  Returns MGCNN_E_NORECORD without a
+ * recorded forward for the current problem set.  Iterations are recomputed from the
+ * checkpointed iterates u_0..u_{K-1} (one iteration's activations live at a time). */
+int mgcnn_backward(mgcnn_ctx *ctx, const float *dL_du, float *dL_dweights, float *dL_df);
+
+/* Replace the weights from DEVICE memory (training loops); asynchronous on the stream. */
+int mgcnn_set_weights_device(mgcnn_ctx *ctx, const float *weights_dev);
+
 /* Apply the network once: z = B(r / D) for a residual r [batch][n][n] float32 device;
  * z float32 device.  This is the linear preconditioner of Sec. 2.2 for Krylov methods. */
 int mgcnn_apply(mgcnn_ctx *ctx, const float *r, float *z);
@@ -118,6 +139,27 @@ int mgcnn_residual_norms(mgcnn_ctx *ctx, const float *f, const void *u, double *
 
 /* Copy the level-l setup tensor (l = 1..L) into `out` [batch][n_l][n_l][16] float32 device. */
 int mgcnn_get_setup_tensor(mgcnn_ctx *ctx, int level, float *out);
+
+/* Per-launch profiling of the solve loop.  Between mgcnn_profile_begin and mgcnn_profile_end
+ * every kernel launched by mgcnn_solve / mgcnn_forward / mgcnn_apply is bracketed by HIP
+ * events on the context stream (graph capture is bypassed while profiling).  profile_end
+ * synchronises and aggregates per (kernel kind, level): launch count, total milliseconds and
+ * the algorithmic bytes one launch must move (compulsory reads + writes of its operands:
+ * e.g. smoother 3 x 16 x state-bytes per node of its level).  Kinds: */
+enum {
+  MGCNN_K_RESIDUAL = 0, MGCNN_K_FINALIZE = 1, MGCNN_K_CONV_IN = 2, MGCNN_K_SMOOTH_DOWN = 3,
+  MGCNN_K_RESTRICT = 4, MGCNN_K_SMOOTH_UP = 5, MGCNN_K_PROLONG = 6, MGCNN_K_OUT_UPDATE = 7
+};
+typedef struct {
+  int kind;                /* MGCNN_K_* */
+  int level;               /* 0 = finest */
+  int launches;
+  double ms_total;
+  double bytes_per_launch;
+} mgcnn_kernel_stat;
+int mgcnn_profile_begin(mgcnn_ctx *ctx);
+/* stats may be NULL (then only *n_stats is set); at most max_stats entries are written. */
+int mgcnn_profile_end(mgcnn_ctx *ctx, mgcnn_kernel_stat *stats, int max_stats, int *n_stats);
 
 /* Number of levels of the current problem set (0 before setup). */
 int mgcnn_levels(const mgcnn_ctx *ctx);

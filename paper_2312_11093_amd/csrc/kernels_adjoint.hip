@@ -1,0 +1,421 @@
+// Reverse-mode kernels for training the MGCNN networks through K unrolled iterations.
+//
+// The reverse of every convolution of the networks is again a convolution:
+//   * same-size conv  y = W * x       ->  dx = (W flipped, channels swapped) * dy
+//                                         dW[o][c][p][q] = sum_px dy[px][o] x[px + (p-1,q-1)][c]
+//   * stride-2 conv   y = W *_2 x     ->  dx = convT_2(W, dy),  dW = sum dy[I] x[2I + (p,q)]
+//   * convT_2         y = convT_2(W,x) -> dx = W *_2 dy,        dW[c][o] = sum x[I][c] dy[2I+(p,q)][o]
+// (the transposed conv of Sec. 2.4, Eq. (3), is the exact transpose of the stride-2 conv).
+// These kernels are direct VALU convolutions (training runs on small grids); weight gradients
+// are written as per-workgroup partial sums and reduced in a fixed order (deterministic).
+//
+// All tensors are channel-last [B][m][m][ch] float32.
+#include "mgcnn_internal.h"
+#include "mgcnn_device.h"
+#include "mgcnn_adjoint.h"
+
+namespace mg {
+
+// ------------------------------------------------------------------------------------------
+// generic direct conv with epilogues
+// ------------------------------------------------------------------------------------------
+// Geometry: GM_SAME (pad 1, mo = mi), GM_S2 (stride 2, pad 0, mo = (mi-1)/2),
+//           GM_T2 (transposed stride 2, pad 0, mo = 2 mi + 1).
+// Weight access: element (o, c, tap) of the operator actually applied is
+//   W[ trans ? (c*CO + o) : (o*CI + c) ][ flip ? 8 - tap : tap ].
+// Pre-multiplication of the input (at every input pixel): PM_NONE, PM_MUL (x * m),
+//   PM_TANHD (x * (1 - m^2)).
+// Epilogue: EP_STORE y = acc; EP_ADD y += acc; EP_SKIP y = skip + acc;
+//   EP_SMOOTH_BWD (gz = acc): y = skip + m2 * gz, gs += m3 * gz.
+template <int CI, int CO, int GM, int PM, int EP>
+__global__ __launch_bounds__(256) void dconv_kernel(ConvArgs A) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int tiles_per_prob = A.tiles_per_prob;
+  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int mo = A.mo, mi = A.mi;
+  const int j = (tile % A.tiles_x) * 64 + (threadIdx.x & 63);
+  const int i = (tile / A.tiles_x) * 4 + (threadIdx.x >> 6);
+  if (i >= mo || j >= mo) return;
+  const float* X = A.x + (size_t)b * mi * mi * CI;
+  const float* Mp = A.m ? A.m + (size_t)b * mi * mi * CI : nullptr;
+  float acc[CO];
+#pragma unroll
+  for (int o = 0; o < CO; ++o) acc[o] = 0.f;
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      int ii, jj;
+      bool ok;
+      if constexpr (GM == GM_SAME) {
+        ii = i + p - 1; jj = j + q - 1;
+        ok = ii >= 0 && ii < mi && jj >= 0 && jj < mi;
+      } else if constexpr (GM == GM_S2) {
+        ii = 2 * i + p; jj = 2 * j + q;
+        ok = ii < mi && jj < mi;
+      } else {
+        // output fine (i, j) gets input coarse (I, J) with 2I + p = i, 2J + q = j
+        const int di = i - p, dj = j - q;
+        ok = di >= 0 && dj >= 0 && (di & 1) == 0 && (dj & 1) == 0;
+        ii = di >> 1; jj = dj >> 1;
+        ok = ok && ii < mi && jj < mi;
+      }
+      if (!ok) continue;
+      const size_t px = (size_t)ii * mi + jj;
+      float v[CI];
+#pragma unroll
+      for (int c = 0; c < CI; ++c) {
+        float xv = X[px * CI + c];
+        if constexpr (PM == PM_MUL) xv *= Mp[px * CI + c];
+        if constexpr (PM == PM_TANHD) { const float tv = Mp[px * CI + c]; xv *= (1.f - tv * tv); }
+        v[c] = xv;
+      }
+      const int tap = A.flip ? 8 - (p * 3 + q) : (p * 3 + q);
+#pragma unroll
+      for (int o = 0; o < CO; ++o) {
+        float s = acc[o];
+#pragma unroll
+        for (int c = 0; c < CI; ++c) {
+          const int wi = A.trans ? (c * CO + o) : (o * CI + c);
+          s = fmaf(A.W[wi * 9 + tap], v[c], s);
+        }
+        acc[o] = s;
+      }
+    }
+  }
+  const size_t op = (size_t)b * mo * mo + (size_t)i * mo + j;
+  float* Y = A.y + op * CO;
+#pragma unroll
+  for (int o = 0; o < CO; ++o) {
+    if constexpr (EP == EP_STORE) Y[o] = acc[o];
+    if constexpr (EP == EP_ADD) Y[o] += acc[o];
+    if constexpr (EP == EP_SKIP) Y[o] = A.skip[op * CO + o] + acc[o];
+    if constexpr (EP == EP_TANH_BIAS) Y[o] = tanhf(acc[o] + A.bias[o]);
+    if constexpr (EP == EP_SMOOTH_BWD) {
+      Y[o] = A.skip[op * CO + o] + A.m2[op * CO + o] * acc[o];
+      A.gs[op * CO + o] += A.m3[op * CO + o] * acc[o];
+    }
+  }
+}
+
+#define DCONV_CASE(CI_, CO_, GM_, PM_, EP_)                                                   \
+  if (A.ci == CI_ && A.co == CO_ && A.gm == GM_ && A.pm == PM_ && A.ep == EP_) {             \
+    hipLaunchKernelGGL((dconv_kernel<CI_, CO_, GM_, PM_, EP_>), grid, dim3(256), 0, st, A); \
+    return;                                                                                   \
+  }
+
+void launch_dconv(ConvArgs A, int B, hipStream_t st) {
+  A.tiles_x = (A.mo + 63) / 64;
+  A.tiles_per_prob = A.tiles_x * ((A.mo + 3) / 4);
+  const dim3 grid(A.tiles_per_prob * B);
+  // output-layer adjoint 1 -> 16, input-layer adjoint 16 -> 1
+  DCONV_CASE(1, 16, GM_SAME, PM_NONE, EP_STORE)
+  DCONV_CASE(16, 1, GM_SAME, PM_NONE, EP_STORE)
+  // smoother adjoint
+  DCONV_CASE(16, 16, GM_SAME, PM_NONE, EP_SMOOTH_BWD)
+  // setup layer adjoint
+  DCONV_CASE(16, 16, GM_SAME, PM_TANHD, EP_SKIP)
+  // setup recomputation (tape for the reverse pass)
+  DCONV_CASE(4, 16, GM_SAME, PM_NONE, EP_STORE)
+  DCONV_CASE(16, 16, GM_SAME, PM_NONE, EP_TANH_BIAS)
+  // transfers (adjoint of restrict = transposed conv; adjoint of prolong = stride-2 conv)
+  DCONV_CASE(16, 16, GM_T2, PM_NONE, EP_ADD)
+  DCONV_CASE(16, 16, GM_S2, PM_NONE, EP_STORE)
+  DCONV_CASE(16, 16, GM_S2, PM_NONE, EP_ADD)
+}
+
+// ------------------------------------------------------------------------------------------
+// weight gradients: dW[a][bb][tap] = sum over "A pixels" P of A[P][a] * Bsrc(P, tap)[bb]
+//   GM_SAME: Bsrc(P, tap) = Bx[P + (p-1, q-1)] (zero outside), A and B on the same grid
+//   GM_S2:   A on the coarse grid (mc), Bsrc = Bx[2I + p, 2J + q] on the fine grid (2 mc + 1)
+// Optional pre-multiplication of B (PM_MUL: Bx * Bm) and of A (PM_TANHD on A: A * (1 - Am^2)).
+// One workgroup handles 256 A-pixels of one problem and writes CA*CB*9 partial sums.
+// ------------------------------------------------------------------------------------------
+template <int CA, int CB, int GM, int PMB, int PMA>
+struct WgradTile {
+  static constexpr int TH = (GM == GM_SAME) ? 4 : 4;
+  static constexpr int TW = (GM == GM_SAME) ? 64 : 32;
+  static constexpr int BH = (GM == GM_SAME) ? TH + 2 : 2 * TH + 1;
+  static constexpr int BW = (GM == GM_SAME) ? TW + 2 : 2 * TW + 1;
+};
+
+template <int CA, int CB, int GM, int PMB, int PMA>
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs G) {
+  typedef WgradTile<CA, CB, GM, PMB, PMA> T;
+  constexpr int NE = CA * CB * 9;
+  constexpr int NP = T::TH * T::TW;
+  __shared__ float sA[NP * CA];
+  __shared__ float sB[T::BH * T::BW * CB];
+  const int t = blockIdx.x;     // one partial row per workgroup; fixed order for the reduction
+  const int b = t / G.tiles_per_prob, tile = t % G.tiles_per_prob;
+  const int ma = G.ma, mb = G.mb;
+  const int i0 = (tile / G.tiles_x) * T::TH, j0 = (tile % G.tiles_x) * T::TW;
+  for (int k = threadIdx.x; k < NP * CA; k += 256) {
+    const int P = k / CA, a = k % CA;
+    const int i = i0 + P / T::TW, j = j0 + P % T::TW;
+    float v = 0.f;
+    if (i < ma && j < ma) {
+      const size_t pa = (size_t)b * ma * ma + (size_t)i * ma + j;
+      v = G.A[pa * CA + a];
+      if constexpr (PMA == PM_TANHD) { const float tv = G.Am[pa * CA + a]; v *= (1.f - tv * tv); }
+    }
+    sA[k] = v;
+  }
+  const int bi0 = (GM == GM_SAME) ? i0 - 1 : 2 * i0;
+  const int bj0 = (GM == GM_SAME) ? j0 - 1 : 2 * j0;
+  for (int k = threadIdx.x; k < T::BH * T::BW * CB; k += 256) {
+    const int pix = k / CB, c = k % CB;
+    const int ii = bi0 + pix / T::BW, jj = bj0 + pix % T::BW;
+    float v = 0.f;
+    if (ii >= 0 && ii < mb && jj >= 0 && jj < mb) {
+      const size_t pb = (size_t)b * mb * mb + (size_t)ii * mb + jj;
+      v = G.Bx[pb * CB + c];
+      if constexpr (PMB == PM_MUL) v *= G.Bm[pb * CB + c];
+    }
+    sB[k] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NE; e += 256) {
+    const int tap = e % 9, ab = e / 9;
+    const int a = ab / CB, c = ab % CB;
+    const int p = tap / 3, q = tap % 3;
+    float s = 0.f;
+    for (int P = 0; P < NP; ++P) {
+      const int pi = P / T::TW, pj = P % T::TW;
+      const int bi = (GM == GM_SAME) ? pi + p : 2 * pi + p;
+      const int bj = (GM == GM_SAME) ? pj + q : 2 * pj + q;
+      s = fmaf(sA[P * CA + a], sB[(bi * T::BW + bj) * CB + c], s);
+    }
+    G.partial[(size_t)t * NE + e] = s;
+  }
+}
+
+#define WGRAD_CASE(CA_, CB_, GM_, PMB_, PMA_)                                                 \
+  if (G.ca == CA_ && G.cb == CB_ && G.gm == GM_ && G.pmb == PMB_ && G.pma == PMA_) {         \
+    hipLaunchKernelGGL((wgrad_kernel<CA_, CB_, GM_, PMB_, PMA_>), grid, dim3(256), 0, st, G); \
+    return nblocks;                                                                           \
+  }
+
+int launch_wgrad(WgradArgs G, int B, hipStream_t st) {
+  const int TW = (G.gm == GM_SAME) ? 64 : 32, TH = 4;
+  G.tiles_x = (G.ma + TW - 1) / TW;
+  G.tiles_per_prob = G.tiles_x * ((G.ma + TH - 1) / TH);
+  const int nblocks = G.tiles_per_prob * B;
+  const dim3 grid(nblocks);
+  WGRAD_CASE(16, 16, GM_SAME, PM_MUL, PM_NONE)    // smoothers: B = s . x
+  WGRAD_CASE(16, 16, GM_SAME, PM_NONE, PM_TANHD)  // setup ResNet layers: A = g . (1 - t^2)
+  WGRAD_CASE(16, 16, GM_S2, PM_NONE, PM_NONE)     // restriction / prolongation / setup restriction
+  WGRAD_CASE(16, 1, GM_SAME, PM_NONE, PM_NONE)    // reChannel-in
+  WGRAD_CASE(1, 16, GM_SAME, PM_NONE, PM_NONE)    // reChannel-out
+  WGRAD_CASE(16, 4, GM_SAME, PM_NONE, PM_NONE)    // setup reChannel
+  return -1;
+}
+
+// out[e] (+)= sum_{k < nblocks} partial[k * ne + e]  (fixed order)
+__global__ void reduce_partials_kernel(const float* __restrict__ partial, int nblocks, int ne,
+                                       float* __restrict__ out, int accumulate) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double s = 0.0;
+  for (int k = 0; k < nblocks; ++k) s += (double)partial[(size_t)k * ne + e];
+  out[e] = accumulate ? out[e] + (float)s : (float)s;
+}
+
+void launch_reduce_partials(const float* partial, int nblocks, int ne, float* out, bool accumulate,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((ne + 255) / 256), dim3(256), 0, st, partial,
+                     nblocks, ne, out, accumulate ? 1 : 0);
+}
+
+// bias gradient partials: partial[wg][o] = sum_px g[px][o] (1 - t[px][o]^2)
+__global__ __launch_bounds__(256) void bias_grad_kernel(const float* __restrict__ g,
+                                                        const float* __restrict__ tt,
+                                                        float* __restrict__ partial, size_t npx) {
+  __shared__ float red[256][C + 1];
+  float s[C];
+#pragma unroll
+  for (int o = 0; o < C; ++o) s[o] = 0.f;
+  for (size_t px = (size_t)blockIdx.x * 256 + threadIdx.x; px < npx; px += (size_t)gridDim.x * 256) {
+#pragma unroll
+    for (int o = 0; o < C; ++o) {
+      const float tv = tt[px * C + o];
+      s[o] = fmaf(g[px * C + o], 1.f - tv * tv, s[o]);
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < C; ++o) red[threadIdx.x][o] = s[o];
+  __syncthreads();
+  if (threadIdx.x < C) {
+    float acc = 0.f;
+    for (int k = 0; k < 256; ++k) acc += red[k][threadIdx.x];
+    partial[(size_t)blockIdx.x * C + threadIdx.x] = acc;
+  }
+}
+
+int launch_bias_grad(const float* g, const float* t, float* partial, size_t npx, hipStream_t st) {
+  int blocks = (int)((npx + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks), dim3(256), 0, st, g, t, partial, npx);
+  return blocks;
+}
+
+// ------------------------------------------------------------------------------------------
+// operator transpose and the iteration adjoint
+// ------------------------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R harm2(R p, R q) { return (R(2) * p * q) / (p + q); }
+
+// Entries of row (i, j) of A (divergence form, harmonic faces, upwind convection).
+struct Row { double C, E, W, N, S; };
+__device__ __forceinline__ Row row_of(const float* Ab, int n, int i, int j, double bx, double by) {
+  const size_t ij = (size_t)i * n + j;
+  const double ac = Ab[ij];
+  const double aE = (j + 1 < n) ? harm2<double>(ac, Ab[ij + 1]) : ac;
+  const double aW = (j > 0) ? harm2<double>(ac, Ab[ij - 1]) : ac;
+  const double aN = (i + 1 < n) ? harm2<double>(ac, Ab[ij + n]) : ac;
+  const double aS = (i > 0) ? harm2<double>(ac, Ab[ij - n]) : ac;
+  const double ih = (double)(n + 1), ih2 = ih * ih;
+  const double bxp = bx > 0 ? bx : 0, bxm = bx < 0 ? bx : 0;
+  const double byp = by > 0 ? by : 0, bym = by < 0 ? by : 0;
+  Row r;
+  r.C = (aE + aW + aN + aS) * ih2 + (bxp - bxm + byp - bym) * ih;
+  r.E = -aE * ih2 + bxm * ih;
+  r.W = -aW * ih2 - bxp * ih;
+  r.N = -aN * ih2 + bym * ih;
+  r.S = -aS * ih2 - byp * ih;
+  return r;
+}
+
+// out = base + alpha_b * A^T (v / D)   where (v / D) is taken row-wise (div_by_diag) or not.
+// Used for lambda_k = lambda_{k+1} - A^T (g_rt / D) (alpha = -1, div) and for the loss
+// gradient -2 A^T r / (N ||f||^2) (base = 0, alpha_b = -2/(N nf2[b]), no div).
+__global__ __launch_bounds__(256) void apply_AT_kernel(const float* __restrict__ a,
+                                                       const float* __restrict__ bvec,
+                                                       const float* __restrict__ v,
+                                                       const float* __restrict__ base,
+                                                       const double* __restrict__ nf2, double alpha,
+                                                       int div_by_diag, float* __restrict__ out,
+                                                       float* __restrict__ df_acc, int n,
+                                                       int tiles_x, int tiles_per_prob, int N) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
+  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
+  if (i >= n || j >= n) return;
+  const float* Ab = a + (size_t)b * n * n;
+  const float* V = v + (size_t)b * n * n;
+  const double bx = bvec[2 * b], by = bvec[2 * b + 1];
+  auto val = [&](int ii, int jj, const Row& r) -> double {
+    const double x = V[(size_t)ii * n + jj];
+    return div_by_diag ? x / r.C : x;
+  };
+  const Row rc = row_of(Ab, n, i, j, bx, by);
+  double s = rc.C * val(i, j, rc);
+  if (j > 0) { const Row r = row_of(Ab, n, i, j - 1, bx, by); s += r.E * val(i, j - 1, r); }
+  if (j + 1 < n) { const Row r = row_of(Ab, n, i, j + 1, bx, by); s += r.W * val(i, j + 1, r); }
+  if (i > 0) { const Row r = row_of(Ab, n, i - 1, j, bx, by); s += r.N * val(i - 1, j, r); }
+  if (i + 1 < n) { const Row r = row_of(Ab, n, i + 1, j, bx, by); s += r.S * val(i + 1, j, r); }
+  double al = alpha;
+  if (nf2 != nullptr) al = alpha / ((double)N * nf2[b]);
+  const size_t c = (size_t)b * n * n + (size_t)i * n + j;
+  const double bs = base ? (double)base[c] : 0.0;
+  out[c] = (float)(bs + al * s);
+  if (df_acc != nullptr) df_acc[c] += (float)(val(i, j, rc));
+}
+
+void launch_apply_AT(const float* a, const float* b, const float* v, const float* base,
+                     const double* nf2, double alpha, bool div_by_diag, float* out, float* df_acc,
+                     int n, int B, hipStream_t st) {
+  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  hipLaunchKernelGGL(apply_AT_kernel, dim3(tx * ty * B), dim3(256), 0, st, a, b, v, base, nf2, alpha,
+                     div_by_diag ? 1 : 0, out, df_acc, n, tx, tx * ty, B);
+}
+
+// residual r = f - A u (u f32) into r, and per-problem partial sums of r^2
+// (reuses the forward residual kernel's conventions); loss partials via launch_residual.
+
+__global__ void loss_finalize_kernel(const double* __restrict__ rr, const double* __restrict__ nf2,
+                                     int B, double* __restrict__ loss) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < B; ++b) s += rr[b] / nf2[b];
+  *loss = s / B;
+}
+
+void launch_loss_finalize(const double* rr, const double* nf2, int B, double* loss, hipStream_t st) {
+  hipLaunchKernelGGL(loss_finalize_kernel, dim3(1), dim3(64), 0, st, rr, nf2, B, loss);
+}
+
+// dL/df from the loss term itself: 2 r / (N nf2) - 2 rr f / (N nf2^2)
+__global__ void loss_df_kernel(const float* __restrict__ r, const float* __restrict__ f,
+                               const double* __restrict__ rr, const double* __restrict__ nf2,
+                               float* __restrict__ df, size_t nn, int B) {
+  const size_t total = nn * (size_t)B;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const int b = (int)(k / nn);
+    const double q = nf2[b];
+    df[k] = (float)(2.0 * r[k] / (B * q) - 2.0 * rr[b] * f[k] / (B * q * q));
+  }
+}
+
+void launch_loss_df(const float* r, const float* f, const double* rr, const double* nf2, float* df,
+                    int n, int B, hipStream_t st) {
+  const size_t nn = (size_t)n * n;
+  size_t blocks = (nn * B + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(loss_df_kernel, dim3((unsigned)blocks), dim3(256), 0, st, r, f, rr, nf2, df, nn, B);
+}
+
+// r = f - A u in float32 output (u f32 or f64) -- the plain residual (no scaling)
+template <typename UT>
+__global__ __launch_bounds__(256) void residual_plain_kernel(const float* __restrict__ a,
+                                                             const float* __restrict__ bvec,
+                                                             const float* __restrict__ f,
+                                                             const UT* __restrict__ u,
+                                                             float* __restrict__ r, int n,
+                                                             int tiles_x, int tiles_per_prob) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
+  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
+  if (i >= n || j >= n) return;
+  const float* Ab = a + (size_t)b * n * n;
+  const UT* U = u + (size_t)b * n * n;
+  const Row rw = row_of(Ab, n, i, j, bvec[2 * b], bvec[2 * b + 1]);
+  const size_t ij = (size_t)i * n + j;
+  double s = rw.C * (double)U[ij];
+  if (j + 1 < n) s += rw.E * (double)U[ij + 1];
+  if (j > 0) s += rw.W * (double)U[ij - 1];
+  if (i + 1 < n) s += rw.N * (double)U[ij + n];
+  if (i > 0) s += rw.S * (double)U[ij - n];
+  r[(size_t)b * n * n + ij] = (float)((double)f[(size_t)b * n * n + ij] - s);
+}
+
+void launch_residual_plain(const float* a, const float* b, const float* f, const void* u, bool u_f64,
+                           float* r, int n, int B, hipStream_t st) {
+  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  if (u_f64)
+    hipLaunchKernelGGL(residual_plain_kernel<double>, dim3(tx * ty * B), dim3(256), 0, st, a, b, f,
+                       (const double*)u, r, n, tx, tx * ty);
+  else
+    hipLaunchKernelGGL(residual_plain_kernel<float>, dim3(tx * ty * B), dim3(256), 0, st, a, b, f,
+                       (const float*)u, r, n, tx, tx * ty);
+}
+
+// elementwise y = x + z
+__global__ void add_kernel(const float* __restrict__ x, const float* __restrict__ z,
+                           float* __restrict__ y, size_t count) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += (size_t)gridDim.x * blockDim.x)
+    y[k] = x[k] + z[k];
+}
+
+void launch_add(const float* x, const float* z, float* y, size_t count, hipStream_t st) {
+  if (count == 0) return;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(add_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, z, y, count);
+}
+
+}  // namespace mg

@@ -12,6 +12,7 @@
 
 #include "../../include/mgcnn.h"
 #include "mgcnn_internal.h"
+#include "mgcnn_ctx.h"
 
 using namespace mg;
 
@@ -43,37 +44,8 @@ void launch_scale_by_diag(const float* a, const float* b, const float* r, float*
 
 }  // namespace mg
 
-struct mgcnn_ctx {
-  mgcnn_opts opts{};
-  hipStream_t stream = nullptr;
-  WeightOffsets off{};
-  float* d_w = nullptr;
-  std::string err;
-
-  // problem set
-  int n = 0, B = 0, L = 0;
-  int alloc_n = 0, alloc_B = 0;
-  std::vector<int> nl;
-  float* d_a = nullptr;
-  float* d_b = nullptr;
-  std::vector<void*> s, xin, xdn;
-  float* d_rt = nullptr;
-  double* d_partial = nullptr;
-  int tiles = 0;
-  double* d_nf2 = nullptr;
-  int* d_active = nullptr;
-  int* d_status = nullptr;
-  int* d_iters = nullptr;
-  double* d_relres = nullptr;
-  bool ready = false;
-
-  size_t state_bytes() const { return opts.state_dtype == MGCNN_BF16 ? 2 : 4; }
-  StateType st() const { return opts.state_dtype == MGCNN_BF16 ? ST_BF16 : ST_F32; }
-  bool u64() const { return opts.u_dtype == MGCNN_U_F64; }
-  const float* W(size_t o) const { return d_w + o; }
-};
-
-namespace {
+namespace mg {
+namespace api {
 
 int fail(mgcnn_ctx* ctx, int code, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -84,17 +56,14 @@ int hip_fail(mgcnn_ctx* ctx, hipError_t e, const char* what) {
   return fail(ctx, MGCNN_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(ctx, call)                                            \
-  do {                                                                \
-    hipError_t e_ = (call);                                           \
-    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);          \
-  } while (0)
-
-#define LAUNCH_CHECK(ctx)                                             \
-  do {                                                                \
-    hipError_t e_ = hipGetLastError();                                \
-    if (e_ != hipSuccess) return hip_fail((ctx), e_, "kernel launch"); \
-  } while (0)
+hipEvent_t pool_event(mgcnn_ctx* c) {
+  if (c->pool_used == c->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->pool.push_back(e);
+  }
+  return c->pool[c->pool_used++];
+}
 
 bool valid_n(int n) {
   if (n < 3 || n > 4095) return false;
@@ -169,37 +138,69 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active) {
   const StateType st = c->st();
   const int L = c->L, B = c->B;
   hipStream_t s = c->stream;
-  launch_conv_in(1, c->d_rt, c->W(c->off.solve_in), c->xin[0], st, c->n, B, active, s);
+  const double S = (double)c->state_bytes() * C;        // bytes of one 16-channel pixel
+  auto nodes = [&](int l) { return (double)c->nl[l] * c->nl[l] * B; };
+  {
+    Prof p(c, MGCNN_K_CONV_IN, 0, nodes(0) * (4.0 + S));
+    launch_conv_in(1, c->d_rt, c->W(c->off.solve_in), c->xin[0], st, c->n, B, active, s);
+  }
   for (int l = 0; l < L; ++l) {
-    launch_conv16(CM_SMOOTH, st, c->xin[l], c->s[l], c->W(c->off.smooth_down), nullptr, c->xdn[l],
-                  c->nl[l], B, active, s);
-    if (l < L - 1)
+    {
+      Prof p(c, MGCNN_K_SMOOTH_DOWN, l, nodes(l) * 3.0 * S);
+      launch_conv16(CM_SMOOTH, st, c->xin[l], c->s[l], c->W(c->off.smooth_down), nullptr, c->xdn[l],
+                    c->nl[l], B, active, s);
+    }
+    if (l < L - 1) {
+      Prof p(c, MGCNN_K_RESTRICT, l, (nodes(l) + nodes(l + 1)) * S);
       launch_conv16(CM_RESTRICT, st, c->xdn[l], nullptr, c->W(c->off.restrict_), nullptr,
                     c->xin[l + 1], c->nl[l], B, active, s);
+    }
   }
-  launch_conv16(CM_SMOOTH, st, c->xdn[L - 1], c->s[L - 1], c->W(c->off.smooth_up), nullptr,
-                c->xin[L - 1], c->nl[L - 1], B, active, s);
+  {
+    Prof p(c, MGCNN_K_SMOOTH_UP, L - 1, nodes(L - 1) * 3.0 * S);
+    launch_conv16(CM_SMOOTH, st, c->xdn[L - 1], c->s[L - 1], c->W(c->off.smooth_up), nullptr,
+                  c->xin[L - 1], c->nl[L - 1], B, active, s);
+  }
   for (int l = L - 2; l >= 0; --l) {
-    launch_prolong_add(st, c->xin[l + 1], c->W(c->off.prolong), c->xdn[l], c->nl[l + 1], B, active,
-                       s);
-    launch_conv16(CM_SMOOTH, st, c->xdn[l], c->s[l], c->W(c->off.smooth_up), nullptr, c->xin[l],
-                  c->nl[l], B, active, s);
+    {
+      Prof p(c, MGCNN_K_PROLONG, l, (nodes(l + 1) + 2.0 * nodes(l)) * S);
+      launch_prolong_add(st, c->xin[l + 1], c->W(c->off.prolong), c->xdn[l], c->nl[l + 1], B,
+                         active, s);
+    }
+    {
+      Prof p(c, MGCNN_K_SMOOTH_UP, l, nodes(l) * 3.0 * S);
+      launch_conv16(CM_SMOOTH, st, c->xdn[l], c->s[l], c->W(c->off.smooth_up), nullptr, c->xin[l],
+                    c->nl[l], B, active, s);
+    }
   }
-  launch_out_update(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, active, s);
+  {
+    Prof p(c, MGCNN_K_OUT_UPDATE, 0, nodes(0) * (S + 2.0 * (u_f64 ? 8 : 4)));
+    launch_out_update(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, active, s);
+  }
   LAUNCH_CHECK(c);
   return MGCNN_OK;
 }
 
 // residual of the current iterate, stopping test, then one V-cycle for live problems
 int solve_step(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit) {
-  launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->B, c->d_active,
-                  c->stream);
-  launch_finalize(c->d_partial, c->tiles, c->d_nf2, tol, maxit, c->d_active, c->d_status,
-                  c->d_iters, c->d_relres, c->B, c->stream);
+  {
+    const double nodes = (double)c->n * c->n * c->B;
+    Prof p(c, MGCNN_K_RESIDUAL, 0, nodes * (12.0 + (c->u64() ? 8 : 4)));
+    launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->B, c->d_active,
+                    c->stream);
+  }
+  {
+    Prof p(c, MGCNN_K_FINALIZE, 0, (double)c->tiles * c->B * 8.0);
+    launch_finalize(c->d_partial, c->tiles, c->d_nf2, tol, maxit, c->d_active, c->d_status,
+                    c->d_iters, c->d_relres, c->B, c->stream);
+  }
   return vcycle(c, u, c->u64(), c->d_active);
 }
 
-}  // namespace
+}  // namespace api
+}  // namespace mg
+
+using namespace mg::api;
 
 extern "C" {
 
@@ -364,10 +365,14 @@ int mgcnn_forward(mgcnn_ctx* c, const float* f, void* u, int K, int record) {
   if (!c) return MGCNN_E_ARG;
   if (!c->ready) return fail(c, MGCNN_E_STATE, "forward: call mgcnn_setup first");
   if (!f || !u || K < 0) return fail(c, MGCNN_E_ARG, "forward: bad argument");
-  if (record) return fail(c, MGCNN_E_ARG, "forward: recording is not available in this build");
+  if (record) return forward_record(c, f, (float*)u, K);
   for (int k = 0; k < K; ++k) {
-    launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->B, nullptr,
-                    c->stream);
+    {
+      const double nodes = (double)c->n * c->n * c->B;
+      Prof p(c, MGCNN_K_RESIDUAL, 0, nodes * (12.0 + (c->u64() ? 8 : 4)));
+      launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->B, nullptr,
+                      c->stream);
+    }
     int r = vcycle(c, u, c->u64(), nullptr);
     if (r) return r;
   }
@@ -417,6 +422,42 @@ int mgcnn_get_setup_tensor(mgcnn_ctx* c, int level, float* out) {
   return MGCNN_OK;
 }
 
+int mgcnn_profile_begin(mgcnn_ctx* c) {
+  if (!c) return MGCNN_E_ARG;
+  c->recs.clear();
+  c->pool_used = 0;
+  c->prof = true;
+  return MGCNN_OK;
+}
+
+int mgcnn_profile_end(mgcnn_ctx* c, mgcnn_kernel_stat* stats, int max_stats, int* n_stats) {
+  if (!c) return MGCNN_E_ARG;
+  c->prof = false;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<mgcnn_kernel_stat> agg;
+  for (const auto& r : c->recs) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, r.e0, r.e1));
+    mgcnn_kernel_stat* hit = nullptr;
+    for (auto& a : agg)
+      if (a.kind == r.kind && a.level == r.level) { hit = &a; break; }
+    if (!hit) {
+      mgcnn_kernel_stat z{};
+      z.kind = r.kind; z.level = r.level; z.bytes_per_launch = r.bytes;
+      agg.push_back(z);
+      hit = &agg.back();
+    }
+    hit->launches += 1;
+    hit->ms_total += ms;
+  }
+  c->recs.clear();
+  c->pool_used = 0;
+  if (n_stats) *n_stats = (int)agg.size();
+  if (stats)
+    for (int i = 0; i < (int)agg.size() && i < max_stats; ++i) stats[i] = agg[i];
+  return MGCNN_OK;
+}
+
 int mgcnn_levels(const mgcnn_ctx* c) { return (c && c->ready) ? c->L : 0; }
 
 const char* mgcnn_status_string(int s) {
@@ -439,7 +480,9 @@ const char* mgcnn_last_error(const mgcnn_ctx* c) { return c ? c->err.c_str() : "
 void mgcnn_destroy(mgcnn_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+  free_train(c);
   free_problem(c);
+  for (auto e : c->pool) (void)hipEventDestroy(e);
   if (c->d_w) (void)hipFree(c->d_w);
   delete c;
 }

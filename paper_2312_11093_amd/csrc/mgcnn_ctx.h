@@ -1,0 +1,111 @@
+// Internal definition of the library context shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mgcnn.h"
+#include "mgcnn_internal.h"
+
+struct mgcnn_ctx {
+  mgcnn_opts opts{};
+  hipStream_t stream = nullptr;
+  mg::WeightOffsets off{};
+  float* d_w = nullptr;
+  std::string err;
+
+  // problem set
+  int n = 0, B = 0, L = 0;
+  int alloc_n = 0, alloc_B = 0;
+  std::vector<int> nl;
+  float* d_a = nullptr;
+  float* d_b = nullptr;
+  std::vector<void*> s, xin, xdn;
+  float* d_rt = nullptr;
+  double* d_partial = nullptr;
+  int tiles = 0;
+  double* d_nf2 = nullptr;
+  int* d_active = nullptr;
+  int* d_status = nullptr;
+  int* d_iters = nullptr;
+  double* d_relres = nullptr;
+  bool ready = false;
+
+  // per-launch profiling (HIP events around every kernel launch of the solve loop)
+  struct ProfRec { int kind, level; double bytes; hipEvent_t e0, e1; };
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+
+  // training: recorded forward (checkpoints of u_0..u_{K-1}) and reverse-pass workspace
+  struct Train {
+    int alloc_n = 0, alloc_B = 0, alloc_K = 0;
+    int K = 0;                       // iterations recorded by the last forward(record)
+    const float* f = nullptr;        // right-hand side of the recorded forward (caller-owned)
+    float* uk = nullptr;             // [K][B][n][n] checkpoints
+    std::vector<float*> xin, xdn, v, xup, g1, g2, gs;   // per level, [B][m][m][16]
+    std::vector<float*> c, gc;       // setup: coefficient tensors and their gradients per level
+    std::vector<float*> z, t;        // setup: layer inputs / tanh outputs, [level * 4 + k]
+    float *F = nullptr, *gz0 = nullptr, *gz1 = nullptr;
+    float *grt = nullptr, *lam0 = nullptr, *lam1 = nullptr, *r = nullptr;
+    float* grad = nullptr;           // [num_weights]
+    float* partial = nullptr;        // weight-gradient partial sums
+    size_t partial_floats = 0;
+    double* d_loss = nullptr;
+    double* d_rr = nullptr;
+  } tr;
+
+  size_t state_bytes() const { return opts.state_dtype == MGCNN_BF16 ? 2 : 4; }
+  mg::StateType st() const { return opts.state_dtype == MGCNN_BF16 ? mg::ST_BF16 : mg::ST_F32; }
+  bool u64() const { return opts.u_dtype == MGCNN_U_F64; }
+  const float* W(size_t o) const { return d_w + o; }
+};
+
+
+namespace mg {
+namespace api {
+
+int fail(mgcnn_ctx* ctx, int code, const std::string& msg);
+int hip_fail(mgcnn_ctx* ctx, hipError_t e, const char* what);
+int alloc(mgcnn_ctx* c, void** p, size_t bytes);
+hipEvent_t pool_event(mgcnn_ctx* c);
+int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active);
+int forward_record(mgcnn_ctx* c, const float* f, float* u, int K);
+void free_train(mgcnn_ctx* c);
+
+#define HIP_TRY(ctx, call)                                            \
+  do {                                                                \
+    hipError_t e_ = (call);                                           \
+    if (e_ != hipSuccess) return mg::api::hip_fail((ctx), e_, #call); \
+  } while (0)
+
+#define LAUNCH_CHECK(ctx)                                                      \
+  do {                                                                         \
+    hipError_t e_ = hipGetLastError();                                         \
+    if (e_ != hipSuccess) return mg::api::hip_fail((ctx), e_, "kernel launch"); \
+  } while (0)
+
+// Record events around one launch when profiling is on.
+struct Prof {
+  mgcnn_ctx* c;
+  mgcnn_ctx::ProfRec r{};
+  bool on;
+  Prof(mgcnn_ctx* c_, int kind, int level, double bytes) : c(c_), on(c_->prof) {
+    if (!on) return;
+    r.kind = kind; r.level = level; r.bytes = bytes;
+    r.e0 = pool_event(c); r.e1 = pool_event(c);
+    if (!r.e0 || !r.e1) { on = false; return; }
+    (void)hipEventRecord(r.e0, c->stream);
+  }
+  ~Prof() {
+    if (!on) return;
+    (void)hipEventRecord(r.e1, c->stream);
+    c->recs.push_back(r);
+  }
+};
+
+}  // namespace api
+}  // namespace mg

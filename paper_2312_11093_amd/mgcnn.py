@@ -31,6 +31,14 @@ class mgcnn_opts(ctypes.Structure):
                 ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int)]
 
 
+class mgcnn_kernel_stat(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("level", ctypes.c_int), ("launches", ctypes.c_int),
+                ("ms_total", ctypes.c_double), ("bytes_per_launch", ctypes.c_double)]
+
+
+KERNEL_KINDS = {0: "residual", 1: "finalize", 2: "conv_in", 3: "smooth_down", 4: "restrict",
+                5: "smooth_up", 6: "prolong", 7: "out_update"}
+
 EXPORTS = {
     # name: (restype, argtypes)
     "mgcnn_default_opts": (None, [ctypes.POINTER(mgcnn_opts)]),
@@ -50,6 +58,13 @@ EXPORTS = {
                                             ctypes.c_void_p]),
     "mgcnn_get_setup_tensor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "mgcnn_levels": (ctypes.c_int, [ctypes.c_void_p]),
+    "mgcnn_loss": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
+    "mgcnn_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mgcnn_set_weights_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mgcnn_profile_begin": (ctypes.c_int, [ctypes.c_void_p]),
+    "mgcnn_profile_end": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int)]),
     "mgcnn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mgcnn_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "mgcnn_destroy": (None, [ctypes.c_void_p]),
@@ -194,6 +209,44 @@ class Solver:
         out = torch.empty((self.batch, m, m, 16), dtype=torch.float32, device="cuda")
         self._raise(self._L.mgcnn_get_setup_tensor(self._h, int(level), _ptr(out)))
         return out
+
+    def set_weights_device(self, w):
+        import torch
+        _check_dev(w, torch.float32, "weights")
+        return self._raise(self._L.mgcnn_set_weights_device(self._h, _ptr(w)))
+
+    def loss(self, f, u, dloss_du=None, dloss_df=None):
+        """Mean over the batch of ||f - A u||^2 / ||f||^2 (u float32); optionally its gradients."""
+        import torch
+        _check_dev(f, torch.float32, "f")
+        _check_dev(u, torch.float32, "u")
+        out = ctypes.c_double(0.0)
+        self._raise(self._L.mgcnn_loss(self._h, _ptr(f), _ptr(u), ctypes.byref(out),
+                                       _ptr(dloss_du) if dloss_du is not None else None,
+                                       _ptr(dloss_df) if dloss_df is not None else None))
+        return out.value
+
+    def backward(self, dL_du, dL_dw=None, dL_df=None):
+        """Reverse pass of the last recorded forward; returns dL/dweights (device tensor).
+        dL_df, if given, is accumulated into."""
+        import torch
+        _check_dev(dL_du, torch.float32, "dL_du")
+        if dL_dw is None:
+            dL_dw = torch.empty(int(self._L.mgcnn_num_weights(16)), dtype=torch.float32, device="cuda")
+        self._raise(self._L.mgcnn_backward(self._h, _ptr(dL_du), _ptr(dL_dw),
+                                           _ptr(dL_df) if dL_df is not None else None))
+        return dL_dw
+
+    def profile_begin(self):
+        return self._raise(self._L.mgcnn_profile_begin(self._h))
+
+    def profile_end(self, max_stats: int = 256):
+        arr = (mgcnn_kernel_stat * max_stats)()
+        cnt = ctypes.c_int(0)
+        self._raise(self._L.mgcnn_profile_end(self._h, arr, max_stats, ctypes.byref(cnt)))
+        return [dict(kind=KERNEL_KINDS.get(arr[i].kind, str(arr[i].kind)), level=arr[i].level,
+                     launches=arr[i].launches, ms_total=arr[i].ms_total,
+                     bytes_per_launch=arr[i].bytes_per_launch) for i in range(min(cnt.value, max_stats))]
 
     @property
     def levels(self) -> int:

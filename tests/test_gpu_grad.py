@@ -1,0 +1,143 @@
+"""GPU reverse pass (through the C-ABI) against the FP64 oracle's reverse mode, which the
+CPU tests pin to central finite differences.  Tolerance: relative 1e-4 on every parameter
+tensor's gradient (f32 forward + f32 adjoint vs f64)."""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import adjoint as oadj
+from oracle import network as onet
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_11093_amd import Solver  # noqa: E402
+from paper_2312_11093_amd.autograd import MGCNNLoss, MGCNNUnrolled  # noqa: E402
+
+GRAD_TOL = 1e-4
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype)
+
+
+def trained_like_weights(seed):
+    """Xavier weights scaled down and with non-zero setup biases, so that K iterations stay
+    bounded and every parameter tensor gets a non-trivial gradient."""
+    w = datagen.xavier_weights(16, seed).astype(np.float64) * 0.5
+    P = onet.unpack_weights(w, 16)
+    rng = np.random.default_rng(seed)
+    for k in range(4):
+        P[f"beta_k{k}"] = 0.2 * rng.standard_normal(16)
+    return onet.pack_weights(P, 16).astype(np.float32)
+
+
+def per_tensor_errors(g, ref):
+    P = onet.unpack_weights(np.asarray(g, np.float64), 16)
+    R = onet.unpack_weights(np.asarray(ref, np.float64), 16)
+    return {k: float(np.linalg.norm(P[k] - R[k]) / max(np.linalg.norm(R[k]), 1e-30)) for k in R}
+
+
+def gpu_loss_grad(w, a, b, f, K, want_df=False):
+    B, n, _ = a.shape
+    S = Solver(w, state="f32", u="f32")
+    S.setup(dev(a), b)
+    df_ = dev(f)
+    u = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
+    S.forward(df_, u, K, record=True)
+    du = torch.empty_like(u)
+    dfl = torch.empty_like(u)
+    L = S.loss(df_, u, du, dfl)
+    g = S.backward(du, dL_df=dfl if want_df else None)
+    torch.cuda.synchronize()
+    out = (L, g.cpu().numpy(), dfl.cpu().numpy() if want_df else None)
+    S.close()
+    return out
+
+
+@pytest.mark.parametrize("n,B,K", [(7, 2, 1), (15, 2, 2), (31, 2, 3)])
+def test_gradient_vs_oracle(n, B, K):
+    say("gradient", n, B, K)
+    a, b, f = datagen.make_batch("mixture127", n, B, seed=11)
+    w = trained_like_weights(1)
+    L, g, _ = gpu_loss_grad(w, a, b, f, K)
+    L_ref, g_ref = oadj.loss_and_grad(w, list(a), list(b), list(f), K)
+    say("  loss", L, L_ref)
+    assert abs(L - L_ref) <= 1e-5 * abs(L_ref)
+    errs = per_tensor_errors(g, g_ref)
+    say("  worst tensor", max(errs.items(), key=lambda kv: kv[1]))
+    assert max(errs.values()) <= GRAD_TOL, errs
+
+
+def test_gradient_wrt_rhs():
+    say("gradient wrt f")
+    n, B, K = 15, 2, 2
+    a, b, f = datagen.make_batch("mixture127", n, B, seed=12)
+    w = trained_like_weights(2)
+    _, _, df = gpu_loss_grad(w, a, b, f, K, want_df=True)
+    _, _, dfs = oadj.loss_and_grad(w, list(a), list(b), list(f), K, want_df=True)
+    for p in range(B):
+        err = np.linalg.norm(df[p] - dfs[p]) / np.linalg.norm(dfs[p])
+        assert err <= GRAD_TOL, (p, err)
+
+
+def test_training_shape_127_k8_sampled():
+    """Training configuration (127 x 127, 8 unrolled iterations, mixture coefficients):
+    gradient of a 4-problem batch vs the oracle, and the 32-problem batch gradient equals
+    the size-weighted mean of its chunk gradients (the loss is a mean over problems)."""
+    say("training shape 127, K=8")
+    n, K = 127, 8
+    a, b, f = datagen.make_batch("mixture127", n, 32, seed=0)
+    w = trained_like_weights(3)
+    L4, g4, _ = gpu_loss_grad(w, a[:4], b[:4], f[:4], K)
+    L_ref, g_ref = oadj.loss_and_grad(w, list(a[:4]), list(b[:4]), list(f[:4]), K)
+    errs = per_tensor_errors(g4, g_ref)
+    say("  loss", L4, L_ref, "worst", max(errs.items(), key=lambda kv: kv[1]))
+    assert abs(L4 - L_ref) <= 1e-5 * abs(L_ref)
+    assert max(errs.values()) <= GRAD_TOL, errs
+    L32, g32, _ = gpu_loss_grad(w, a, b, f, K)
+    parts = [gpu_loss_grad(w, a[i:i + 8], b[i:i + 8], f[i:i + 8], K) for i in range(0, 32, 8)]
+    gmean = sum(p[1] for p in parts) / 4
+    Lmean = sum(p[0] for p in parts) / 4
+    assert abs(L32 - Lmean) <= 1e-6 * abs(L32)
+    assert np.linalg.norm(g32 - gmean) <= 1e-4 * np.linalg.norm(g32)
+
+
+def test_autograd_function():
+    say("autograd")
+    n, B, K = 15, 2, 2
+    a, b, f = datagen.make_batch("mixture127", n, B, seed=13)
+    w0 = trained_like_weights(4)
+    S = Solver(w0, state="f32", u="f32")
+    w = dev(w0).requires_grad_(True)
+    ft = dev(f).requires_grad_(True)
+    u = MGCNNUnrolled.apply(w, S, dev(a), b, ft, K)
+    L = MGCNNLoss.apply(u, S, ft)
+    L.backward()
+    _, g_ref, dfs = oadj.loss_and_grad(w0, list(a), list(b), list(f), K, want_df=True)
+    errs = per_tensor_errors(w.grad.cpu().numpy(), g_ref)
+    assert max(errs.values()) <= GRAD_TOL, errs
+    dfe = np.linalg.norm(ft.grad.cpu().numpy() - np.stack(dfs)) / np.linalg.norm(np.stack(dfs))
+    assert dfe <= GRAD_TOL
+    S.close()
+
+
+def test_backward_without_record_fails():
+    from paper_2312_11093_amd import mgcnn as M
+    S = Solver(trained_like_weights(5), state="f32", u="f32")
+    a, b, f = datagen.make_batch("mixture127", 15, 1, seed=1)
+    S.setup(dev(a), b)
+    with pytest.raises(M.MGCNNError) as e:
+        S.backward(torch.zeros((1, 15, 15), device="cuda"))
+    assert e.value.status == M.E_NORECORD
+    S.close()
