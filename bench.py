@@ -80,6 +80,7 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=4, help="problems solved one by one in the plain-FP32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -99,7 +100,8 @@ def main():
     df = torch.from_numpy(f).cuda()
     u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
 
-    S = Solver(weights, state=args.state, u="f64", check_every=args.check_every)
+    S = Solver(weights, state=args.state, u="f64", check_every=args.check_every,
+               use_graph=not args.no_graph)
 
     def step():
         u.zero_()
@@ -123,8 +125,20 @@ def main():
     mean_iters = float(np.mean(its[-1]))
     value = B / (ms / 1000.0) if converged else 0.0
 
+    # time of one batched V-cycle iteration (residual + network + update), weight independent
+    KI = 10
+    u.zero_()
+    S.forward(df, u, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.forward(df, u, KI)
+    torch.cuda.synchronize()
+    iter_ms = 1000.0 * (time.perf_counter() - t0) / KI
+
     # independent check of the returned solutions (sampled problems, host FP64 residual)
     from oracle import solve as osv
+    u.zero_()
+    step()
     check = [osv.relres(a[p], b[p], f[p], u[p].cpu().numpy()) for p in (0, B - 1)]
 
     # profiled pass: HIP events around every launch of one solve
@@ -183,6 +197,7 @@ def main():
                    "global_batch": B, "n": n, "state": args.state, "u": "f64", "weights": wsrc,
                    "parallelism": "single GPU"},
         "converged": converged, "mean_iters": mean_iters, "max_iters": int(np.max(its[-1])),
+        "ms_per_iteration": round(iter_ms, 3),
         "oracle_relres_sampled": [float(x) for x in check],
         "roofline": roof, "kernel_time_share": kernel_share,
         "plain_fp32_unbatched": plain,

@@ -133,6 +133,9 @@ int mgcnn_set_weights_device(mgcnn_ctx *ctx, const float *weights_dev);
  * z float32 device.  This is the linear preconditioner of Sec. 2.2 for Krylov methods. */
 int mgcnn_apply(mgcnn_ctx *ctx, const float *r, float *z);
 
+/* r = f - A u (float32 device [batch][n][n]; u per opts.u_dtype, arithmetic in f64). */
+int mgcnn_residual(mgcnn_ctx *ctx, const float *f, const void *u, float *r);
+
 /* Relative residuals ||f - A u|| / ||f|| per problem (u per opts.u_dtype); relres_host
  * [batch].  Blocks the host. */
 int mgcnn_residual_norms(mgcnn_ctx *ctx, const float *f, const void *u, double *relres_host);
@@ -148,7 +151,9 @@ int mgcnn_get_setup_tensor(mgcnn_ctx *ctx, int level, float *out);
  * e.g. smoother 3 x 16 x state-bytes per node of its level).  Kinds: */
 enum {
   MGCNN_K_RESIDUAL = 0, MGCNN_K_FINALIZE = 1, MGCNN_K_CONV_IN = 2, MGCNN_K_SMOOTH_DOWN = 3,
-  MGCNN_K_RESTRICT = 4, MGCNN_K_SMOOTH_UP = 5, MGCNN_K_PROLONG = 6, MGCNN_K_OUT_UPDATE = 7
+  MGCNN_K_RESTRICT = 4, MGCNN_K_SMOOTH_UP = 5, MGCNN_K_PROLONG = 6, MGCNN_K_OUT_UPDATE = 7,
+  MGCNN_K_SMOOTH_IN = 8,   /* finest down smoother with the reChannel-in conv folded in */
+  MGCNN_K_SMOOTH_OUT = 9   /* finest up smoother with reChannel-out and the u update folded in */
 };
 typedef struct {
   int kind;                /* MGCNN_K_* */

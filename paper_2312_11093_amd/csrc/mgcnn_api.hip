@@ -76,7 +76,10 @@ int level_count(int n) {
   return L;
 }
 
+void drop_graph(mgcnn_ctx* c);
+
 void free_problem(mgcnn_ctx* c) {
+  drop_graph(c);
   auto fr = [](void* p) { if (p) (void)hipFree(p); };
   fr(c->d_a); fr(c->d_b); fr(c->d_rt); fr(c->d_partial); fr(c->d_nf2);
   fr(c->d_active); fr(c->d_status); fr(c->d_iters); fr(c->d_relres);
@@ -130,6 +133,44 @@ int ensure_problem(mgcnn_ctx* c, int n, int B) {
   c->alloc_n = n;
   c->alloc_B = B;
   c->L = L;
+  c->gen += 1;
+  return MGCNN_OK;
+}
+
+int solve_step(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit);
+
+void drop_graph(mgcnn_ctx* c) {
+  if (c->gcache.exec) (void)hipGraphExecDestroy(c->gcache.exec);
+  if (c->gcache.graph) (void)hipGraphDestroy(c->gcache.graph);
+  c->gcache = mgcnn_ctx::GraphCache{};
+}
+
+// Run `chunk` solver iterations, from a cached hipGraph when enabled.
+int run_chunk(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int chunk, bool graph) {
+  if (!graph) {
+    for (int k = 0; k < chunk; ++k) {
+      int r = solve_step(c, f, u, tol, maxit);
+      if (r) return r;
+    }
+    return MGCNN_OK;
+  }
+  auto& G = c->gcache;
+  const bool hit = G.exec && G.f == f && G.u == u && G.tol == tol && G.maxit == maxit &&
+                   G.chunk == chunk && G.gen == c->gen;
+  if (!hit) {
+    drop_graph(c);
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    int r = MGCNN_OK;
+    for (int k = 0; k < chunk && r == MGCNN_OK; ++k) r = solve_step(c, f, u, tol, maxit);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (r) { if (g) (void)hipGraphDestroy(g); return r; }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); G.exec = nullptr; return hip_fail(c, e, "hipGraphInstantiate"); }
+    G.graph = g; G.f = f; G.u = u; G.tol = tol; G.maxit = maxit; G.chunk = chunk; G.gen = c->gen;
+  }
+  HIP_TRY(c, hipGraphLaunch(G.exec, c->stream));
   return MGCNN_OK;
 }
 
@@ -140,12 +181,13 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active) {
   hipStream_t s = c->stream;
   const double S = (double)c->state_bytes() * C;        // bytes of one 16-channel pixel
   auto nodes = [&](int l) { return (double)c->nl[l] * c->nl[l] * B; };
-  {
-    Prof p(c, MGCNN_K_CONV_IN, 0, nodes(0) * (4.0 + S));
-    launch_conv_in(1, c->d_rt, c->W(c->off.solve_in), c->xin[0], st, c->n, B, active, s);
-  }
   for (int l = 0; l < L; ++l) {
-    {
+    if (l == 0) {
+      // finest level: reChannel-in folded into the down smoother
+      Prof p(c, MGCNN_K_SMOOTH_IN, 0, nodes(0) * (4.0 + 2.0 * S));
+      launch_smooth_in(st, c->d_rt, c->s[0], c->W(c->off.solve_in), c->W(c->off.smooth_down), c->xdn[0],
+                       c->nl[0], B, active, s);
+    } else {
       Prof p(c, MGCNN_K_SMOOTH_DOWN, l, nodes(l) * 3.0 * S);
       launch_conv16(CM_SMOOTH, st, c->xin[l], c->s[l], c->W(c->off.smooth_down), nullptr, c->xdn[l],
                     c->nl[l], B, active, s);
@@ -167,15 +209,16 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active) {
       launch_prolong_add(st, c->xin[l + 1], c->W(c->off.prolong), c->xdn[l], c->nl[l + 1], B,
                          active, s);
     }
-    {
+    if (l == 0) {
+      // finest level: up smoother with reChannel-out and the update of u folded in
+      Prof p(c, MGCNN_K_SMOOTH_OUT, 0, nodes(0) * (2.0 * S + 2.0 * (u_f64 ? 8 : 4)));
+      launch_smooth_out(st, c->xdn[0], c->s[0], c->W(c->off.smooth_up), c->W(c->off.solve_out), u,
+                        u_f64, c->nl[0], B, active, s);
+    } else {
       Prof p(c, MGCNN_K_SMOOTH_UP, l, nodes(l) * 3.0 * S);
       launch_conv16(CM_SMOOTH, st, c->xdn[l], c->s[l], c->W(c->off.smooth_up), nullptr, c->xin[l],
                     c->nl[l], B, active, s);
     }
-  }
-  {
-    Prof p(c, MGCNN_K_OUT_UPDATE, 0, nodes(0) * (S + 2.0 * (u_f64 ? 8 : 4)));
-    launch_out_update(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, active, s);
   }
   LAUNCH_CHECK(c);
   return MGCNN_OK;
@@ -318,6 +361,19 @@ int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, in
   if (!c->ready) return fail(c, MGCNN_E_STATE, "solve: call mgcnn_setup first");
   if (!f || !u) return fail(c, MGCNN_E_ARG, "solve: null f or u");
   if (!(tol > 0.0) || maxit < 0) return fail(c, MGCNN_E_ARG, "solve: need tol > 0 and maxit >= 0");
+  const bool graph = c->opts.use_graph != 0 && !c->prof;
+  hipStream_t user = c->stream;
+  if (graph && user == nullptr) {
+    // stream capture needs a non-null stream: work on a private one ordered after the user's
+    if (!c->cap_stream) {
+      HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    }
+    HIP_TRY(c, hipEventRecord(c->join_ev, user));
+    HIP_TRY(c, hipStreamWaitEvent(c->cap_stream, c->join_ev, 0));
+    c->stream = c->cap_stream;
+  }
+  struct Restore { mgcnn_ctx* c; hipStream_t s; ~Restore() { c->stream = s; } } restore{c, user};
   hipStream_t s = c->stream;
   const int B = c->B;
   // ||f||^2 per problem
@@ -331,10 +387,8 @@ int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, in
   const int max_steps = maxit + 1;
   while (steps < max_steps) {
     const int chunk = std::min(c->opts.check_every, max_steps - steps);
-    for (int k = 0; k < chunk; ++k) {
-      int r = solve_step(c, f, u, tol, maxit);
-      if (r) return r;
-    }
+    int r = run_chunk(c, f, u, tol, maxit, chunk, graph && chunk == c->opts.check_every);
+    if (r) return r;
     steps += chunk;
     HIP_TRY(c, hipMemcpyAsync(act.data(), c->d_active, (size_t)B * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -481,7 +535,10 @@ void mgcnn_destroy(mgcnn_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
   free_train(c);
+  drop_graph(c);
   free_problem(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->join_ev) (void)hipEventDestroy(c->join_ev);
   for (auto e : c->pool) (void)hipEventDestroy(e);
   if (c->d_w) (void)hipFree(c->d_w);
   delete c;

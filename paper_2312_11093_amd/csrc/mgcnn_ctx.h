@@ -40,6 +40,19 @@ struct mgcnn_ctx {
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
 
+  // hipGraph of one block of `check_every` solver iterations (replayed while problems are live)
+  struct GraphCache {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* f = nullptr;
+    void* u = nullptr;
+    double tol = 0.0;
+    int maxit = -1, chunk = 0, gen = -1;
+  } gcache;
+  int gen = 0;                      // bumped whenever problem buffers are reallocated
+  hipStream_t cap_stream = nullptr; // capture stream used when the context stream is the null stream
+  hipEvent_t join_ev = nullptr;
+
   // training: recorded forward (checkpoints of u_0..u_{K-1}) and reverse-pass workspace
   struct Train {
     int alloc_n = 0, alloc_B = 0, alloc_K = 0;

@@ -32,12 +32,14 @@ __device__ __forceinline__ double block_sum_256(double v) {
   return s;
 }
 
-// bf16 (round to nearest even; NaN stays NaN).
+// bf16 conversion: the hardware packed convert (round to nearest even) of gfx950.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu) != 0u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)x);
+}
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
@@ -74,9 +76,7 @@ __device__ __forceinline__ void store16(uint16_t* p, const float* v) {
   for (int k = 0; k < 2; ++k) {
     uint32_t w[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      w[e] = (uint32_t)f32_to_bf16_rne(v[8 * k + 2 * e]) |
-             ((uint32_t)f32_to_bf16_rne(v[8 * k + 2 * e + 1]) << 16);
+    for (int e = 0; e < 4; ++e) w[e] = pack_bf16x2(v[8 * k + 2 * e], v[8 * k + 2 * e + 1]);
     q[k] = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }

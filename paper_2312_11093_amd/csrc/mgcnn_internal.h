@@ -45,6 +45,13 @@ void launch_conv16(ConvMode mode, StateType t, const void* x, const void* s, con
 void launch_prolong_add(StateType t, const void* xc, const float* WT, void* yf, int mc, int B,
                         const int* active, hipStream_t st);
 
+// Finest-level fused kernels: y = x1 + W*(s.x1) with x1 = W_in * rt computed on the fly;
+// and u += W_out * (v + W*(s.v)) without storing the up-smoothed state.
+void launch_smooth_in(StateType t, const float* rt, const void* s, const float* Win, const float* W,
+                      void* y, int m, int B, const int* active, hipStream_t st);
+void launch_smooth_out(StateType t, const void* v, const void* s, const float* W, const float* Wout,
+                       void* u, bool u_f64, int m, int B, const int* active, hipStream_t st);
+
 // u += W_out * x (16 -> 1 same-size conv), u f32 or f64.
 void launch_out_update(StateType t, const void* x, const float* Wout, void* u, bool u_f64,
                        int n, int B, const int* active, hipStream_t st);

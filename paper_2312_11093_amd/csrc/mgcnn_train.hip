@@ -270,6 +270,15 @@ int mgcnn_set_weights_device(mgcnn_ctx* c, const float* w_dev) {
   return MGCNN_OK;
 }
 
+int mgcnn_residual(mgcnn_ctx* c, const float* f, const void* u, float* r) {
+  if (!c) return MGCNN_E_ARG;
+  if (!c->ready) return fail(c, MGCNN_E_STATE, "residual: call mgcnn_setup first");
+  if (!f || !u || !r) return fail(c, MGCNN_E_ARG, "residual: null pointer");
+  launch_residual_plain(c->d_a, c->d_b, f, u, c->u64(), r, c->n, c->B, c->stream);
+  LAUNCH_CHECK(c);
+  return MGCNN_OK;
+}
+
 int mgcnn_loss(mgcnn_ctx* c, const float* f, const float* u, double* loss_host, float* dloss_du,
                float* dloss_df) {
   if (!c) return MGCNN_E_ARG;

@@ -37,7 +37,7 @@ class mgcnn_kernel_stat(ctypes.Structure):
 
 
 KERNEL_KINDS = {0: "residual", 1: "finalize", 2: "conv_in", 3: "smooth_down", 4: "restrict",
-                5: "smooth_up", 6: "prolong", 7: "out_update"}
+                5: "smooth_up", 6: "prolong", 7: "out_update", 8: "smooth_in", 9: "smooth_out"}
 
 EXPORTS = {
     # name: (restype, argtypes)
@@ -58,6 +58,7 @@ EXPORTS = {
                                             ctypes.c_void_p]),
     "mgcnn_get_setup_tensor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "mgcnn_levels": (ctypes.c_int, [ctypes.c_void_p]),
+    "mgcnn_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mgcnn_loss": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p]),
     "mgcnn_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -192,6 +193,16 @@ class Solver:
             z = torch.empty_like(r)
         self._raise(self._L.mgcnn_apply(self._h, _ptr(r), _ptr(z)))
         return z
+
+    def residual(self, f, u, r=None):
+        """r = f - A u (float32 device tensor)."""
+        import torch
+        _check_dev(f, torch.float32, "f")
+        _check_dev(u, self.u_dtype, "u")
+        if r is None:
+            r = torch.empty_like(f)
+        self._raise(self._L.mgcnn_residual(self._h, _ptr(f), _ptr(u), _ptr(r)))
+        return r
 
     def residual_norms(self, f, u):
         import torch

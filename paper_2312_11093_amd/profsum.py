@@ -1,0 +1,31 @@
+"""Summarise a rocprofv3 kernel trace (CSV) per kernel and grid size.
+
+    python -m paper_2312_11093_amd.profsum <run_kernel_trace.csv> [top]
+
+Prints launches, average and total duration per (kernel, grid size); the grid size
+separates the levels of the multigrid hierarchy.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import sys
+
+
+def summarize(path: str, top: int = 25) -> str:
+    rows = list(csv.DictReader(open(path)))
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for r in rows:
+        key = (r["Kernel_Name"].split("(")[0], int(r["Grid_Size_X"]))
+        agg[key][0] += 1
+        agg[key][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    total = sum(v[1] for v in agg.values())
+    out = [f"{'kernel':60s} {'grid_x':>10s} {'launches':>8s} {'avg_us':>10s} {'total_ms':>10s} {'share':>6s}"]
+    for (name, grid), (cnt, us) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        out.append(f"{name[:60]:60s} {grid:10d} {cnt:8d} {us / cnt:10.1f} {us / 1e3:10.2f} {us / total:6.3f}")
+    out.append(f"total kernel time {total / 1e3:.2f} ms over {sum(v[0] for v in agg.values())} launches")
+    return "\n".join(out)
+
+
+if __name__ == "__main__":
+    print(summarize(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 25))
