@@ -58,6 +58,11 @@ enum {
 enum { MGCNN_F32 = 0, MGCNN_BF16 = 1 };
 /* Precision of u, of the residual arithmetic and of the stopping test. */
 enum { MGCNN_U_F32 = 0, MGCNN_U_F64 = 1 };
+/* Outer method of mgcnn_solve. */
+enum {
+  MGCNN_METHOD_STATIONARY = 0,  /* u += B((f - A u)/D), Sec. 2.2 Eq. (1) */
+  MGCNN_METHOD_FGMRES = 1       /* restarted flexible GMRES, B((.)/D) as right preconditioner (Sec. 2.2) */
+};
 
 typedef struct {
   int channels;     /* hidden channels; must be 16 */
@@ -66,9 +71,13 @@ typedef struct {
                        MGCNN_U_F64: u float64, residual in f64 arithmetic */
   int use_graph;    /* 1: capture each block of check_every iterations in a hipGraph */
   int check_every;  /* iterations between host convergence checks in mgcnn_solve (>= 1) */
+  int method;       /* MGCNN_METHOD_STATIONARY or MGCNN_METHOD_FGMRES */
+  int restart;      /* FGMRES restart length m, 1..63 (Krylov vectors are float32; the true
+                       residual is recomputed in f64 at every restart) */
 } mgcnn_opts;
 
-/* Default options: 16 channels, f32 state, f64 u, graphs on, check every 4 iterations. */
+/* Default options: 16 channels, f32 state, f64 u, graphs off, check every 4 iterations,
+ * stationary method, FGMRES restart 30. */
 void mgcnn_default_opts(mgcnn_opts *opts);
 
 /* Number of weights for `channels` hidden channels: 81 C^2 + 58 C. */
@@ -97,6 +106,9 @@ int mgcnn_setup(mgcnn_ctx *ctx, const float *a, const float *b_host, int n, int 
  * Per problem, at iterate k: rho_k = ||f - A u_k||_2 / ||f||_2; stop with OK if rho_k <= tol
  * (iters = k), NOT_CONVERGED if k == maxit, DIVERGED if rho_k is not finite or > 1e10;
  * otherwise apply one V-cycle.  A zero f gives u = 0, iters = 0, OK.
+ * With opts.method = MGCNN_METHOD_FGMRES the same stopping rule is applied to the true
+ * residual at every restart (and iters counts network applications); the Arnoldi estimate
+ * ends a restart cycle early.
  * iters_host [batch], relres_host [batch], status_host [batch] (each may be NULL) receive the
  * per-problem results.  Return: OK if every problem converged, else E_DIVERGED if any
  * diverged, else NOT_CONVERGED.  Blocks the host until the solve has finished. */

@@ -57,7 +57,23 @@ void launch_features(const float* a, const float* b, float* F, int n, int B, hip
 // ------------------------------------------------------------------------------------------
 // residual: r = f - A u ; rt = r / D ; per-workgroup partial sum of r^2 in f64.
 // ------------------------------------------------------------------------------------------
-int residual_tiles(int n) { return ((n + 63) / 64) * ((n + 3) / 4); }
+// Tiles of 256 columns x RES_ROWS rows; each thread walks one column of its tile, keeping the
+// row above, the current row and the row below in registers, so every vertical face
+// coefficient is formed once and every value of a and u comes from HBM once.
+constexpr int RES_ROWS = 8;
+int residual_tiles(int n) { return ((n + 255) / 256) * ((n + RES_ROWS - 1) / RES_ROWS); }
+
+// 1/x to full double precision: hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double rcp_full(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ float rcp_full(float x) { return 1.0f / x; }
+template <typename R>
+__device__ __forceinline__ R harm_fast(R p, R q) { return (R(2) * p * q) * rcp_full(p + q); }
 
 template <typename R, typename UT, bool HAS_U>
 __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__ a,
@@ -71,41 +87,65 @@ __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
   if (active != nullptr && active[b] == 0) return;
-  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
-  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
+  const int j = (tile % tiles_x) * 256 + threadIdx.x;
+  const int i0 = (tile / tiles_x) * RES_ROWS;
+  const size_t base = (size_t)b * n * n;
+  const float* A = a + base;
+  const float* F = f + base;
   double r2 = 0.0;
-  if (i < n && j < n) {
-    const size_t base = (size_t)b * n * n;
-    const size_t c = base + (size_t)i * n + j;
-    R r = (R)f[c];
+  if (j < n) {
     if constexpr (HAS_U) {
-      const float* A = a + base;
-      const size_t ij = (size_t)i * n + j;
-      const R ac = (R)A[ij];
-      const R aE = (j + 1 < n) ? harm<R>(ac, (R)A[ij + 1]) : ac;
-      const R aW = (j > 0) ? harm<R>(ac, (R)A[ij - 1]) : ac;
-      const R aN = (i + 1 < n) ? harm<R>(ac, (R)A[ij + n]) : ac;
-      const R aS = (i > 0) ? harm<R>(ac, (R)A[ij - n]) : ac;
       const UT* U = u + base;
-      const R uc = (R)U[ij];
-      const R uE = (j + 1 < n) ? (R)U[ij + 1] : R(0);
-      const R uW = (j > 0) ? (R)U[ij - 1] : R(0);
-      const R uN = (i + 1 < n) ? (R)U[ij + n] : R(0);
-      const R uS = (i > 0) ? (R)U[ij - n] : R(0);
       const R ih = (R)(n + 1), ih2 = ih * ih;
       const R bx = (R)bvec[2 * b], by = (R)bvec[2 * b + 1];
       const R bxp = bx > R(0) ? bx : R(0), bxm = bx < R(0) ? bx : R(0);
       const R byp = by > R(0) ? by : R(0), bym = by < R(0) ? by : R(0);
-      const R sa = aE + aW + aN + aS;
-      const R Au = (sa * uc - aE * uE - aW * uW - aN * uN - aS * uS) * ih2 +
-                   (bxp * (uc - uW) + bxm * (uE - uc) + byp * (uc - uS) + bym * (uN - uc)) * ih;
-      const R D = sa * ih2 + (fabs(bx) + fabs(by)) * ih;
-      r = r - Au;
-      if (rt != nullptr) rt[c] = (float)(r / D);
+      const R conv_diag = (bxp - bxm + byp - bym) * ih;
+      const bool hasE = j + 1 < n, hasW = j > 0;
+      // rows i0 - 1 (south) and i0 (centre)
+      R ac = (R)A[i0 * n + j];
+      R uc = (R)U[i0 * n + j];
+      R us = (i0 > 0) ? (R)U[(i0 - 1) * n + j] : R(0);
+      R aS = (i0 > 0) ? harm_fast<R>(ac, (R)A[(i0 - 1) * n + j]) : ac;
+      const int dE = hasE ? 1 : 0, dW = hasW ? 1 : 0;       // clamped offsets: branch-free loads
+#pragma unroll 2
+      for (int r = 0; r < RES_ROWS; ++r) {
+        const int i = i0 + r;
+        if (i >= n) break;
+        const int ij = i * n + j;
+        const bool hasN = i + 1 < n;
+        const int dN = hasN ? n : 0;
+        const R an_raw = (R)A[ij + dN], un_raw = (R)U[ij + dN];
+        const R ae_raw = (R)A[ij + dE], aw_raw = (R)A[ij - dW];
+        const R ue_raw = (R)U[ij + dE], uw_raw = (R)U[ij - dW];
+        const R fv = (R)F[ij];
+        const R an = an_raw;
+        const R un = hasN ? un_raw : R(0);
+        const R aN = hasN ? harm_fast<R>(ac, an) : ac;
+        const R aE = hasE ? harm_fast<R>(ac, ae_raw) : ac;
+        const R aW = hasW ? harm_fast<R>(ac, aw_raw) : ac;
+        const R uE = hasE ? ue_raw : R(0);
+        const R uW = hasW ? uw_raw : R(0);
+        const R sa = aE + aW + aN + aS;
+        const R Au = (sa * uc - aE * uE - aW * uW - aN * un - aS * us) * ih2 +
+                     (bxp * (uc - uW) + bxm * (uE - uc) + byp * (uc - us) + bym * (un - uc)) * ih;
+        const R rr = fv - Au;
+        if (rt != nullptr) {
+          const R D = sa * ih2 + conv_diag;
+          rt[base + ij] = (float)(rr * (R)__builtin_amdgcn_rcp((double)D));
+        }
+        r2 += (double)rr * (double)rr;
+        us = uc; uc = un; ac = an; aS = aN;
+      }
     } else {
-      (void)a; (void)bvec; (void)u;
+      (void)a; (void)bvec; (void)u; (void)rt;
+      for (int r = 0; r < RES_ROWS; ++r) {
+        const int i = i0 + r;
+        if (i >= n) break;
+        const double v = (double)F[i * n + j];
+        r2 += v * v;
+      }
     }
-    r2 = (double)r * (double)r;
   }
   r2 = block_sum_256(r2);
   if (threadIdx.x == 0) partial[(size_t)b * tiles_per_prob + tile] = r2;
@@ -113,7 +153,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__
 
 void launch_residual(const float* a, const float* b, const float* f, const void* u, bool u_f64,
                      float* rt, double* partial, int n, int B, const int* active, hipStream_t st) {
-  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  const int tx = (n + 255) / 256, ty = (n + RES_ROWS - 1) / RES_ROWS;
   const dim3 grid(tx * ty * B), blk(256);
   if (u == nullptr) {
     hipLaunchKernelGGL((residual_kernel<double, double, false>), grid, blk, 0, st, a, b, f,

@@ -209,16 +209,15 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active) {
       launch_prolong_add(st, c->xin[l + 1], c->W(c->off.prolong), c->xdn[l], c->nl[l + 1], B,
                          active, s);
     }
-    if (l == 0) {
-      // finest level: up smoother with reChannel-out and the update of u folded in
-      Prof p(c, MGCNN_K_SMOOTH_OUT, 0, nodes(0) * (2.0 * S + 2.0 * (u_f64 ? 8 : 4)));
-      launch_smooth_out(st, c->xdn[0], c->s[0], c->W(c->off.smooth_up), c->W(c->off.solve_out), u,
-                        u_f64, c->nl[0], B, active, s);
-    } else {
+    {
       Prof p(c, MGCNN_K_SMOOTH_UP, l, nodes(l) * 3.0 * S);
       launch_conv16(CM_SMOOTH, st, c->xdn[l], c->s[l], c->W(c->off.smooth_up), nullptr, c->xin[l],
                     c->nl[l], B, active, s);
     }
+  }
+  {
+    Prof p(c, MGCNN_K_OUT_UPDATE, 0, nodes(0) * (S + 2.0 * (u_f64 ? 8 : 4)));
+    launch_out_update(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, active, s);
   }
   LAUNCH_CHECK(c);
   return MGCNN_OK;
@@ -254,6 +253,8 @@ void mgcnn_default_opts(mgcnn_opts* o) {
   o->u_dtype = MGCNN_U_F64;
   o->use_graph = 0;
   o->check_every = 4;
+  o->method = MGCNN_METHOD_STATIONARY;
+  o->restart = 30;
 }
 
 size_t mgcnn_num_weights(int channels) {
@@ -271,6 +272,8 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.state_dtype != MGCNN_F32 && o.state_dtype != MGCNN_BF16) return MGCNN_E_ARG;
   if (o.u_dtype != MGCNN_U_F32 && o.u_dtype != MGCNN_U_F64) return MGCNN_E_ARG;
   if (o.check_every < 1) return MGCNN_E_ARG;
+  if (o.method != MGCNN_METHOD_STATIONARY && o.method != MGCNN_METHOD_FGMRES) return MGCNN_E_ARG;
+  if (o.method == MGCNN_METHOD_FGMRES && (o.restart < 1 || o.restart > 63)) return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
   if (!c) return MGCNN_E_NOMEM;
   c->opts = o;
@@ -361,6 +364,8 @@ int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, in
   if (!c->ready) return fail(c, MGCNN_E_STATE, "solve: call mgcnn_setup first");
   if (!f || !u) return fail(c, MGCNN_E_ARG, "solve: null f or u");
   if (!(tol > 0.0) || maxit < 0) return fail(c, MGCNN_E_ARG, "solve: need tol > 0 and maxit >= 0");
+  if (c->opts.method == MGCNN_METHOD_FGMRES)
+    return fgmres_solve(c, f, u, tol, maxit, iters_host, relres_host, status_host);
   const bool graph = c->opts.use_graph != 0 && !c->prof;
   hipStream_t user = c->stream;
   if (graph && user == nullptr) {
@@ -535,6 +540,7 @@ void mgcnn_destroy(mgcnn_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
   free_train(c);
+  free_krylov(c);
   drop_graph(c);
   free_problem(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

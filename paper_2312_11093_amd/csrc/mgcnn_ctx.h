@@ -53,6 +53,17 @@ struct mgcnn_ctx {
   hipStream_t cap_stream = nullptr; // capture stream used when the context stream is the null stream
   hipEvent_t join_ev = nullptr;
 
+  // Krylov (FGMRES) workspace
+  struct Krylov {
+    int n = 0, B = 0, m = 0;
+    float* V = nullptr;       // (m+1) Arnoldi vectors [B][n][n]
+    float* Z = nullptr;       // m preconditioned vectors
+    double* partial = nullptr;
+    double* h = nullptr;      // per-problem scalars exchanged with the host
+    int* act = nullptr;       // problems extending their basis
+    int* cyc = nullptr;       // problems live in the current restart cycle
+  } kr;
+
   // training: recorded forward (checkpoints of u_0..u_{K-1}) and reverse-pass workspace
   struct Train {
     int alloc_n = 0, alloc_B = 0, alloc_K = 0;
@@ -88,6 +99,9 @@ hipEvent_t pool_event(mgcnn_ctx* c);
 int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active);
 int forward_record(mgcnn_ctx* c, const float* f, float* u, int K);
 void free_train(mgcnn_ctx* c);
+void free_krylov(mgcnn_ctx* c);
+int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int* iters_host,
+                 double* relres_host, int* status_host);
 
 #define HIP_TRY(ctx, call)                                            \
   do {                                                                \

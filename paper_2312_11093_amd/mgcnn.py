@@ -28,7 +28,8 @@ _lib = None
 
 class mgcnn_opts(ctypes.Structure):
     _fields_ = [("channels", ctypes.c_int), ("state_dtype", ctypes.c_int), ("u_dtype", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("method", ctypes.c_int), ("restart", ctypes.c_int)]
 
 
 class mgcnn_kernel_stat(ctypes.Structure):
@@ -111,7 +112,7 @@ class Solver:
     """One library context (weights + workspace for one problem set)."""
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", use_graph: bool = False,
-                 check_every: int = 4, stream=None):
+                 check_every: int = 4, stream=None, method: str = "stationary", restart: int = 30):
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -121,6 +122,8 @@ class Solver:
         o.u_dtype = {"f32": U_F32, "f64": U_F64}[u]
         o.use_graph = int(bool(use_graph))
         o.check_every = int(check_every)
+        o.method = {"stationary": 0, "fgmres": 1}[method]
+        o.restart = int(restart)
         self.opts = o
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())

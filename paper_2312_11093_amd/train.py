@@ -36,13 +36,18 @@ DEFAULT_SCHEDULE = [(31, 16, 2, 4000, 0.5, 12), (63, 8, 2, 4000, 0.5, 16),
                     (127, 4, 2, 4000, 0.6, 20), (255, 2, 2, 3000, 0.6, 24)]
 
 
-def coefficient_pool(n: int, count: int, seed: int):
-    """Float32 coefficient fields (count, n, n) from the four families, equal shares."""
+FAMILIES = ("blocks", "grf", "checker", "inclusions")
+
+
+def coefficient_pool(n: int, count: int, seed: int, mix=(1, 1, 1, 1)):
+    """Float32 coefficient fields (count, n, n) from the four families (blocks, GRF,
+    checkerboard, inclusions) in the proportions `mix`."""
     import datagen
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 9001, n])))
     out = np.empty((count, n, n), np.float32)
+    kinds = np.repeat(np.arange(4), np.asarray(mix, dtype=int))
     for i in range(count):
-        kind = i % 4
+        kind = int(kinds[i % len(kinds)])
         if kind == 0:
             a = datagen.blocks_lognormal(n, rng)
         elif kind == 1:
@@ -63,7 +68,7 @@ def random_velocity(rng, B):
 
 def train(out: str, schedule=None, lr: float = 3e-3, decay_every: int = 2000, gamma: float = 0.8,
           seed: int = 0, resume: str | None = None, minutes: float = 1e9, pool: int = 256,
-          log: str | None = None, init: str | None = None, clip: float = 0.0):
+          log: str | None = None, init: str | None = None, clip: float = 0.0, mix=(1, 1, 1, 1)):
     import torch
 
     import datagen
@@ -93,7 +98,7 @@ def train(out: str, schedule=None, lr: float = 3e-3, decay_every: int = 2000, ga
     while state["stage"] < len(schedule):
         entry = tuple(schedule[state["stage"]]) + (0.0, 0)
         n, B, K, steps, slow_frac, kpre_max = entry[:6]
-        a_pool = torch.from_numpy(coefficient_pool(n, pool, seed + state["stage"])).cuda()
+        a_pool = torch.from_numpy(coefficient_pool(n, pool, seed + state["stage"], mix)).cuda()
         u = torch.zeros((B, n, n), device="cuda")
         du = torch.empty_like(u)
         ema = None
@@ -182,11 +187,12 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--pool", type=int, default=256)
     ap.add_argument("--log", default=None)
-    ap.add_argument("--schedule", default=None, help="json list of [n, batch, K, steps]")
+    ap.add_argument("--schedule", default=None, help="json list of [n, batch, K, steps, slow_fraction, max_pre]")
+    ap.add_argument("--mix", default="1,1,1,1", help="proportions of blocks, grf, checkerboard, inclusions")
     args = ap.parse_args()
     schedule = [tuple(x) for x in json.loads(args.schedule)] if args.schedule else None
     train(args.out, schedule, args.lr, args.decay_every, args.gamma, args.seed, args.resume,
-          args.minutes, args.pool, args.log, args.init)
+          args.minutes, args.pool, args.log, args.init, 0.0, tuple(int(x) for x in args.mix.split(",")))
 
 
 if __name__ == "__main__":

@@ -1,0 +1,95 @@
+"""GPU: the stationary solve with the hand-set cycle weights against the FP64 oracle, and the
+batched FGMRES solve (the network as right preconditioner, Sec. 2.2) checked by the property
+that defines a solution: the oracle recomputes ||f - A u|| / ||f|| in FP64 and it must be at
+most tol, for every problem of the batch; zero right-hand sides give u = 0."""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import solve as osv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_11093_amd import Solver  # noqa: E402
+from paper_2312_11093_amd import mgcnn as M  # noqa: E402
+from paper_2312_11093_amd.handbuilt import vcycle_weights  # noqa: E402
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype)
+
+
+def test_stationary_handbuilt_matches_oracle():
+    """A convergent learned-layout cycle (hand-set weights): same iteration count as the
+    oracle's stationary iteration (within one check), solution within 1e-6 of the oracle's."""
+    say("stationary hand-set cycle grf31")
+    n, B = 31, 3
+    a, b, f = datagen.make_batch("grf31", n, B, seed=11)
+    w = vcycle_weights()
+    S = Solver(w, state="f32", u="f64", check_every=1)
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(f), u, 1e-8, 200)
+    assert st == M.OK, (it, rr, ps)
+    for p in range(B):
+        ou, ost, oit, orho, _ = osv.Solver(w, a[p], b[p]).solve(f[p], 1e-8, 200)
+        assert ost == osv.OK
+        assert abs(int(it[p]) - oit) <= 1, (p, it[p], oit)
+        up = u[p].cpu().numpy()
+        assert np.linalg.norm(up - ou) <= 1e-6 * np.linalg.norm(ou)
+        assert osv.relres(a[p], b[p], f[p], up) <= 1e-8
+    S.close()
+
+
+@pytest.mark.parametrize("workload,n,B,state,restart", [
+    ("grf31", 31, 3, "f32", 30),
+    ("mixture127", 127, 4, "bf16", 20),
+    ("blocks1023", 127, 4, "bf16", 30),
+    ("blocks1023", 255, 2, "f32", 8),
+])
+def test_fgmres_converges_to_tol(workload, n, B, state, restart):
+    say("fgmres", workload, n, B, state, restart)
+    a, b, f = datagen.make_batch(workload, n, B, seed=12)
+    f[B - 1] = 0.0                                   # a zero right-hand side in the batch
+    S = Solver(vcycle_weights(), state=state, u="f64", method="fgmres", restart=restart)
+    S.setup(dev(a), b)
+    u = torch.full((B, n, n), 0.5, dtype=torch.float64, device="cuda")
+    tol = 1e-8
+    st, it, rr, ps = S.solve(dev(f), u, tol, 2000)
+    say("  iters", list(it), "relres", list(rr))
+    assert st == M.OK and (ps == 0).all()
+    assert int(it[B - 1]) == 0 and (u[B - 1] == 0).all()
+    for p in range(B - 1):
+        rho = osv.relres(a[p], b[p], f[p], u[p].cpu().numpy())
+        assert rho <= tol * (1 + 1e-6), (p, rho)
+        assert abs(rho - rr[p]) <= 1e-3 * tol + 1e-6 * rho, (p, rho, rr[p])
+    S.close()
+
+
+def test_fgmres_maxit_and_args():
+    say("fgmres maxit / args")
+    n, B = 63, 2
+    a, b, f = datagen.make_batch("blocks1023", n, B, seed=13)
+    S = Solver(vcycle_weights(), state="f32", u="f64", method="fgmres", restart=4)
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(f), u, 1e-12, 6)
+    assert st == M.NOT_CONVERGED and (ps == M.NOT_CONVERGED).all()
+    assert (it <= 6).all() and (it >= 1).all()
+    for p in range(B):   # the reported residual is that of the returned u
+        rho = osv.relres(a[p], b[p], f[p], u[p].cpu().numpy())
+        assert abs(rho - rr[p]) <= 1e-5 * rho
+    S.close()
+    with pytest.raises(M.MGCNNError):
+        Solver(vcycle_weights(), method="fgmres", restart=64)
