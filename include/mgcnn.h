@@ -165,7 +165,12 @@ enum {
   MGCNN_K_RESIDUAL = 0, MGCNN_K_FINALIZE = 1, MGCNN_K_CONV_IN = 2, MGCNN_K_SMOOTH_DOWN = 3,
   MGCNN_K_RESTRICT = 4, MGCNN_K_SMOOTH_UP = 5, MGCNN_K_PROLONG = 6, MGCNN_K_OUT_UPDATE = 7,
   MGCNN_K_SMOOTH_IN = 8,   /* finest down smoother with the reChannel-in conv folded in */
-  MGCNN_K_SMOOTH_OUT = 9   /* finest up smoother with reChannel-out and the u update folded in */
+  MGCNN_K_SMOOTH_OUT = 9,  /* finest up smoother with reChannel-out and the u update folded in */
+  /* FGMRES vector kernels; for DOTS, ORTH and COMBINE `level` holds the number of basis
+     vectors the launch reads */
+  MGCNN_K_KRYLOV_APPLY_A = 10, MGCNN_K_KRYLOV_DOTS = 11, MGCNN_K_KRYLOV_ORTH = 12,
+  MGCNN_K_KRYLOV_SCALE = 13, MGCNN_K_KRYLOV_COMBINE = 14, MGCNN_K_KRYLOV_RESIDUAL = 15,
+  MGCNN_K_SCALE_BY_DIAG = 16, MGCNN_K_ZERO = 17
 };
 typedef struct {
   int kind;                /* MGCNN_K_* */

@@ -63,6 +63,7 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
   const size_t nn = (size_t)n * n * B;
   const size_t vs = nn;                       // stride between basis vectors (floats)
   const bool u64 = c->u64();
+  const double nodes = (double)nn;           // all problems; retired ones are skipped by the kernels
   // ||f||^2
   launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, n, B, nullptr, s);
   launch_sum_partials(c->d_partial, c->tiles, c->d_nf2, B, s);
@@ -83,9 +84,15 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
   auto Hij = [&](int b, int i, int j) -> double& { return H[((size_t)b * (LD + 1) + i) * LD + j]; };
   while (true) {
     // true residual of every live problem, its norm, and the stopping rule
-    launch_residual_plain(c->d_a, c->d_b, f, u, u64, K.V, n, B, s);
+    {
+      Prof p(c, MGCNN_K_KRYLOV_RESIDUAL, 0, nodes * (12.0 + (u64 ? 8 : 4)));
+      launch_residual_plain(c->d_a, c->d_b, f, u, u64, K.V, n, B, s);
+    }
     HIP_TRY(c, hipMemcpyAsync(K.act, act.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
-    launch_dots(K.V, K.V, vs, 1, n, B, K.partial, K.h, K.act, s);
+    {
+      Prof p(c, MGCNN_K_KRYLOV_DOTS, 1, nodes * 4.0);
+      launch_dots(K.V, K.V, vs, 1, n, B, K.partial, K.h, K.act, s);
+    }
     LAUNCH_CHECK(c);
     HIP_TRY(c, hipMemcpyAsync(hbuf.data(), K.h, (size_t)B * LD * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -114,27 +121,48 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
     HIP_TRY(c, hipMemcpyAsync(K.cyc, cyc.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(K.act, live.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(K.h, sc.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
-    launch_scale(K.V, n, B, K.h, K.act, s);
+    {
+      Prof p(c, MGCNN_K_KRYLOV_SCALE, 0, nodes * 8.0);
+      launch_scale(K.V, n, B, K.h, K.act, s);
+    }
     for (int j = 0; j < m; ++j) {
       float* Vj = K.V + (size_t)j * vs;
       float* Vn = K.V + (size_t)(j + 1) * vs;
       float* Zj = K.Z + (size_t)j * vs;
       // z_j = B(v_j / D)
-      launch_scale_by_diag(c->d_a, c->d_b, Vj, c->d_rt, n, B, s);
-      launch_zero(Zj, nn * 4, s);
+      {
+        Prof p(c, MGCNN_K_SCALE_BY_DIAG, 0, nodes * 12.0);
+        launch_scale_by_diag(c->d_a, c->d_b, Vj, c->d_rt, n, B, s);
+      }
+      {
+        Prof p(c, MGCNN_K_ZERO, 0, nodes * 4.0);
+        launch_zero(Zj, nn * 4, s);
+      }
       if ((r = vcycle(c, Zj, false, K.act))) return r;
       // w = A z_j, orthogonalised twice against v_0..v_j
-      launch_apply_A(c->d_a, c->d_b, Zj, Vn, n, B, K.act, s);
+      {
+        Prof p(c, MGCNN_K_KRYLOV_APPLY_A, 0, nodes * 12.0);
+        launch_apply_A(c->d_a, c->d_b, Zj, Vn, n, B, K.act, s);
+      }
       for (int pass = 0; pass < 2; ++pass) {
-        launch_dots(Vn, K.V, vs, j + 1, n, B, K.partial, K.h, K.act, s);
+        {
+          Prof p(c, MGCNN_K_KRYLOV_DOTS, j + 1, nodes * 4.0 * (j + 2));
+          launch_dots(Vn, K.V, vs, j + 1, n, B, K.partial, K.h, K.act, s);
+        }
         HIP_TRY(c, hipMemcpyAsync(hbuf.data(), K.h, (size_t)B * LD * 8, hipMemcpyDeviceToHost, s));
-        launch_orth_update(Vn, K.V, vs, j + 1, n, B, K.h, K.act, s);
+        {
+          Prof p(c, MGCNN_K_KRYLOV_ORTH, j + 1, nodes * 4.0 * (j + 3));
+          launch_orth_update(Vn, K.V, vs, j + 1, n, B, K.h, K.act, s);
+        }
         HIP_TRY(c, hipStreamSynchronize(s));
         for (int b = 0; b < B; ++b)
           if (live[b])
             for (int i = 0; i <= j; ++i) Hij(b, i, j) += hbuf[(size_t)b * LD + i];
       }
-      launch_dots(Vn, Vn, vs, 1, n, B, K.partial, K.h, K.act, s);
+      {
+        Prof p(c, MGCNN_K_KRYLOV_DOTS, 1, nodes * 4.0);
+        launch_dots(Vn, Vn, vs, 1, n, B, K.partial, K.h, K.act, s);
+      }
       LAUNCH_CHECK(c);
       HIP_TRY(c, hipMemcpyAsync(hbuf.data(), K.h, (size_t)B * LD * 8, hipMemcpyDeviceToHost, s));
       HIP_TRY(c, hipStreamSynchronize(s));
@@ -167,7 +195,10 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
       }
       if (!more || j == m - 1) break;
       HIP_TRY(c, hipMemcpyAsync(K.h, sc.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
-      launch_scale(Vn, n, B, K.h, K.act, s);
+      {
+        Prof p(c, MGCNN_K_KRYLOV_SCALE, 0, nodes * 8.0);
+        launch_scale(Vn, n, B, K.h, K.act, s);
+      }
       HIP_TRY(c, hipMemcpyAsync(K.act, live.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
     }
     // y = R^-1 g (upper triangular, k_b x k_b) and u += Z y
@@ -184,7 +215,10 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
     int kmax = 0;
     for (int b = 0; b < B; ++b) if (cyc[b]) kmax = std::max(kmax, kb[b]);
     HIP_TRY(c, hipMemcpyAsync(K.h, ybuf.data(), (size_t)B * LD * 8, hipMemcpyHostToDevice, s));
-    launch_combine(u, u64, K.Z, vs, kmax, n, B, K.h, K.cyc, s);
+    {
+      Prof p(c, MGCNN_K_KRYLOV_COMBINE, kmax, nodes * (4.0 * kmax + 2.0 * (u64 ? 8 : 4)));
+      launch_combine(u, u64, K.Z, vs, kmax, n, B, K.h, K.cyc, s);
+    }
     LAUNCH_CHECK(c);
   }
   bool diverged = false, notconv = false;

@@ -38,7 +38,9 @@ class mgcnn_kernel_stat(ctypes.Structure):
 
 
 KERNEL_KINDS = {0: "residual", 1: "finalize", 2: "conv_in", 3: "smooth_down", 4: "restrict",
-                5: "smooth_up", 6: "prolong", 7: "out_update", 8: "smooth_in", 9: "smooth_out"}
+                5: "smooth_up", 6: "prolong", 7: "out_update", 8: "smooth_in", 9: "smooth_out",
+                10: "krylov_apply_A", 11: "krylov_dots", 12: "krylov_orth", 13: "krylov_scale",
+                14: "krylov_combine", 15: "krylov_residual", 16: "scale_by_diag", 17: "zero"}
 
 EXPORTS = {
     # name: (restype, argtypes)
