@@ -1,19 +1,40 @@
 // Batched vector kernels for the Krylov (FGMRES) solve with the MGCNN network as a fixed
-// right preconditioner (Sec. 2.2: the linear network serves as the preconditioner of a
-// Krylov method).  Every kernel handles a batch of independent problems [B][n][n]; problems
-// whose flag in `active` is zero are skipped.
+// right preconditioner (Sec. 2.2: the network is linear in its input, so it can precondition
+// a Krylov method).  Every kernel handles a batch of independent problems; problems whose flag
+// in `active` is zero are skipped.
+//
+// Layout: Arnoldi vectors are [B][vpad] float32 with vpad = n*n rounded up to 512; the
+// padding is zero from allocation on and no kernel writes it with anything but zero, so the
+// Gram-Schmidt kernels run without bounds checks.  Preconditioned vectors Z and the rhs / u
+// keep the [B][n][n] layout of the rest of the library.
 #include "mgcnn_device.h"
 #include "mgcnn_internal.h"
 #include "mgcnn_krylov.h"
 
 namespace mg {
 
-// y = A x (divergence form, harmonic faces, upwind convection), f64 arithmetic, f32 in/out.
-__global__ __launch_bounds__(256) void apply_A_kernel(const float* __restrict__ a,
-                                                      const float* __restrict__ bvec,
-                                                      const float* __restrict__ x,
-                                                      float* __restrict__ y, int n, int tiles_x,
-                                                      int tiles_per_prob, const int* __restrict__ active) {
+constexpr int KR_LD = KRYLOV_LD;
+constexpr int KG_THREADS = 256;
+constexpr int KG_ELEMS = 2 * KG_THREADS;    // elements per group (two per thread)
+constexpr int KG_ITERS = 1;                 // groups per workgroup (more adds register pressure)
+
+size_t krylov_vpad(int n) {
+  const size_t nn = (size_t)n * n, q = (size_t)KG_ELEMS * KG_ITERS;
+  return (nn + q - 1) / q * q;
+}
+int krylov_blocks(int n) { return (int)(krylov_vpad(n) / ((size_t)KG_ELEMS * KG_ITERS)); }
+
+// ---- stencil: y = A x, or y = f - A u ------------------------------------------------------
+// Divergence-form 5-point diffusion with harmonic face means plus first-order upwind
+// convection, f64 arithmetic; y is written with per-problem stride ystride.
+template <typename UT, bool RESIDUAL>
+__global__ __launch_bounds__(256) void kstencil_kernel(const float* __restrict__ a,
+                                                       const float* __restrict__ bvec,
+                                                       const float* __restrict__ f,
+                                                       const UT* __restrict__ x,
+                                                       float* __restrict__ y, size_t ystride, int n,
+                                                       int tiles_x, int tiles_per_prob,
+                                                       const int* __restrict__ active) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
   if (active != nullptr && active[b] == 0) return;
@@ -22,7 +43,7 @@ __global__ __launch_bounds__(256) void apply_A_kernel(const float* __restrict__ 
   if (i >= n || j >= n) return;
   const size_t base = (size_t)b * n * n;
   const float* A = a + base;
-  const float* X = x + base;
+  const UT* X = x + base;
   const int ij = i * n + j;
   auto H = [](double p, double q) { return 2.0 * p * q / (p + q); };
   const double ac = A[ij];
@@ -41,108 +62,262 @@ __global__ __launch_bounds__(256) void apply_A_kernel(const float* __restrict__ 
   const double byp = by > 0 ? by : 0, bym = by < 0 ? by : 0;
   const double v = ((aE + aW + aN + aS) * xc - aE * xE - aW * xW - aN * xN - aS * xS) * ih2 +
                    (bxp * (xc - xW) + bxm * (xE - xc) + byp * (xc - xS) + bym * (xN - xc)) * ih;
-  y[base + ij] = (float)v;
+  y[(size_t)b * ystride + ij] = RESIDUAL ? (float)((double)f[base + ij] - v) : (float)v;
 }
 
-void launch_apply_A(const float* a, const float* b, const float* x, float* y, int n, int B,
-                    const int* active, hipStream_t st) {
+void launch_apply_A(const float* a, const float* b, const float* x, float* y, size_t ystride, int n,
+                    int B, const int* active, hipStream_t st) {
   const int tx = (n + 63) / 64, ty = (n + 3) / 4;
-  hipLaunchKernelGGL(apply_A_kernel, dim3(tx * ty * B), dim3(256), 0, st, a, b, x, y, n, tx, tx * ty,
-                     active);
+  hipLaunchKernelGGL((kstencil_kernel<float, false>), dim3(tx * ty * B), dim3(256), 0, st, a, b,
+                     (const float*)nullptr, x, y, ystride, n, tx, tx * ty, active);
 }
 
-// partial[b][blk][i] = sum over the block's elements of w[b][k] * V_i[b][k], i < cnt.
-// Each block covers KR_CHUNK consecutive elements of one problem.
-constexpr int KR_CHUNK = 8192;
-constexpr int KR_MAXV = 64;
+void launch_krylov_residual(const float* a, const float* b, const float* f, const void* u, bool u_f64,
+                            float* r, size_t rstride, int n, int B, const int* active, hipStream_t st) {
+  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  if (u_f64)
+    hipLaunchKernelGGL((kstencil_kernel<double, true>), dim3(tx * ty * B), dim3(256), 0, st, a, b, f,
+                       (const double*)u, r, rstride, n, tx, tx * ty, active);
+  else
+    hipLaunchKernelGGL((kstencil_kernel<float, true>), dim3(tx * ty * B), dim3(256), 0, st, a, b, f,
+                       (const float*)u, r, rstride, n, tx, tx * ty, active);
+}
 
-int krylov_blocks(int n) { return (int)(((size_t)n * n + KR_CHUNK - 1) / KR_CHUNK); }
+// ---- Gram-Schmidt passes -----------------------------------------------------------------------
+// c ? y : x on values, written as a bit blend so that the compiler cannot turn it into a
+// select of addresses (which would keep register arrays out of registers).
+__device__ __forceinline__ float blend(bool c, float x, float y) {
+  const unsigned m = 0u - (unsigned)c;
+  return __uint_as_float((__float_as_uint(x) & ~m) | (__float_as_uint(y) & m));
+}
 
-__global__ __launch_bounds__(256) void dots_kernel(const float* __restrict__ w,
-                                                   const float* __restrict__ V, size_t vstride,
-                                                   int cnt, size_t nn, int blocks,
-                                                   double* __restrict__ partial,
-                                                   const int* __restrict__ active) {
+// Reduce-scatter over the 64 lanes of a wave: on entry every lane holds S partial values (S a
+// power of two <= 64); on exit the lanes whose low 6 - log2(S) bits are clear hold in a[0] the
+// wave total of slot (lane >> (6 - log2(S))).  S - 1 + 6 - log2(S) shuffles instead of 6 S.
+template <int S>
+__device__ __forceinline__ void wave_reduce_scatter(float (&a)[S]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int step = S / 2, bit = 32; step >= 1; step >>= 1, bit >>= 1) {
+    const bool hi = (lane & bit) != 0;
+#pragma unroll
+    for (int k = 0; k < step; ++k) {
+      const float lo_v = a[k], hi_v = a[k + step];
+      const float keep = blend(hi, lo_v, hi_v);
+      const float send = blend(hi, hi_v, lo_v);
+      a[k] = keep + __shfl_xor(send, bit, 64);
+    }
+  }
+#pragma unroll
+  for (int b2 = 32 / S; b2 >= 1; b2 >>= 1) a[0] += __shfl_xor(a[0], b2, 64);
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+template <int S>
+__device__ __forceinline__ int slot_of_lane(int lane) {
+  return lane >> (6 - __builtin_ctz((unsigned)S));
+}
+
+template <int N>
+struct Pow2Ceil { static constexpr int value = 2 * Pow2Ceil<(N + 1) / 2>::value; };
+template <>
+struct Pow2Ceil<1> { static constexpr int value = 1; };
+
+enum KgMode : int { KG_DOTS = 0, KG_ORTH_DOTS = 1, KG_ORTH_NORM = 2 };
+
+// One pass over w and the basis V_0..V_{cnt-1} of every live problem; each workgroup covers
+// KG_ITERS groups of 512 elements of one problem:
+//   KG_DOTS:      partial <- V_i . w (slots i < cnt) and w . w (slot cnt)
+//   KG_ORTH_DOTS: w <- w - sum_i h_i V_i, then partial <- V_i . w (the group's basis values stay
+//                 in registers between the two uses)
+//   KG_ORTH_NORM: w <- w - sum_i h_i V_i, then partial <- w . w (slot 0)
+// Per-thread products are float32 over the workgroup's 2 * KG_ITERS elements per thread, wave
+// sums float32, workgroup and grid sums f64 in a fixed order.  partial layout: [b][slot][block].
+template <int MODE, int MAXV>
+__global__ __launch_bounds__(KG_THREADS) void kgs_kernel(float* __restrict__ w,
+                                                         const float* __restrict__ V, size_t vstride,
+                                                         size_t vpad, int cnt, int blocks,
+                                                         const double* __restrict__ h,
+                                                         double* __restrict__ partial,
+                                                         const int* __restrict__ active) {
+  constexpr int S = (MODE == KG_ORTH_NORM) ? 1 : Pow2Ceil<MAXV>::value;
+  __shared__ double red[4][S];
+  __shared__ double redn[4];
+  __shared__ double hs[MAXV];
   const int b = blockIdx.x / blocks, blk = blockIdx.x % blocks;
   if (active != nullptr && active[b] == 0) return;
-  const size_t k0 = (size_t)blk * KR_CHUNK;
-  const size_t k1 = (k0 + KR_CHUNK < nn) ? k0 + KR_CHUNK : nn;
-  const float* W = w + (size_t)b * nn;
-  for (int i = 0; i < cnt; ++i) {
-    const float* Vi = V + (size_t)i * vstride + (size_t)b * nn;
-    double s = 0.0;
-    for (size_t k = k0 + threadIdx.x; k < k1; k += 256) s += (double)W[k] * (double)Vi[k];
-    s = block_sum_256(s);
-    if (threadIdx.x == 0) partial[((size_t)b * blocks + blk) * KR_MAXV + i] = s;
+  if (MODE != KG_DOTS) {
+    if ((int)threadIdx.x < MAXV)
+      hs[threadIdx.x] = (int)threadIdx.x < cnt ? h[(size_t)b * KR_LD + threadIdx.x] : 0.0;
+    __syncthreads();
   }
+  float acc[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) acc[i] = 0.f;
+  float nrm = 0.f;
+#pragma unroll 1
+  for (int it = 0; it < KG_ITERS; ++it) {
+    const size_t e = (size_t)b * vpad + ((size_t)blk * KG_ITERS + it) * KG_ELEMS + 2 * threadIdx.x;
+    const float2 w2 = *reinterpret_cast<const float2*>(w + e);
+    // all MAXV loads are issued unconditionally (slots past cnt re-read V_0, a cache hit) so
+    // that none of them waits behind a branch; those slots are zeroed afterwards
+    float2 v[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      v[i] = *reinterpret_cast<const float2*>(V + (size_t)(i < cnt ? i : 0) * vstride + e);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      v[i].x = blend(i >= cnt, v[i].x, 0.f);
+      v[i].y = blend(i >= cnt, v[i].y, 0.f);
+    }
+    if (MODE == KG_DOTS) {
+#pragma unroll
+      for (int i = 0; i < MAXV; ++i) acc[i] = fmaf(v[i].x, w2.x, fmaf(v[i].y, w2.y, acc[i]));
+      nrm = fmaf(w2.x, w2.x, fmaf(w2.y, w2.y, nrm));
+    } else {
+      double x0 = w2.x, x1 = w2.y;
+#pragma unroll
+      for (int i = 0; i < MAXV; ++i) {
+        const double hi = hs[i];
+        x0 -= hi * (double)v[i].x;
+        x1 -= hi * (double)v[i].y;
+      }
+      const float2 xf = make_float2((float)x0, (float)x1);
+      *reinterpret_cast<float2*>(w + e) = xf;
+      if (MODE == KG_ORTH_DOTS) {
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i) acc[i] = fmaf(v[i].x, xf.x, fmaf(v[i].y, xf.y, acc[i]));
+      } else {
+        nrm = fmaf(xf.x, xf.x, fmaf(xf.y, xf.y, nrm));
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (MODE != KG_ORTH_NORM) {
+    wave_reduce_scatter<S>(acc);
+    if ((lane & ((64 / S) - 1)) == 0) red[wv][slot_of_lane<S>(lane)] = (double)acc[0];
+  }
+  if (MODE != KG_ORTH_DOTS) {
+    nrm = wave_sum(nrm);
+    if (lane == 0) redn[wv] = (double)nrm;
+  }
+  __syncthreads();
+  double* out = partial + (size_t)b * KR_LD * blocks + blk;
+  if (MODE != KG_ORTH_NORM && (int)threadIdx.x < cnt)
+    out[(size_t)threadIdx.x * blocks] =
+        (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+  if (MODE != KG_ORTH_DOTS && threadIdx.x == 0)
+    out[(size_t)(MODE == KG_DOTS ? cnt : 0) * blocks] = (redn[0] + redn[1]) + (redn[2] + redn[3]);
 }
 
-__global__ void dots_reduce_kernel(const double* __restrict__ partial, int blocks, int cnt, int B,
-                                   double* __restrict__ out, const int* __restrict__ active) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= B * cnt) return;
-  const int b = id / cnt, i = id % cnt;
-  if (active != nullptr && active[b] == 0) { out[b * KR_MAXV + i] = 0.0; return; }
+// out[b][i] = sum over blocks of partial[b][i][block], one wave per (b, i), fixed order.
+__global__ __launch_bounds__(256) void kgs_reduce_kernel(const double* __restrict__ partial, int blocks,
+                                                         int total, int B, double* __restrict__ out,
+                                                         const int* __restrict__ active) {
+  const int id = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (id >= B * total) return;
+  const int b = id / total, i = id % total;
+  if (active != nullptr && active[b] == 0) {
+    if (lane == 0) out[(size_t)b * KR_LD + i] = 0.0;
+    return;
+  }
+  const double* p = partial + ((size_t)b * KR_LD + i) * blocks;
   double s = 0.0;
-  for (int k = 0; k < blocks; ++k) s += partial[((size_t)b * blocks + k) * KR_MAXV + i];
-  out[b * KR_MAXV + i] = s;
+  for (int k = lane; k < blocks; k += 64) s += p[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[(size_t)b * KR_LD + i] = s;
 }
 
-void launch_dots(const float* w, const float* V, size_t vstride, int cnt, int n, int B,
-                 double* partial, double* out, const int* active, hipStream_t st) {
-  const size_t nn = (size_t)n * n;
+template <int MODE, int MAXV>
+static void launch_kgs_one(float* w, const float* V, size_t vstride, size_t vpad, int cnt, int blocks,
+                           int B, const double* h, double* partial, const int* active, hipStream_t st) {
+  hipLaunchKernelGGL((kgs_kernel<MODE, MAXV>), dim3(blocks * B), dim3(KG_THREADS), 0, st, w, V, vstride,
+                     vpad, cnt, blocks, h, partial, active);
+}
+
+// Register-held basis slice: the instance with the smallest multiple of 8 >= cnt.
+template <int MODE>
+static void launch_kgs_mode(float* w, const float* V, size_t vstride, size_t vpad, int cnt, int blocks,
+                            int B, const double* h, double* partial, const int* active, hipStream_t st) {
+  switch ((cnt + 7) / 8) {
+    case 0:
+    case 1: launch_kgs_one<MODE, 8>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st); break;
+    case 2: launch_kgs_one<MODE, 16>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st); break;
+    case 3: launch_kgs_one<MODE, 24>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st); break;
+    case 4: launch_kgs_one<MODE, 32>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st); break;
+    case 5: launch_kgs_one<MODE, 40>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st); break;
+    case 6: launch_kgs_one<MODE, 48>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st); break;
+    case 7: launch_kgs_one<MODE, 56>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st); break;
+    default: launch_kgs_one<MODE, 64>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st); break;
+  }
+}
+
+int launch_gs_pass(int mode, float* w, const float* V, size_t vstride, int cnt, int n, int B,
+                   const double* h, double* partial, double* out, const int* active, hipStream_t st) {
+  const size_t vpad = krylov_vpad(n);
   const int blocks = krylov_blocks(n);
-  hipLaunchKernelGGL(dots_kernel, dim3(blocks * B), dim3(256), 0, st, w, V, vstride, cnt, nn, blocks,
-                     partial, active);
-  hipLaunchKernelGGL(dots_reduce_kernel, dim3((B * cnt + 255) / 256), dim3(256), 0, st, partial,
-                     blocks, cnt, B, out, active);
+  if (cnt < 0 || cnt > KRYLOV_MAX_BASIS || (mode != KG_DOTS && cnt < 1)) return -1;
+  const int total = (mode == KG_DOTS) ? cnt + 1 : (mode == KG_ORTH_DOTS ? cnt : 1);
+  if (mode == KG_DOTS)
+    launch_kgs_mode<KG_DOTS>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st);
+  else if (mode == KG_ORTH_DOTS)
+    launch_kgs_mode<KG_ORTH_DOTS>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st);
+  else
+    launch_kgs_mode<KG_ORTH_NORM>(w, V, vstride, vpad, cnt, blocks, B, h, partial, active, st);
+  const int waves = B * total;
+  hipLaunchKernelGGL(kgs_reduce_kernel, dim3((waves + 3) / 4), dim3(256), 0, st, partial, blocks, total,
+                     B, out, active);
+  return 0;
 }
 
-// w[b] -= sum_{i<cnt} h[b][i] V_i[b]
-__global__ void orth_update_kernel(float* __restrict__ w, const float* __restrict__ V,
-                                   size_t vstride, int cnt, size_t nn, int B,
-                                   const double* __restrict__ h, const int* __restrict__ active) {
-  const size_t total = nn * (size_t)B;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
-       k += (size_t)gridDim.x * blockDim.x) {
-    const int b = (int)(k / nn);
-    if (active != nullptr && active[b] == 0) continue;
-    double acc = w[k];
-    for (int i = 0; i < cnt; ++i) acc -= h[b * KR_MAXV + i] * (double)V[(size_t)i * vstride + k];
-    w[k] = (float)acc;
-  }
+// v *= s[b] in place (stride vpad) and rt = v / D ([B][n][n]).  D as in the operator: sum of
+// face coefficients / h^2 + (|bx| + |by|) / h.
+__global__ __launch_bounds__(256) void knormalize_diag_kernel(const float* __restrict__ a,
+                                                              const float* __restrict__ bvec,
+                                                              float* __restrict__ v, size_t vpad,
+                                                              float* __restrict__ rt,
+                                                              const double* __restrict__ s, int n,
+                                                              int tiles_x, int tiles_per_prob,
+                                                              const int* __restrict__ active) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
+  if (active != nullptr && active[b] == 0) return;
+  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
+  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
+  if (i >= n || j >= n) return;
+  const size_t base = (size_t)b * n * n;
+  const float* A = a + base;
+  const int ij = i * n + j;
+  auto H = [](double p, double q) { return 2.0 * p * q / (p + q); };
+  const double ac = A[ij];
+  const double aE = (j + 1 < n) ? H(ac, A[ij + 1]) : ac;
+  const double aW = (j > 0) ? H(ac, A[ij - 1]) : ac;
+  const double aN = (i + 1 < n) ? H(ac, A[ij + n]) : ac;
+  const double aS = (i > 0) ? H(ac, A[ij - n]) : ac;
+  const double ih = (double)(n + 1);
+  const double D = (aE + aW + aN + aS) * ih * ih +
+                   (fabs((double)bvec[2 * b]) + fabs((double)bvec[2 * b + 1])) * ih;
+  float* vp = v + (size_t)b * vpad + ij;
+  const double x = (double)*vp * s[(size_t)b * KR_LD];
+  *vp = (float)x;
+  rt[base + ij] = (float)(x / D);
 }
 
-void launch_orth_update(float* w, const float* V, size_t vstride, int cnt, int n, int B,
-                        const double* h, const int* active, hipStream_t st) {
-  const size_t total = (size_t)n * n * B;
-  size_t blocks = (total + 255) / 256;
-  if (blocks > 131072) blocks = 131072;
-  hipLaunchKernelGGL(orth_update_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w, V, vstride, cnt,
-                     (size_t)n * n, B, h, active);
+void launch_normalize_diag(const float* a, const float* b, float* v, float* rt, const double* s, int n,
+                           int B, const int* active, hipStream_t st) {
+  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  hipLaunchKernelGGL(knormalize_diag_kernel, dim3(tx * ty * B), dim3(256), 0, st, a, b, v,
+                     krylov_vpad(n), rt, s, n, tx, tx * ty, active);
 }
 
-// x[b] *= s[b]
-__global__ void scale_kernel(float* __restrict__ x, size_t nn, int B, const double* __restrict__ s,
-                             const int* __restrict__ active) {
-  const size_t total = nn * (size_t)B;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
-       k += (size_t)gridDim.x * blockDim.x) {
-    const int b = (int)(k / nn);
-    if (active != nullptr && active[b] == 0) continue;
-    x[k] = (float)((double)x[k] * s[b]);
-  }
-}
-
-void launch_scale(float* x, int n, int B, const double* s, const int* active, hipStream_t st) {
-  const size_t total = (size_t)n * n * B;
-  size_t blocks = (total + 255) / 256;
-  if (blocks > 131072) blocks = 131072;
-  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, (size_t)n * n, B, s,
-                     active);
-}
-
-// u[b] += sum_{j<cnt} y[b][j] Z_j[b]
+// u[b] += sum_{j<cnt} y[b][j] Z_j[b] (terms with y = 0 are skipped: their Z_j may be stale)
 template <typename UT>
 __global__ void combine_kernel(UT* __restrict__ u, const float* __restrict__ Z, size_t zstride,
                                int cnt, size_t nn, int B, const double* __restrict__ y,
@@ -153,7 +328,10 @@ __global__ void combine_kernel(UT* __restrict__ u, const float* __restrict__ Z, 
     const int b = (int)(k / nn);
     if (active != nullptr && active[b] == 0) continue;
     double acc = 0.0;
-    for (int j = 0; j < cnt; ++j) acc += y[b * KR_MAXV + j] * (double)Z[(size_t)j * zstride + k];
+    for (int j = 0; j < cnt; ++j) {
+      const double yj = y[(size_t)b * KR_LD + j];
+      if (yj != 0.0) acc += yj * (double)Z[(size_t)j * zstride + k];
+    }
     u[k] = (UT)((double)u[k] + acc);
   }
 }

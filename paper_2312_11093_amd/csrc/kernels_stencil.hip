@@ -314,7 +314,8 @@ __global__ __launch_bounds__(256) void out_update_kernel(const XT* __restrict__ 
                                                          const float* __restrict__ W,
                                                          UT* __restrict__ u, int n, int tiles_x,
                                                          int tiles_per_prob,
-                                                         const int* __restrict__ active) {
+                                                         const int* __restrict__ active,
+                                                         int accumulate) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
   if (active != nullptr && active[b] == 0) return;
@@ -336,27 +337,27 @@ __global__ __launch_bounds__(256) void out_update_kernel(const XT* __restrict__ 
     }
   }
   UT* U = u + (size_t)b * n * n + (size_t)i * n + j;
-  *U = *U + (UT)acc;
+  *U = accumulate ? *U + (UT)acc : (UT)acc;
 }
 
 void launch_out_update(StateType t, const void* x, const float* Wout, void* u, bool u_f64, int n,
-                       int B, const int* active, hipStream_t st) {
+                       int B, const int* active, hipStream_t st, bool accumulate) {
   const int tx = (n + 63) / 64, ty = (n + 3) / 4;
   const dim3 grid(tx * ty * B), blk(256);
   if (t == ST_F32) {
     if (u_f64)
       hipLaunchKernelGGL((out_update_kernel<float, double>), grid, blk, 0, st, (const float*)x,
-                         Wout, (double*)u, n, tx, tx * ty, active);
+                         Wout, (double*)u, n, tx, tx * ty, active, accumulate ? 1 : 0);
     else
       hipLaunchKernelGGL((out_update_kernel<float, float>), grid, blk, 0, st, (const float*)x,
-                         Wout, (float*)u, n, tx, tx * ty, active);
+                         Wout, (float*)u, n, tx, tx * ty, active, accumulate ? 1 : 0);
   } else {
     if (u_f64)
       hipLaunchKernelGGL((out_update_kernel<bf16_t, double>), grid, blk, 0, st, (const bf16_t*)x,
-                         Wout, (double*)u, n, tx, tx * ty, active);
+                         Wout, (double*)u, n, tx, tx * ty, active, accumulate ? 1 : 0);
     else
       hipLaunchKernelGGL((out_update_kernel<bf16_t, float>), grid, blk, 0, st, (const bf16_t*)x,
-                         Wout, (float*)u, n, tx, tx * ty, active);
+                         Wout, (float*)u, n, tx, tx * ty, active, accumulate ? 1 : 0);
   }
 }
 

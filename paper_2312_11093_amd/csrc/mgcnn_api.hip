@@ -65,6 +65,28 @@ hipEvent_t pool_event(mgcnn_ctx* c) {
   return c->pool[c->pool_used++];
 }
 
+int prof_drain(mgcnn_ctx* c) {
+  for (const auto& r : c->recs) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, r.e0, r.e1));
+    mgcnn_kernel_stat* hit = nullptr;
+    for (auto& a : c->agg)
+      if (a.kind == r.kind && a.level == r.level) { hit = &a; break; }
+    if (!hit) {
+      mgcnn_kernel_stat z{};
+      z.kind = r.kind; z.level = r.level;
+      c->agg.push_back(z);
+      hit = &c->agg.back();
+    }
+    hit->launches += 1;
+    hit->ms_total += ms;
+    hit->bytes_per_launch += r.bytes;
+  }
+  c->recs.clear();
+  c->pool_used = 0;
+  return MGCNN_OK;
+}
+
 bool valid_n(int n) {
   if (n < 3 || n > 4095) return false;
   return ((n + 1) & n) == 0;
@@ -174,8 +196,9 @@ int run_chunk(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int 
   return MGCNN_OK;
 }
 
-// One application of the solve network (Alg. 3) to c->d_rt, added into u (u += B(rt)).
-int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active) {
+// One application of the solve network (Alg. 3) to c->d_rt, added into u (u += B(rt)), or
+// stored into u (u = B(rt)) when !accumulate.
+int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, bool accumulate) {
   const StateType st = c->st();
   const int L = c->L, B = c->B;
   hipStream_t s = c->stream;
@@ -217,7 +240,8 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active) {
   }
   {
     Prof p(c, MGCNN_K_OUT_UPDATE, 0, nodes(0) * (S + 2.0 * (u_f64 ? 8 : 4)));
-    launch_out_update(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, active, s);
+    launch_out_update(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, active, s,
+                      accumulate);
   }
   LAUNCH_CHECK(c);
   return MGCNN_OK;
@@ -397,6 +421,7 @@ int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, in
     steps += chunk;
     HIP_TRY(c, hipMemcpyAsync(act.data(), c->d_active, (size_t)B * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
+    if (c->prof && (r = prof_drain(c))) return r;
     bool any = false;
     for (int b = 0; b < B; ++b) any |= act[b] != 0;
     if (!any) break;
@@ -444,8 +469,7 @@ int mgcnn_apply(mgcnn_ctx* c, const float* r, float* z) {
   if (!c->ready) return fail(c, MGCNN_E_STATE, "apply: call mgcnn_setup first");
   if (!r || !z) return fail(c, MGCNN_E_ARG, "apply: null pointer");
   launch_scale_by_diag(c->d_a, c->d_b, r, c->d_rt, c->n, c->B, c->stream);
-  launch_zero(z, (size_t)c->n * c->n * c->B * 4, c->stream);
-  return vcycle(c, z, false, nullptr);
+  return vcycle(c, z, false, nullptr, false);
 }
 
 int mgcnn_residual_norms(mgcnn_ctx* c, const float* f, const void* u, double* relres_host) {
@@ -484,7 +508,9 @@ int mgcnn_get_setup_tensor(mgcnn_ctx* c, int level, float* out) {
 int mgcnn_profile_begin(mgcnn_ctx* c) {
   if (!c) return MGCNN_E_ARG;
   c->recs.clear();
+  c->agg.clear();
   c->pool_used = 0;
+  c->prof_live = 0;
   c->prof = true;
   return MGCNN_OK;
 }
@@ -493,27 +519,14 @@ int mgcnn_profile_end(mgcnn_ctx* c, mgcnn_kernel_stat* stats, int max_stats, int
   if (!c) return MGCNN_E_ARG;
   c->prof = false;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::vector<mgcnn_kernel_stat> agg;
-  for (const auto& r : c->recs) {
-    float ms = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&ms, r.e0, r.e1));
-    mgcnn_kernel_stat* hit = nullptr;
-    for (auto& a : agg)
-      if (a.kind == r.kind && a.level == r.level) { hit = &a; break; }
-    if (!hit) {
-      mgcnn_kernel_stat z{};
-      z.kind = r.kind; z.level = r.level; z.bytes_per_launch = r.bytes;
-      agg.push_back(z);
-      hit = &agg.back();
-    }
-    hit->launches += 1;
-    hit->ms_total += ms;
-  }
-  c->recs.clear();
-  c->pool_used = 0;
-  if (n_stats) *n_stats = (int)agg.size();
+  int r = prof_drain(c);
+  if (r) return r;
+  std::vector<mgcnn_kernel_stat> out = c->agg;
+  for (auto& a : out) a.bytes_per_launch = a.launches ? a.bytes_per_launch / a.launches : 0.0;
+  c->agg.clear();
+  if (n_stats) *n_stats = (int)out.size();
   if (stats)
-    for (int i = 0; i < (int)agg.size() && i < max_stats; ++i) stats[i] = agg[i];
+    for (int i = 0; i < (int)out.size() && i < max_stats; ++i) stats[i] = out[i];
   return MGCNN_OK;
 }
 

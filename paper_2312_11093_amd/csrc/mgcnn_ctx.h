@@ -37,6 +37,8 @@ struct mgcnn_ctx {
   struct ProfRec { int kind, level; double bytes; hipEvent_t e0, e1; };
   bool prof = false;
   std::vector<ProfRec> recs;
+  std::vector<mgcnn_kernel_stat> agg;   // records already folded in (bytes_per_launch holds the sum)
+  int prof_live = 0;                     // live problems of the next launches (0: all), for bytes
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
 
@@ -59,7 +61,8 @@ struct mgcnn_ctx {
     float* V = nullptr;       // (m+1) Arnoldi vectors [B][n][n]
     float* Z = nullptr;       // m preconditioned vectors
     double* partial = nullptr;
-    double* h = nullptr;      // per-problem scalars exchanged with the host
+    double* h = nullptr;      // per-problem inner products returned to the host
+    double* s = nullptr;      // per-problem scale factors / combination coefficients
     int* act = nullptr;       // problems extending their basis
     int* cyc = nullptr;       // problems live in the current restart cycle
   } kr;
@@ -96,7 +99,9 @@ int fail(mgcnn_ctx* ctx, int code, const std::string& msg);
 int hip_fail(mgcnn_ctx* ctx, hipError_t e, const char* what);
 int alloc(mgcnn_ctx* c, void** p, size_t bytes);
 hipEvent_t pool_event(mgcnn_ctx* c);
-int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active);
+// Fold completed profiling records into c->agg and recycle their events (stream synchronised).
+int prof_drain(mgcnn_ctx* c);
+int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, bool accumulate = true);
 int forward_record(mgcnn_ctx* c, const float* f, float* u, int K);
 void free_train(mgcnn_ctx* c);
 void free_krylov(mgcnn_ctx* c);
@@ -122,7 +127,8 @@ struct Prof {
   bool on;
   Prof(mgcnn_ctx* c_, int kind, int level, double bytes) : c(c_), on(c_->prof) {
     if (!on) return;
-    r.kind = kind; r.level = level; r.bytes = bytes;
+    r.kind = kind; r.level = level;
+    r.bytes = (c->prof_live > 0 && c->B > 0) ? bytes * c->prof_live / c->B : bytes;
     r.e0 = pool_event(c); r.e1 = pool_event(c);
     if (!r.e0 || !r.e1) { on = false; return; }
     (void)hipEventRecord(r.e0, c->stream);

@@ -21,18 +21,14 @@ using namespace mg;
 using namespace mg::api;
 
 namespace mg {
-void launch_scale_by_diag(const float* a, const float* b, const float* r, float* rt, int n, int B,
-                          hipStream_t st);
 void launch_zero_if_zero_rhs(void* u, bool u_f64, const double* nf2, int n, int B, hipStream_t st);
-void launch_residual_plain(const float* a, const float* b, const float* f, const void* u, bool u_f64,
-                           float* r, int n, int B, hipStream_t st);
 
 namespace api {
 
 void free_krylov(mgcnn_ctx* c) {
   auto& K = c->kr;
   auto fr = [](void* p) { if (p) (void)hipFree(p); };
-  fr(K.V); fr(K.Z); fr(K.partial); fr(K.h); fr(K.act); fr(K.cyc);
+  fr(K.V); fr(K.Z); fr(K.partial); fr(K.h); fr(K.s); fr(K.act); fr(K.cyc);
   K = mgcnn_ctx::Krylov{};
 }
 
@@ -41,17 +37,25 @@ static int ensure_krylov(mgcnn_ctx* c, int m) {
   if (K.n == c->n && K.B == c->B && K.m >= m) return MGCNN_OK;
   free_krylov(c);
   const size_t nn = (size_t)c->n * c->n * c->B;
+  const size_t nv = krylov_vpad(c->n) * c->B;
+  const size_t ld = (size_t)c->B * KRYLOV_LD * 8;
   int r;
-  if ((r = alloc(c, (void**)&K.V, nn * 4 * (m + 1)))) return r;
+  if ((r = alloc(c, (void**)&K.V, nv * 4 * (m + 1)))) return r;
+  // the padding of every basis vector stays zero (set once here, outside any captured work)
+  HIP_TRY(c, hipMemset(K.V, 0, nv * 4 * (m + 1)));
   if ((r = alloc(c, (void**)&K.Z, nn * 4 * m))) return r;
-  if ((r = alloc(c, (void**)&K.partial, (size_t)c->B * krylov_blocks(c->n) * KRYLOV_MAX_BASIS * 8))) return r;
-  if ((r = alloc(c, (void**)&K.h, (size_t)c->B * KRYLOV_MAX_BASIS * 8))) return r;
+  if ((r = alloc(c, (void**)&K.partial, (size_t)krylov_blocks(c->n) * ld))) return r;
+  if ((r = alloc(c, (void**)&K.h, ld))) return r;
+  if ((r = alloc(c, (void**)&K.s, ld))) return r;
   if ((r = alloc(c, (void**)&K.act, (size_t)c->B * 4))) return r;
   if ((r = alloc(c, (void**)&K.cyc, (size_t)c->B * 4))) return r;
   K.n = c->n; K.B = c->B; K.m = m;
   return MGCNN_OK;
 }
 
+// Restarted FGMRES(m), right preconditioned by z = B(v / D), one Arnoldi process per problem.
+// Orthogonalisation: classical Gram-Schmidt applied twice (three passes over the basis).  The
+// small least-squares problems (Givens rotations) run on the host in f64.
 int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int* iters_host,
                  double* relres_host, int* status_host) {
   const int m = std::max(1, std::min(c->opts.restart > 0 ? c->opts.restart : 30, KRYLOV_MAX_BASIS - 1));
@@ -61,9 +65,11 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
   hipStream_t s = c->stream;
   const int B = c->B, n = c->n;
   const size_t nn = (size_t)n * n * B;
-  const size_t vs = nn;                       // stride between basis vectors (floats)
+  const size_t vs = krylov_vpad(n) * B;      // stride between basis vectors (floats)
+  const size_t zs = nn;                      // stride between preconditioned vectors
   const bool u64 = c->u64();
   const double nodes = (double)nn;           // all problems; retired ones are skipped by the kernels
+  const int LD = KRYLOV_LD;
   // ||f||^2
   launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, n, B, nullptr, s);
   launch_sum_partials(c->d_partial, c->tiles, c->d_nf2, B, s);
@@ -77,30 +83,40 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
     if (nf2[b] > 0.0) act[b] = 1;
     else { status[b] = MGCNN_OK; relres[b] = 0.0; }
   }
-  const int LD = KRYLOV_MAX_BASIS;
-  std::vector<double> H((size_t)B * (LD + 1) * LD), g((size_t)B * LD), cs((size_t)B * LD),
-      sn((size_t)B * LD), hbuf((size_t)B * LD), ybuf((size_t)B * LD), sc(B);
+  const int HL = KRYLOV_MAX_BASIS;
+  std::vector<double> H((size_t)B * (HL + 1) * HL), g((size_t)B * HL + B), cs((size_t)B * HL),
+      sn((size_t)B * HL), hb((size_t)B * LD), hb2((size_t)B * LD), hb3((size_t)B * LD),
+      sc((size_t)B * LD, 0.0),
+      nw2(B, 0.0);
   std::vector<int> kb(B);
-  auto Hij = [&](int b, int i, int j) -> double& { return H[((size_t)b * (LD + 1) + i) * LD + j]; };
+  auto Hij = [&](int b, int i, int j) -> double& { return H[((size_t)b * (HL + 1) + i) * HL + j]; };
+  auto gi = [&](int b, int i) -> double& { return g[(size_t)b * (HL + 1) + i]; };
+  auto to_dev = [&](int* d, const std::vector<int>& h) {
+    return hipMemcpyAsync(d, h.data(), (size_t)B * 4, hipMemcpyHostToDevice, s);
+  };
+  auto from_dev = [&](std::vector<double>& h) {
+    return hipMemcpyAsync(h.data(), K.h, (size_t)B * LD * 8, hipMemcpyDeviceToHost, s);
+  };
   while (true) {
     // true residual of every live problem, its norm, and the stopping rule
+    c->prof_live = 0;
     {
       Prof p(c, MGCNN_K_KRYLOV_RESIDUAL, 0, nodes * (12.0 + (u64 ? 8 : 4)));
-      launch_residual_plain(c->d_a, c->d_b, f, u, u64, K.V, n, B, s);
+      launch_krylov_residual(c->d_a, c->d_b, f, u, u64, K.V, krylov_vpad(n), n, B, nullptr, s);
     }
-    HIP_TRY(c, hipMemcpyAsync(K.act, act.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, to_dev(K.act, act));
     {
-      Prof p(c, MGCNN_K_KRYLOV_DOTS, 1, nodes * 4.0);
-      launch_dots(K.V, K.V, vs, 1, n, B, K.partial, K.h, K.act, s);
+      Prof p(c, MGCNN_K_KRYLOV_DOTS, 0, nodes * 4.0);
+      launch_gs_pass(0, K.V, K.V, vs, 0, n, B, nullptr, K.partial, K.h, K.act, s);
     }
     LAUNCH_CHECK(c);
-    HIP_TRY(c, hipMemcpyAsync(hbuf.data(), K.h, (size_t)B * LD * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, from_dev(hb));
     HIP_TRY(c, hipStreamSynchronize(s));
     bool any = false;
     for (int b = 0; b < B; ++b) {
       cyc[b] = 0;
       if (!act[b]) continue;
-      const double beta = std::sqrt(std::max(hbuf[(size_t)b * LD], 0.0));
+      const double beta = std::sqrt(std::max(hb[(size_t)b * LD], 0.0));
       const double rho = beta / std::sqrt(nf2[b]);
       relres[b] = rho;
       if (rho <= tol) { status[b] = MGCNN_OK; act[b] = 0; }
@@ -109,72 +125,70 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
       else {
         cyc[b] = 1;
         any = true;
-        sc[b] = 1.0 / beta;
-        for (int i = 0; i < LD; ++i) { g[(size_t)b * LD + i] = 0.0; }
-        g[(size_t)b * LD] = beta;
-        std::fill(&Hij(b, 0, 0), &Hij(b, 0, 0) + (size_t)(LD + 1) * LD, 0.0);
+        sc[(size_t)b * LD] = 1.0 / beta;
+        for (int i = 0; i <= HL; ++i) gi(b, i) = 0.0;
+        gi(b, 0) = beta;
+        std::fill(&Hij(b, 0, 0), &Hij(b, 0, 0) + (size_t)(HL + 1) * HL, 0.0);
         kb[b] = 0;
       }
     }
     if (!any) break;
     std::vector<int> live = cyc;                 // problems still extending their basis this cycle
-    HIP_TRY(c, hipMemcpyAsync(K.cyc, cyc.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipMemcpyAsync(K.act, live.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipMemcpyAsync(K.h, sc.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
-    {
-      Prof p(c, MGCNN_K_KRYLOV_SCALE, 0, nodes * 8.0);
-      launch_scale(K.V, n, B, K.h, K.act, s);
-    }
+    c->prof_live = (int)std::count(live.begin(), live.end(), 1);
+    HIP_TRY(c, to_dev(K.cyc, cyc));
+    HIP_TRY(c, to_dev(K.act, live));
     for (int j = 0; j < m; ++j) {
       float* Vj = K.V + (size_t)j * vs;
       float* Vn = K.V + (size_t)(j + 1) * vs;
-      float* Zj = K.Z + (size_t)j * vs;
-      // z_j = B(v_j / D)
+      float* Zj = K.Z + (size_t)j * zs;
+      // v_j /= |v_j| (in place) and z_j = B(v_j / D)
+      HIP_TRY(c, hipMemcpyAsync(K.s, sc.data(), (size_t)B * LD * 8, hipMemcpyHostToDevice, s));
       {
-        Prof p(c, MGCNN_K_SCALE_BY_DIAG, 0, nodes * 12.0);
-        launch_scale_by_diag(c->d_a, c->d_b, Vj, c->d_rt, n, B, s);
+        Prof p(c, MGCNN_K_SCALE_BY_DIAG, 0, nodes * 16.0);
+        launch_normalize_diag(c->d_a, c->d_b, Vj, c->d_rt, K.s, n, B, K.act, s);
       }
-      {
-        Prof p(c, MGCNN_K_ZERO, 0, nodes * 4.0);
-        launch_zero(Zj, nn * 4, s);
-      }
-      if ((r = vcycle(c, Zj, false, K.act))) return r;
-      // w = A z_j, orthogonalised twice against v_0..v_j
+      if ((r = vcycle(c, Zj, false, K.act, false))) return r;
+      // w = A z_j
       {
         Prof p(c, MGCNN_K_KRYLOV_APPLY_A, 0, nodes * 12.0);
-        launch_apply_A(c->d_a, c->d_b, Zj, Vn, n, B, K.act, s);
+        launch_apply_A(c->d_a, c->d_b, Zj, Vn, krylov_vpad(n), n, B, K.act, s);
       }
-      for (int pass = 0; pass < 2; ++pass) {
-        {
-          Prof p(c, MGCNN_K_KRYLOV_DOTS, j + 1, nodes * 4.0 * (j + 2));
-          launch_dots(Vn, K.V, vs, j + 1, n, B, K.partial, K.h, K.act, s);
-        }
-        HIP_TRY(c, hipMemcpyAsync(hbuf.data(), K.h, (size_t)B * LD * 8, hipMemcpyDeviceToHost, s));
-        {
-          Prof p(c, MGCNN_K_KRYLOV_ORTH, j + 1, nodes * 4.0 * (j + 3));
-          launch_orth_update(Vn, K.V, vs, j + 1, n, B, K.h, K.act, s);
-        }
-        HIP_TRY(c, hipStreamSynchronize(s));
-        for (int b = 0; b < B; ++b)
-          if (live[b])
-            for (int i = 0; i <= j; ++i) Hij(b, i, j) += hbuf[(size_t)b * LD + i];
-      }
+      // classical Gram-Schmidt applied twice, in three passes:
+      //   h1 = V^T w ; w -= V h1 and h2 = V^T w ; w -= V h2 and |w|^2
+      const int cnt = j + 1;
       {
-        Prof p(c, MGCNN_K_KRYLOV_DOTS, 1, nodes * 4.0);
-        launch_dots(Vn, Vn, vs, 1, n, B, K.partial, K.h, K.act, s);
+        Prof p(c, MGCNN_K_KRYLOV_DOTS, cnt, nodes * 4.0 * (cnt + 1));
+        launch_gs_pass(0, Vn, K.V, vs, cnt, n, B, nullptr, K.partial, K.h, K.act, s);
+      }
+      HIP_TRY(c, from_dev(hb));
+      {
+        Prof p(c, MGCNN_K_KRYLOV_ORTH, cnt, nodes * 4.0 * (cnt + 2));
+        launch_gs_pass(1, Vn, K.V, vs, cnt, n, B, K.h, K.partial, K.h, K.act, s);
+      }
+      HIP_TRY(c, from_dev(hb2));
+      {
+        Prof p(c, MGCNN_K_KRYLOV_ORTH, cnt, nodes * 4.0 * (cnt + 2));
+        launch_gs_pass(2, Vn, K.V, vs, cnt, n, B, K.h, K.partial, K.h, K.act, s);
       }
       LAUNCH_CHECK(c);
-      HIP_TRY(c, hipMemcpyAsync(hbuf.data(), K.h, (size_t)B * LD * 8, hipMemcpyDeviceToHost, s));
+      HIP_TRY(c, from_dev(hb3));
       HIP_TRY(c, hipStreamSynchronize(s));
+      for (int b = 0; b < B; ++b) {
+        if (!live[b]) continue;
+        for (int i = 0; i < cnt; ++i)
+          Hij(b, i, j) = hb[(size_t)b * LD + i] + hb2[(size_t)b * LD + i];
+        nw2[b] = hb3[(size_t)b * LD];
+      }
+      if (c->prof && (r = prof_drain(c))) return r;   // the stream is idle here
       bool more = false;
       for (int b = 0; b < B; ++b) {
         if (!live[b]) continue;
-        const double hn = std::sqrt(std::max(hbuf[(size_t)b * LD], 0.0));
+        const double hn = std::sqrt(std::max(nw2[b], 0.0));
         Hij(b, j + 1, j) = hn;
-        sc[b] = hn > 0.0 ? 1.0 / hn : 0.0;
+        sc[(size_t)b * LD] = hn > 0.0 ? 1.0 / hn : 0.0;
         // Givens rotations: previous ones on column j, then a new one for (j, j+1)
         for (int i = 0; i < j; ++i) {
-          const double c0 = cs[(size_t)b * LD + i], s0 = sn[(size_t)b * LD + i];
+          const double c0 = cs[(size_t)b * HL + i], s0 = sn[(size_t)b * HL + i];
           const double h0 = Hij(b, i, j), h1 = Hij(b, i + 1, j);
           Hij(b, i, j) = c0 * h0 + s0 * h1;
           Hij(b, i + 1, j) = -s0 * h0 + c0 * h1;
@@ -182,45 +196,44 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
         const double h0 = Hij(b, j, j), h1 = Hij(b, j + 1, j);
         const double rr = std::hypot(h0, h1);
         const double c0 = rr > 0.0 ? h0 / rr : 1.0, s0 = rr > 0.0 ? h1 / rr : 0.0;
-        cs[(size_t)b * LD + j] = c0; sn[(size_t)b * LD + j] = s0;
+        cs[(size_t)b * HL + j] = c0; sn[(size_t)b * HL + j] = s0;
         Hij(b, j, j) = rr; Hij(b, j + 1, j) = 0.0;
-        const double gj = g[(size_t)b * LD + j];
-        g[(size_t)b * LD + j] = c0 * gj;
-        g[(size_t)b * LD + j + 1] = -s0 * gj;
+        const double gj = gi(b, j);
+        gi(b, j) = c0 * gj;
+        gi(b, j + 1) = -s0 * gj;
         iters[b] += 1;
         kb[b] = j + 1;
-        const double est = std::fabs(g[(size_t)b * LD + j + 1]) / std::sqrt(nf2[b]);
+        const double est = std::fabs(gi(b, j + 1)) / std::sqrt(nf2[b]);
         if (est <= tol || iters[b] >= maxit || hn == 0.0 || !std::isfinite(est)) live[b] = 0;
         else more = true;
       }
       if (!more || j == m - 1) break;
-      HIP_TRY(c, hipMemcpyAsync(K.h, sc.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
-      {
-        Prof p(c, MGCNN_K_KRYLOV_SCALE, 0, nodes * 8.0);
-        launch_scale(Vn, n, B, K.h, K.act, s);
-      }
-      HIP_TRY(c, hipMemcpyAsync(K.act, live.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
+      HIP_TRY(c, to_dev(K.act, live));
+      c->prof_live = (int)std::count(live.begin(), live.end(), 1);
     }
     // y = R^-1 g (upper triangular, k_b x k_b) and u += Z y
-    std::fill(ybuf.begin(), ybuf.end(), 0.0);
+    std::fill(sc.begin(), sc.end(), 0.0);
+    int kmax = 0;
     for (int b = 0; b < B; ++b) {
       if (!cyc[b]) continue;
       const int k = kb[b];
+      kmax = std::max(kmax, k);
       for (int i = k - 1; i >= 0; --i) {
-        double acc = g[(size_t)b * LD + i];
-        for (int l = i + 1; l < k; ++l) acc -= Hij(b, i, l) * ybuf[(size_t)b * LD + l];
-        ybuf[(size_t)b * LD + i] = Hij(b, i, i) != 0.0 ? acc / Hij(b, i, i) : 0.0;
+        double acc = gi(b, i);
+        for (int l = i + 1; l < k; ++l) acc -= Hij(b, i, l) * sc[(size_t)b * LD + l];
+        sc[(size_t)b * LD + i] = Hij(b, i, i) != 0.0 ? acc / Hij(b, i, i) : 0.0;
       }
     }
-    int kmax = 0;
-    for (int b = 0; b < B; ++b) if (cyc[b]) kmax = std::max(kmax, kb[b]);
-    HIP_TRY(c, hipMemcpyAsync(K.h, ybuf.data(), (size_t)B * LD * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(K.s, sc.data(), (size_t)B * LD * 8, hipMemcpyHostToDevice, s));
+    c->prof_live = (int)std::count(cyc.begin(), cyc.end(), 1);
     {
       Prof p(c, MGCNN_K_KRYLOV_COMBINE, kmax, nodes * (4.0 * kmax + 2.0 * (u64 ? 8 : 4)));
-      launch_combine(u, u64, K.Z, vs, kmax, n, B, K.h, K.cyc, s);
+      launch_combine(u, u64, K.Z, zs, kmax, n, B, K.s, K.cyc, s);
     }
     LAUNCH_CHECK(c);
+    HIP_TRY(c, hipStreamSynchronize(s));      // sc is rewritten by the next cycle
   }
+  c->prof_live = 0;
   bool diverged = false, notconv = false;
   for (int b = 0; b < B; ++b) {
     if (iters_host) iters_host[b] = iters[b];

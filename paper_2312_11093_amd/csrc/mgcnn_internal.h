@@ -52,9 +52,9 @@ void launch_smooth_in(StateType t, const float* rt, const void* s, const float* 
 void launch_smooth_out(StateType t, const void* v, const void* s, const float* W, const float* Wout,
                        void* u, bool u_f64, int m, int B, const int* active, hipStream_t st);
 
-// u += W_out * x (16 -> 1 same-size conv), u f32 or f64.
+// u += W_out * x (16 -> 1 same-size conv), u f32 or f64; u = W_out * x when !accumulate.
 void launch_out_update(StateType t, const void* x, const float* Wout, void* u, bool u_f64,
-                       int n, int B, const int* active, hipStream_t st);
+                       int n, int B, const int* active, hipStream_t st, bool accumulate = true);
 
 // r = f - A(a,b) u ; rt = r / D (f32) ; partial[b][tile] = sum r^2 (f64).
 // u == nullptr means u = 0.  mode64: u is f64 and the arithmetic is f64; otherwise u is f32 and

@@ -7,16 +7,31 @@
 namespace mg {
 
 constexpr int KRYLOV_MAX_BASIS = 64;   // maximum restart length + 1
+constexpr int KRYLOV_LD = 72;          // per-problem stride of the scalar arrays (basis + norm + pad)
 
+// Arnoldi vectors are [B][krylov_vpad(n)] float32, zero padded; Gram-Schmidt passes run over
+// krylov_blocks(n) groups of elements per problem.
+size_t krylov_vpad(int n);
 int krylov_blocks(int n);
-void launch_apply_A(const float* a, const float* b, const float* x, float* y, int n, int B,
-                    const int* active, hipStream_t st);
-// out[b * 64 + i] = <w_b, V_i,b> for i < cnt (V_i at V + i * vstride); partial: B * blocks * 64
-void launch_dots(const float* w, const float* V, size_t vstride, int cnt, int n, int B,
-                 double* partial, double* out, const int* active, hipStream_t st);
-void launch_orth_update(float* w, const float* V, size_t vstride, int cnt, int n, int B,
-                        const double* h, const int* active, hipStream_t st);
-void launch_scale(float* x, int n, int B, const double* s, const int* active, hipStream_t st);
+
+// y = A x ([B][n][n] in, per-problem stride ystride out), f64 stencil arithmetic
+void launch_apply_A(const float* a, const float* b, const float* x, float* y, size_t ystride, int n,
+                    int B, const int* active, hipStream_t st);
+// r = f - A u (u f32 or f64, [B][n][n]); r with per-problem stride rstride
+void launch_krylov_residual(const float* a, const float* b, const float* f, const void* u, bool u_f64,
+                            float* r, size_t rstride, int n, int B, const int* active, hipStream_t st);
+// One Gram-Schmidt pass over w and V_0..V_{cnt-1} (V_i at V + i * vstride), results in
+// out[b * KRYLOV_LD + slot]:
+//   mode 0: out[i] = <V_i, w> (i < cnt), out[cnt] = <w, w>
+//   mode 1: w -= sum_i h_i V_i, then out[i] = <V_i, w>
+//   mode 2: w -= sum_i h_i V_i, then out[0] = <w, w>
+// partial: B * KRYLOV_LD * krylov_blocks(n) doubles.  Returns -1 if cnt is out of range.
+int launch_gs_pass(int mode, float* w, const float* V, size_t vstride, int cnt, int n, int B,
+                   const double* h, double* partial, double* out, const int* active, hipStream_t st);
+// v *= s[b * KRYLOV_LD] in place (stride krylov_vpad(n)) and rt = v / D ([B][n][n])
+void launch_normalize_diag(const float* a, const float* b, float* v, float* rt, const double* s, int n,
+                           int B, const int* active, hipStream_t st);
+// u_b += sum_{j<cnt} y[b * KRYLOV_LD + j] Z_j,b  (Z_j at Z + j * zstride, [B][n][n])
 void launch_combine(void* u, bool u_f64, const float* Z, size_t zstride, int cnt, int n, int B,
                     const double* y, const int* active, hipStream_t st);
 
