@@ -309,6 +309,14 @@ void launch_conv_in(int cin, const float* in, const float* W, void* out, StateTy
 }
 
 // u[px] += sum_{c,p,q} W[0][c][p][q] x[px + (p-1, q-1)][c]
+//
+// Each workgroup covers an OU_TH x OU_TW output tile.  Every pixel of the tile plus its one-pixel
+// halo is read once (its 16 channels straight into registers) and reduced over the channels for
+// all nine taps: y_t(q) = sum_c W[c][t] x[q][c].  The nine partial sums go to LDS and every output
+// adds the nine values of its neighbours, u(p) += sum_t y_t(p - d_t).
+constexpr int OU_TH = 8, OU_TW = 64;
+constexpr int OU_SH = OU_TH + 2, OU_SW = OU_TW + 2;
+
 template <typename XT, typename UT>
 __global__ __launch_bounds__(256) void out_update_kernel(const XT* __restrict__ x,
                                                          const float* __restrict__ W,
@@ -316,48 +324,64 @@ __global__ __launch_bounds__(256) void out_update_kernel(const XT* __restrict__ 
                                                          int tiles_per_prob,
                                                          const int* __restrict__ active,
                                                          int accumulate) {
+  __shared__ float Y[9][OU_SH * OU_SW];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
   if (active != nullptr && active[b] == 0) return;
-  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
-  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
-  if (i >= n || j >= n) return;
+  const int i0 = (tile / tiles_x) * OU_TH - 1, j0 = (tile % tiles_x) * OU_TW - 1;
   const XT* X = x + (size_t)b * n * n * C;
-  float acc = 0.f;
+  for (int q = threadIdx.x; q < OU_SH * OU_SW; q += 256) {
+    const int ii = i0 + q / OU_SW, jj = j0 + q % OU_SW;
+    float y[9];
 #pragma unroll
-  for (int p = 0; p < 3; ++p) {
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int ii = i + p - 1, jj = j + q - 1;
-      if (ii < 0 || ii >= n || jj < 0 || jj >= n) continue;
+    for (int k = 0; k < 9; ++k) y[k] = 0.f;
+    if (ii >= 0 && ii < n && jj >= 0 && jj < n) {
       float v[C];
       load16(X + ((size_t)ii * n + jj) * C, v);
 #pragma unroll
-      for (int c = 0; c < C; ++c) acc = fmaf(W[c * 9 + p * 3 + q], v[c], acc);
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) y[k] = fmaf(W[c * 9 + k], v[c], y[k]);
     }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Y[k][q] = y[k];
   }
-  UT* U = u + (size_t)b * n * n + (size_t)i * n + j;
-  *U = accumulate ? *U + (UT)acc : (UT)acc;
+  __syncthreads();
+  const size_t ubase = (size_t)b * n * n;
+  for (int o = threadIdx.x; o < OU_TH * OU_TW; o += 256) {
+    const int r = o / OU_TW, cc = o % OU_TW;
+    const int i = i0 + 1 + r, j = j0 + 1 + cc;
+    if (i >= n || j >= n) continue;
+    // output (r, cc) sits at staged (r + 1, cc + 1); tap (p, q) reads staged (r + p, cc + q)
+    float acc = 0.f;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc += Y[p * 3 + q][(r + p) * OU_SW + cc + q];
+    UT* U = u + ubase + (size_t)i * n + j;
+    *U = accumulate ? *U + (UT)acc : (UT)acc;
+  }
 }
 
 void launch_out_update(StateType t, const void* x, const float* Wout, void* u, bool u_f64, int n,
                        int B, const int* active, hipStream_t st, bool accumulate) {
-  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  const int tx = (n + OU_TW - 1) / OU_TW, ty = (n + OU_TH - 1) / OU_TH;
   const dim3 grid(tx * ty * B), blk(256);
+  const int acc = accumulate ? 1 : 0;
   if (t == ST_F32) {
     if (u_f64)
       hipLaunchKernelGGL((out_update_kernel<float, double>), grid, blk, 0, st, (const float*)x,
-                         Wout, (double*)u, n, tx, tx * ty, active, accumulate ? 1 : 0);
+                         Wout, (double*)u, n, tx, tx * ty, active, acc);
     else
       hipLaunchKernelGGL((out_update_kernel<float, float>), grid, blk, 0, st, (const float*)x,
-                         Wout, (float*)u, n, tx, tx * ty, active, accumulate ? 1 : 0);
+                         Wout, (float*)u, n, tx, tx * ty, active, acc);
   } else {
     if (u_f64)
       hipLaunchKernelGGL((out_update_kernel<bf16_t, double>), grid, blk, 0, st, (const bf16_t*)x,
-                         Wout, (double*)u, n, tx, tx * ty, active, accumulate ? 1 : 0);
+                         Wout, (double*)u, n, tx, tx * ty, active, acc);
     else
       hipLaunchKernelGGL((out_update_kernel<bf16_t, float>), grid, blk, 0, st, (const bf16_t*)x,
-                         Wout, (float*)u, n, tx, tx * ty, active, accumulate ? 1 : 0);
+                         Wout, (float*)u, n, tx, tx * ty, active, acc);
   }
 }
 
