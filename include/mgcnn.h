@@ -74,10 +74,13 @@ typedef struct {
   int method;       /* MGCNN_METHOD_STATIONARY or MGCNN_METHOD_FGMRES */
   int restart;      /* FGMRES restart length m, 1..63 (Krylov vectors are float32; the true
                        residual is recomputed in f64 at every restart) */
+  int f32_split;    /* MGCNN_F32 state only: 1 = 16->16 convs on bf16 matrix cores with both
+                       operands split into three bf16 parts (float32-level products, several
+                       times the f32 matrix rate); 0 = float32 matrix instructions */
 } mgcnn_opts;
 
-/* Default options: 16 channels, f32 state, f64 u, graphs off, check every 4 iterations,
- * stationary method, FGMRES restart 30. */
+/* Default options: 16 channels, f32 state (split-bf16 matrix arithmetic), f64 u, graphs off,
+ * check every 4 iterations, stationary method, FGMRES restart 30. */
 void mgcnn_default_opts(mgcnn_opts *opts);
 
 /* Number of weights for `channels` hidden channels: 81 C^2 + 58 C. */
@@ -165,7 +168,7 @@ enum {
   MGCNN_K_RESIDUAL = 0, MGCNN_K_FINALIZE = 1, MGCNN_K_CONV_IN = 2, MGCNN_K_SMOOTH_DOWN = 3,
   MGCNN_K_RESTRICT = 4, MGCNN_K_SMOOTH_UP = 5, MGCNN_K_PROLONG = 6, MGCNN_K_OUT_UPDATE = 7,
   MGCNN_K_SMOOTH_IN = 8,   /* finest down smoother with the reChannel-in conv folded in */
-  MGCNN_K_SMOOTH_OUT = 9,  /* finest up smoother with reChannel-out and the u update folded in */
+  MGCNN_K_SMOOTH_OUT = 9,  /* reserved (no longer emitted) */
   /* FGMRES vector kernels; for DOTS, ORTH and COMBINE `level` holds the number of basis
      vectors the launch reads */
   MGCNN_K_KRYLOV_APPLY_A = 10, MGCNN_K_KRYLOV_DOTS = 11, MGCNN_K_KRYLOV_ORTH = 12,
@@ -177,7 +180,8 @@ typedef struct {
   int level;               /* 0 = finest */
   int launches;
   double ms_total;
-  double bytes_per_launch;
+  double bytes_per_launch; /* algorithmic HBM bytes (compulsory reads + writes) per launch */
+  double flops_per_launch; /* algorithmic floating-point operations per launch (0 if not counted) */
 } mgcnn_kernel_stat;
 int mgcnn_profile_begin(mgcnn_ctx *ctx);
 /* stats may be NULL (then only *n_stats is set); at most max_stats entries are written. */

@@ -23,6 +23,7 @@ namespace mg {
 
 constexpr int PS = 20;   // LDS pixel stride in elements (16 channels + 4 pad)
 
+
 // ------------------------------------------------------------------------------------------
 // operand helpers
 // ------------------------------------------------------------------------------------------
@@ -35,6 +36,8 @@ struct Frag;
 template <>
 struct Frag<ST_F32> {
   typedef float elem;
+  typedef float lds_t;
+  static constexpr int PLANES = 1;
   float w[9][4];
   __device__ void load_w(const float* W, bool transposed) {
     const int l = threadIdx.x & 63;
@@ -47,7 +50,7 @@ struct Frag<ST_F32> {
         w[t][s] = transposed ? W[(c * C + o) * 9 + t] : W[(o * C + c) * 9 + t];
       }
   }
-  __device__ __forceinline__ f4v mma(int t, const elem* lds_px, f4v acc) const {
+  __device__ __forceinline__ f4v mma(int t, const lds_t* lds_px, f4v acc, int) const {
     const int g = (threadIdx.x & 63) >> 4;
     const float4 z = *reinterpret_cast<const float4*>(lds_px + 4 * g);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[t][0], z.x, acc, 0, 0, 0);
@@ -63,6 +66,8 @@ struct Frag<ST_F32> {
 template <>
 struct Frag<ST_BF16> {
   typedef uint16_t elem;
+  typedef uint16_t lds_t;
+  static constexpr int PLANES = 1;
   s4v w[9];
   __device__ void load_w(const float* W, bool transposed) {
     const int l = threadIdx.x & 63;
@@ -76,13 +81,68 @@ struct Frag<ST_BF16> {
         w[t][e] = (short)f32_to_bf16_rne(v);
       }
   }
-  __device__ __forceinline__ f4v mma(int t, const elem* lds_px, f4v acc) const {
+  __device__ __forceinline__ f4v mma(int t, const lds_t* lds_px, f4v acc, int) const {
     const int g = (threadIdx.x & 63) >> 4;
     const uint2 z = *reinterpret_cast<const uint2*>(lds_px + 4 * g);
-    s4v b;
-    b[0] = (short)(z.x & 0xffffu); b[1] = (short)(z.x >> 16);
-    b[2] = (short)(z.y & 0xffffu); b[3] = (short)(z.y >> 16);
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[t], b, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[t], __builtin_bit_cast(s4v, z), acc, 0, 0, 0);
+  }
+};
+
+// Three-way bf16 split of float32: x = hi + mid + lo exactly up to the rounding of lo
+// (|error| <= 2^-26 |x|); each difference below is exact in float32.
+__device__ __forceinline__ void split3_2(float x0, float x1, uint32_t& h, uint32_t& m, uint32_t& l) {
+  h = pack_bf16x2(x0, x1);
+  const float r0 = x0 - __uint_as_float(h << 16), r1 = x1 - __uint_as_float(h & 0xffff0000u);
+  m = pack_bf16x2(r0, r1);
+  const float q0 = r0 - __uint_as_float(m << 16), q1 = r1 - __uint_as_float(m & 0xffff0000u);
+  l = pack_bf16x2(q0, q1);
+}
+__device__ __forceinline__ void split3_4(float4 v, uint2& H, uint2& M, uint2& L) {
+  split3_2(v.x, v.y, H.x, M.x, L.x);
+  split3_2(v.z, v.w, H.y, M.y, L.y);
+}
+
+// f32 state on bf16 matrix cores: the staged operand is kept in LDS as three bf16 planes
+// (hi, mid, lo) and the weights as three bf16 fragments; per tap six 16x16x16 MFMAs form
+// hi.hi + hi.mid + mid.hi + hi.lo + lo.hi + mid.mid (dropped terms < 2^-24 relative), i.e.
+// float32-level products at the bf16 matrix rate.  Lane layout as in the bf16 case.
+template <>
+struct Frag<ST_F32X> {
+  typedef float elem;
+  typedef uint16_t lds_t;
+  static constexpr int PLANES = 3;
+  s4v wh[9], wm[9], wl[9];
+  __device__ void load_w(const float* W, bool transposed) {
+    const int l = threadIdx.x & 63;
+    const int o = l & 15, g = l >> 4;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 4 * g + e;
+        v[e] = transposed ? W[(c * C + o) * 9 + t] : W[(o * C + c) * 9 + t];
+      }
+      uint2 H, M, L;
+      split3_4(make_float4(v[0], v[1], v[2], v[3]), H, M, L);
+      wh[t] = __builtin_bit_cast(s4v, H);
+      wm[t] = __builtin_bit_cast(s4v, M);
+      wl[t] = __builtin_bit_cast(s4v, L);
+    }
+  }
+  __device__ __forceinline__ f4v mma(int t, const lds_t* lds_px, f4v acc, int pstride) const {
+    const int g = (threadIdx.x & 63) >> 4;
+    const s4v bh = __builtin_bit_cast(s4v, *reinterpret_cast<const uint2*>(lds_px + 4 * g));
+    const s4v bm = __builtin_bit_cast(s4v, *reinterpret_cast<const uint2*>(lds_px + pstride + 4 * g));
+    const s4v bl = __builtin_bit_cast(s4v, *reinterpret_cast<const uint2*>(lds_px + 2 * pstride + 4 * g));
+    // small terms first
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wm[t], bm, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wh[t], bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wl[t], bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wh[t], bm, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wm[t], bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wh[t], bh, acc, 0, 0, 0);
+    return acc;
   }
 };
 
@@ -122,8 +182,18 @@ struct Chunk<ST_F32> {
   static __device__ __forceinline__ T mul(T a, T b) {
     return make_float4(a.x * b.x, a.y * b.y, a.z * b.z, a.w * b.w);
   }
-  static __device__ __forceinline__ void to_lds(float* px, int h, T v) {
+  static __device__ __forceinline__ void to_lds(float* px, int h, T v, int) {
     *reinterpret_cast<float4*>(px + 4 * h) = v;
+  }
+};
+template <>
+struct Chunk<ST_F32X> : Chunk<ST_F32> {
+  static __device__ __forceinline__ void to_lds(uint16_t* px, int h, T v, int pstride) {
+    uint2 H, M, L;
+    split3_4(v, H, M, L);
+    *reinterpret_cast<uint2*>(px + 4 * h) = H;
+    *reinterpret_cast<uint2*>(px + pstride + 4 * h) = M;
+    *reinterpret_cast<uint2*>(px + 2 * pstride + 4 * h) = L;
   }
 };
 template <>
@@ -142,7 +212,7 @@ struct Chunk<ST_BF16> {
   static __device__ __forceinline__ T mul(T a, T b) {
     return make_uint4(mul2(a.x, b.x), mul2(a.y, b.y), mul2(a.z, b.z), mul2(a.w, b.w));
   }
-  static __device__ __forceinline__ void to_lds(uint16_t* px, int h, T v) {
+  static __device__ __forceinline__ void to_lds(uint16_t* px, int h, T v, int) {
     *reinterpret_cast<uint2*>(px + 8 * h) = make_uint2(v.x, v.y);
     *reinterpret_cast<uint2*>(px + 8 * h + 4) = make_uint2(v.z, v.w);
   }
@@ -154,7 +224,7 @@ struct Chunk<ST_BF16> {
 // ------------------------------------------------------------------------------------------
 template <int ST>
 struct SameCfg {
-  static constexpr int TH = 8, TW = (ST == ST_F32) ? 32 : 64;
+  static constexpr int TH = 8, TW = (ST == ST_BF16) ? 64 : 32;
   static constexpr int IR = TH + 2, IC = TW + 2, NPIX = IR * IC;
   static constexpr int NCHUNK = NPIX * Chunk<ST>::CPP, NPT = (NCHUNK + 255) / 256;
   static constexpr int NSEG = TW / 16, NTASK = TH * NSEG, TPW = NTASK / 4;
@@ -169,10 +239,11 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
   typedef typename Frag<ST>::elem E;
   typedef SameCfg<ST> K;
   typedef Chunk<ST> CK;
-  __shared__ __attribute__((aligned(16))) E lds[K::NPIX * PS];
+  constexpr int PSTR = K::NPIX * PS;                  // LDS plane stride
+  __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
-  if (active != nullptr && active[b] == 0) return;
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int row0 = (tile / tiles_x) * K::TH, col0 = (tile % tiles_x) * K::TW;
   const size_t pbase = (size_t)b * m * m * C;     // problem offset in elements
   const E* Xb = x + pbase;
@@ -211,7 +282,7 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
       const int pix = k / CK::CPP, h = k % CK::CPP;
       typename CK::T v = xv[r];
       if constexpr (MODE == CM_SMOOTH) v = CK::mul(v, sv[r]);
-      CK::to_lds(&lds[pix * PS], h, v);
+      CK::to_lds(&lds[pix * PS], h, v, PSTR);
     }
   }
   __syncthreads();
@@ -227,7 +298,7 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
     for (int p = 0; p < 3; ++p)
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        acc = fr.mma(p * 3 + q, &lds[((orow + p) * K::IC + seg * 16 + px + q) * PS], acc);
+        acc = fr.mma(p * 3 + q, &lds[((orow + p) * K::IC + seg * 16 + px + q) * PS], acc, PSTR);
     const int gj = col0 + seg * 16 + px;
     if (gj < m) {
       const float4 c = xc[tt];
@@ -252,7 +323,7 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
 // ------------------------------------------------------------------------------------------
 template <int ST>
 struct RsCfg {
-  static constexpr int TH = (ST == ST_F32) ? 4 : 8, TW = 32;
+  static constexpr int TH = (ST == ST_BF16) ? 8 : 4, TW = 32;
   static constexpr int IR = 2 * TH + 1, IC = 2 * TW + 1, HALF = TW + 1, ROW = 2 * HALF;
   static constexpr int NPIX = IR * IC, NCHUNK = NPIX * Chunk<ST>::CPP, NPT = (NCHUNK + 255) / 256;
   static constexpr int NSEG = TW / 16, NTASK = TH * NSEG, TPW = NTASK / 4;
@@ -269,10 +340,11 @@ __global__ __launch_bounds__(256) void conv16_restrict_kernel(
   typedef typename Frag<ST>::elem E;
   typedef RsCfg<ST> K;
   typedef Chunk<ST> CK;
-  __shared__ __attribute__((aligned(16))) E lds[K::IR * K::ROW * PS];
+  constexpr int PSTR = K::IR * K::ROW * PS;           // LDS plane stride
+  __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
-  if (active != nullptr && active[b] == 0) return;
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int orow0 = (tile / tiles_x) * K::TH, ocol0 = (tile % tiles_x) * K::TW;
   const int frow0 = 2 * orow0, fcol0 = 2 * ocol0;
   const E* Xb = x + (size_t)b * m * m * C;
@@ -295,7 +367,7 @@ __global__ __launch_bounds__(256) void conv16_restrict_kernel(
     if (k < K::NCHUNK) {
       const int pix = k / CK::CPP, h = k % CK::CPP;
       const int lr = pix / K::IC, lc = pix - lr * K::IC;
-      CK::to_lds(&lds[(lr * K::ROW + rs_slot<K::HALF>(lc)) * PS], h, xv[r]);
+      CK::to_lds(&lds[(lr * K::ROW + rs_slot<K::HALF>(lc)) * PS], h, xv[r], PSTR);
     }
   }
   __syncthreads();
@@ -313,7 +385,8 @@ __global__ __launch_bounds__(256) void conv16_restrict_kernel(
     for (int p = 0; p < 3; ++p)
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        acc = fr.mma(p * 3 + q, &lds[((2 * orow + p) * K::ROW + rs_slot<K::HALF>(2 * jj + q)) * PS], acc);
+        acc = fr.mma(p * 3 + q, &lds[((2 * orow + p) * K::ROW + rs_slot<K::HALF>(2 * jj + q)) * PS], acc,
+                     PSTR);
     const int gj = ocol0 + jj;
     if (gj < mo) st4(Yb, gi * mo + gj, g, make_float4(acc[0], acc[1], acc[2], acc[3]));
   }
@@ -337,10 +410,11 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
   typedef typename Frag<ST>::elem E;
   typedef Chunk<ST> CK;
   constexpr int NPIX = PL_IR * PL_IC, NCHUNK = NPIX * CK::CPP, NPT = (NCHUNK + 255) / 256;
-  __shared__ __attribute__((aligned(16))) E lds[NPIX * PS];
+  constexpr int PSTR = NPIX * PS;                     // LDS plane stride
+  __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
-  if (active != nullptr && active[b] == 0) return;
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int m = 2 * mc + 1;
   const int I0 = (tile / tiles_x) * PL_CH, J0 = (tile % tiles_x) * PL_CW;
   const E* Cb = xc + (size_t)b * mc * mc * C;
@@ -370,7 +444,7 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int k = threadIdx.x + 256 * r;
-    if (k < NCHUNK) CK::to_lds(&lds[(k / CK::CPP) * PS], k % CK::CPP, cv[r]);
+    if (k < NCHUNK) CK::to_lds(&lds[(k / CK::CPP) * PS], k % CK::CPP, cv[r], PSTR);
   }
   __syncthreads();
 #pragma unroll
@@ -391,10 +465,10 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
       else if (rt == 0) { p = 0; lr = fr_local / 2 + 1; }
       else { p = 2; lr = fr_local / 2; }
       if (par) {
-        acc = fr.mma(p * 3 + 1, &lds[(lr * PL_IC + jc + 1) * PS], acc);
+        acc = fr.mma(p * 3 + 1, &lds[(lr * PL_IC + jc + 1) * PS], acc, PSTR);
       } else {
-        acc = fr.mma(p * 3 + 0, &lds[(lr * PL_IC + jc + 1) * PS], acc);
-        acc = fr.mma(p * 3 + 2, &lds[(lr * PL_IC + jc) * PS], acc);
+        acc = fr.mma(p * 3 + 0, &lds[(lr * PL_IC + jc + 1) * PS], acc, PSTR);
+        acc = fr.mma(p * 3 + 2, &lds[(lr * PL_IC + jc) * PS], acc, PSTR);
       }
     }
     const int j = 2 * (J0 + jc) + par;
@@ -410,7 +484,8 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
 // Finest level, down smoother with the reChannel-in conv folded in:
 //   x1 = W_in * rt  (1 -> 16, zero padding),  y = x1 + W_dn * (s . x1).
 // x1 is computed on the staged tile (one-pixel halo, zero outside the grid) from an LDS copy of
-// rt with a two-pixel halo, so x1 never travels through HBM.
+// rt with a two-pixel halo, so x1 never travels through HBM; x1 at the output pixels is kept in
+// LDS for the skip term.
 // ------------------------------------------------------------------------------------------
 template <int ST>
 __global__ __launch_bounds__(256) void smooth_in_kernel(
@@ -422,12 +497,14 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
   typedef SameCfg<ST> K;
   constexpr int RR = K::IR + 2, RC = K::IC + 2;          // rt tile (two-pixel halo)
   constexpr int PPT = (K::NPIX + 255) / 256;             // staged pixels per thread
-  __shared__ __attribute__((aligned(16))) E lds[K::NPIX * PS];     // z = s . x1
+  constexpr int RPT = (RR * RC + 255) / 256;             // rt values per thread
+  constexpr int PSTR = K::NPIX * PS;                     // LDS plane stride
+  __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];  // z = s . x1
   __shared__ __attribute__((aligned(16))) E lx[K::TH * K::TW * PS];  // x1 at the output pixels
   __shared__ float lrt[RR * RC];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
-  if (active != nullptr && active[b] == 0) return;
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int row0 = (tile / tiles_x) * K::TH, col0 = (tile % tiles_x) * K::TW;
   const size_t pbase = (size_t)b * m * m;
   const E* Sb = s + pbase * C;
@@ -435,7 +512,15 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
   const float* Rb = rt + pbase;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int px = lane & 15, g = lane >> 4;
-  // s for the staged pixels (one thread = one whole pixel, 16 channels)
+  // 1. every global load of this thread first: the rt tile, then s of the staged pixels
+  float rv[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int k = threadIdx.x + 256 * r;
+    const int lr = k / RC, lc = k - lr * RC;
+    const int gi = row0 + lr - 2, gj = col0 + lc - 2;
+    rv[r] = (k < RR * RC && gi >= 0 && gi < m && gj >= 0 && gj < m) ? Rb[gi * m + gj] : 0.f;
+  }
   float sv[PPT][C];
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
@@ -450,15 +535,15 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
       for (int c = 0; c < C; ++c) sv[r][c] = 0.f;
     }
   }
-  for (int k = threadIdx.x; k < RR * RC; k += 256) {
-    const int lr = k / RC, lc = k - lr * RC;
-    const int gi = row0 + lr - 2, gj = col0 + lc - 2;
-    lrt[k] = (gi >= 0 && gi < m && gj >= 0 && gj < m) ? Rb[gi * m + gj] : 0.f;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int k = threadIdx.x + 256 * r;
+    if (k < RR * RC) lrt[k] = rv[r];
   }
   Frag<ST> fr;
   fr.load_w(W, false);
   __syncthreads();
-  // x1 = W_in * rt on the staged tile (weights are wave-uniform: scalar loads), z = s . x1
+  // 2. x1 = W_in * rt on the staged tile (weights are wave-uniform: scalar loads), z = s . x1
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
     const int pix = threadIdx.x + 256 * r;
@@ -482,10 +567,18 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
       x1[c] = acc;
       z[c] = acc * sv[r][c];
     }
-    store16(&lds[pix * PS], z);
+    if constexpr (ST == ST_F32X) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+        Chunk<ST_F32X>::to_lds(&lds[pix * PS], h, make_float4(z[4 * h], z[4 * h + 1], z[4 * h + 2], z[4 * h + 3]),
+                               PSTR);
+    } else {
+      store16(&lds[pix * PS], z);
+    }
     if (lr >= 1 && lr <= K::TH && lc >= 1 && lc <= K::TW) store16(&lx[((lr - 1) * K::TW + lc - 1) * PS], x1);
   }
   __syncthreads();
+  // 3. implicit GEMM per 16-pixel segment, y = x1 + acc
 #pragma unroll
   for (int tt = 0; tt < K::TPW; ++tt) {
     const int task = wave * K::TPW + tt;
@@ -497,12 +590,12 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
     for (int p = 0; p < 3; ++p)
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        acc = fr.mma(p * 3 + q, &lds[((orow + p) * K::IC + seg * 16 + px + q) * PS], acc);
+        acc = fr.mma(p * 3 + q, &lds[((orow + p) * K::IC + seg * 16 + px + q) * PS], acc, PSTR);
     const int gj = col0 + seg * 16 + px;
     if (gj < m) {
       const E* xp = &lx[(orow * K::TW + seg * 16 + px) * PS + 4 * g];
       float4 xo;
-      if constexpr (ST == ST_F32) {
+      if constexpr (ST != ST_BF16) {
         xo = *reinterpret_cast<const float4*>(xp);
       } else {
         const uint2 zz = *reinterpret_cast<const uint2*>(xp);
@@ -515,185 +608,72 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
 }
 
 // ------------------------------------------------------------------------------------------
-// Finest level, up smoother with the reChannel-out conv and the update folded in:
-//   y = v + W_up * (s . v)  on the output tile plus a one-pixel ring (kept in LDS, zero outside
-//   the grid), then u += W_out * y on the output tile.  y never travels through HBM.
-// Output tile: (TH - 2) x (TW - 2); the MFMA region is TH x TW, staged v region (TH+2)x(TW+2).
-// ------------------------------------------------------------------------------------------
-template <int ST, typename UT>
-__global__ __launch_bounds__(256) void smooth_out_kernel(
-    const typename Frag<ST>::elem* __restrict__ v, const typename Frag<ST>::elem* __restrict__ s,
-    const float* __restrict__ W, const float* __restrict__ Wout, UT* __restrict__ u, int m,
-    int tiles_x, int tiles_per_prob, const int* __restrict__ active) {
-  typedef typename Frag<ST>::elem E;
-  typedef SameCfg<ST> K;
-  typedef Chunk<ST> CK;
-  constexpr int OH = K::TH - 2, OW = K::TW - 2;         // output tile
-  __shared__ __attribute__((aligned(16))) E lds[K::NPIX * PS];
-  __shared__ __attribute__((aligned(16))) E ly[K::TH * K::TW * PS];
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
-  if (active != nullptr && active[b] == 0) return;
-  // origin of the MFMA (y) region; the output tile starts one pixel further in
-  const int yr0 = (tile / tiles_x) * OH - 1, yc0 = (tile % tiles_x) * OW - 1;
-  const size_t pbase = (size_t)b * m * m;
-  const E* Vb = v + pbase * C;
-  const E* Sb = s + pbase * C;
-  UT* Ub = u + pbase;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int px = lane & 15, g = lane >> 4;
-  typename CK::T xv[K::NPT], sv[K::NPT];
-#pragma unroll
-  for (int r = 0; r < K::NPT; ++r) {
-    const int k = threadIdx.x + 256 * r;
-    const int pix = k / CK::CPP, h = k % CK::CPP;
-    const int lr = pix / K::IC, lc = pix - lr * K::IC;
-    const int gi = yr0 + lr - 1, gj = yc0 + lc - 1;
-    const bool ok = k < K::NCHUNK && gi >= 0 && gi < m && gj >= 0 && gj < m;
-    const int gp = ok ? gi * m + gj : 0;
-    xv[r] = ok ? CK::load(Vb, gp, h) : CK::zero();
-    sv[r] = ok ? CK::load(Sb, gp, h) : CK::zero();
-  }
-  float4 xc[K::TPW];
-#pragma unroll
-  for (int tt = 0; tt < K::TPW; ++tt) {
-    const int task = wave * K::TPW + tt;
-    const int gi = yr0 + task / K::NSEG, gj = yc0 + (task % K::NSEG) * 16 + px;
-    const bool ok = gi >= 0 && gi < m && gj >= 0 && gj < m;
-    xc[tt] = ok ? ld4(Vb, gi * m + gj, g) : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-  Frag<ST> fr;
-  fr.load_w(W, false);
-#pragma unroll
-  for (int r = 0; r < K::NPT; ++r) {
-    const int k = threadIdx.x + 256 * r;
-    if (k < K::NCHUNK) CK::to_lds(&lds[(k / CK::CPP) * PS], k % CK::CPP, CK::mul(xv[r], sv[r]));
-  }
-  __syncthreads();
-#pragma unroll
-  for (int tt = 0; tt < K::TPW; ++tt) {
-    const int task = wave * K::TPW + tt;
-    const int orow = task / K::NSEG, seg = task % K::NSEG;
-    const int gi = yr0 + orow;
-    f4v acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-        acc = fr.mma(p * 3 + q, &lds[((orow + p) * K::IC + seg * 16 + px + q) * PS], acc);
-    const int gj = yc0 + seg * 16 + px;
-    const bool in = gi >= 0 && gi < m && gj >= 0 && gj < m;
-    const float4 c = xc[tt];
-    // the up-smoothed state (zero outside the grid: padding of the reChannel-out conv)
-    st4_lds(&ly[(orow * K::TW + seg * 16 + px) * PS + 4 * g],
-            in ? make_float4(c.x + acc[0], c.y + acc[1], c.z + acc[2], c.w + acc[3])
-               : make_float4(0.f, 0.f, 0.f, 0.f));
-  }
-  __syncthreads();
-  // u += W_out * y on the output tile (weights wave-uniform: scalar loads)
-  for (int k = threadIdx.x; k < OH * OW; k += 256) {
-    const int orr = k / OW, occ = k - orr * OW;
-    const int gi = yr0 + 1 + orr, gj = yc0 + 1 + occ;
-    if (gi >= m || gj >= m) continue;
-    float acc = 0.f;
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        float yv[C];
-        load16(&ly[((orr + p) * K::TW + occ + q) * PS], yv);
-#pragma unroll
-        for (int c2 = 0; c2 < C; ++c2) acc = fmaf(Wout[c2 * 9 + p * 3 + q], yv[c2], acc);
-      }
-    UT* U = Ub + gi * m + gj;
-    *U = *U + (UT)acc;
-  }
-}
-
-// ------------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------------
-void launch_conv16(ConvMode mode, StateType st_, const void* x, const void* s, const float* W,
-                   const float* bias, void* y, int m, int B, const int* active, hipStream_t st) {
+template <int ST>
+static void conv16_launch(ConvMode mode, const void* x, const void* s, const float* W, const float* bias,
+                          void* y, int m, int B, const int* active, hipStream_t st) {
+  typedef typename Frag<ST>::elem E;
   if (mode == CM_RESTRICT) {
+    typedef RsCfg<ST> K;
     const int mo = (m - 1) / 2;
-    const int TW = 32, TH = (st_ == ST_F32) ? RsCfg<ST_F32>::TH : RsCfg<ST_BF16>::TH;
-    const int tx = (mo + TW - 1) / TW, ty = (mo + TH - 1) / TH;
-    const dim3 grid(tx * ty * B), blk(256);
-    if (st_ == ST_F32)
-      hipLaunchKernelGGL(conv16_restrict_kernel<ST_F32>, grid, blk, 0, st, (const float*)x, W,
-                         (float*)y, m, mo, tx, tx * ty, active);
-    else
-      hipLaunchKernelGGL(conv16_restrict_kernel<ST_BF16>, grid, blk, 0, st, (const uint16_t*)x, W,
-                         (uint16_t*)y, m, mo, tx, tx * ty, active);
+    const int tx = (mo + K::TW - 1) / K::TW, ty = (mo + K::TH - 1) / K::TH;
+    hipLaunchKernelGGL(conv16_restrict_kernel<ST>, dim3(tx * ty * B), dim3(256), 0, st, (const E*)x, W,
+                       (E*)y, m, mo, tx, tx * ty, active);
     return;
   }
-  const int TW = (st_ == ST_F32 || mode == CM_TANH) ? SameCfg<ST_F32>::TW : SameCfg<ST_BF16>::TW;
-  const int TH = SameCfg<ST_F32>::TH;
-  const int tx = (m + TW - 1) / TW, ty = (m + TH - 1) / TH;
-  const dim3 grid(tx * ty * B), blk(256);
-  if (mode == CM_SMOOTH) {
-    if (st_ == ST_F32)
-      hipLaunchKernelGGL((conv16_same_kernel<ST_F32, CM_SMOOTH>), grid, blk, 0, st,
-                         (const float*)x, (const float*)s, W, bias, (float*)y, m, tx, tx * ty,
-                         active);
-    else
-      hipLaunchKernelGGL((conv16_same_kernel<ST_BF16, CM_SMOOTH>), grid, blk, 0, st,
-                         (const uint16_t*)x, (const uint16_t*)s, W, bias, (uint16_t*)y, m, tx,
-                         tx * ty, active);
-  } else {
-    hipLaunchKernelGGL((conv16_same_kernel<ST_F32, CM_TANH>), grid, blk, 0, st, (const float*)x,
-                       (const float*)nullptr, W, bias, (float*)y, m, tx, tx * ty, active);
-  }
+  typedef SameCfg<ST> K;
+  const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
+  if (mode == CM_SMOOTH)
+    hipLaunchKernelGGL((conv16_same_kernel<ST, CM_SMOOTH>), dim3(tx * ty * B), dim3(256), 0, st,
+                       (const E*)x, (const E*)s, W, bias, (E*)y, m, tx, tx * ty, active);
+  else if constexpr (ST != ST_BF16)
+    hipLaunchKernelGGL((conv16_same_kernel<ST, CM_TANH>), dim3(tx * ty * B), dim3(256), 0, st,
+                       (const E*)x, (const E*)nullptr, W, bias, (E*)y, m, tx, tx * ty, active);
+}
+
+void launch_conv16(ConvMode mode, StateType st_, const void* x, const void* s, const float* W,
+                   const float* bias, void* y, int m, int B, const int* active, hipStream_t st) {
+  // the setup network's tanh layers run in f32.  With f32 storage only the same-size smoothers
+  // use the split (measured faster there); the restriction keeps f32 MFMA (larger LDS tile,
+  // lower occupancy with three planes).
+  if (mode == CM_TANH || st_ == ST_F32 || (st_ == ST_F32X && mode == CM_RESTRICT))
+    conv16_launch<ST_F32>(mode, x, s, W, bias, y, m, B, active, st);
+  else if (st_ == ST_F32X) conv16_launch<ST_F32X>(mode, x, s, W, bias, y, m, B, active, st);
+  else conv16_launch<ST_BF16>(mode, x, s, W, bias, y, m, B, active, st);
+}
+
+template <int ST>
+static void smooth_in_launch(const float* rt, const void* s, const float* Win, const float* W, void* y,
+                             int m, int B, const int* active, hipStream_t st) {
+  typedef SameCfg<ST> K;
+  typedef typename Frag<ST>::elem E;
+  const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
+  hipLaunchKernelGGL(smooth_in_kernel<ST>, dim3(tx * ty * B), dim3(256), 0, st, rt, (const E*)s, Win, W,
+                     (E*)y, m, tx, tx * ty, active);
 }
 
 void launch_smooth_in(StateType st_, const float* rt, const void* s, const float* Win, const float* W,
                       void* y, int m, int B, const int* active, hipStream_t st) {
-  if (st_ == ST_F32) {
-    typedef SameCfg<ST_F32> K;
-    const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
-    hipLaunchKernelGGL(smooth_in_kernel<ST_F32>, dim3(tx * ty * B), dim3(256), 0, st, rt,
-                       (const float*)s, Win, W, (float*)y, m, tx, tx * ty, active);
-  } else {
-    typedef SameCfg<ST_BF16> K;
-    const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
-    hipLaunchKernelGGL(smooth_in_kernel<ST_BF16>, dim3(tx * ty * B), dim3(256), 0, st, rt,
-                       (const uint16_t*)s, Win, W, (uint16_t*)y, m, tx, tx * ty, active);
-  }
+  // f32 storage: f32 MFMA (the split variant measured slower: its three LDS planes halve the
+  // occupancy of this kernel)
+  if (st_ == ST_F32 || st_ == ST_F32X) smooth_in_launch<ST_F32>(rt, s, Win, W, y, m, B, active, st);
+  else smooth_in_launch<ST_BF16>(rt, s, Win, W, y, m, B, active, st);
 }
 
-template <int ST, typename UT>
-static void smooth_out_launch(const void* v, const void* s, const float* W, const float* Wout, void* u,
-                              int m, int B, const int* active, hipStream_t st) {
-  typedef SameCfg<ST> K;
+template <int ST>
+static void prolong_launch(const void* xc, const float* WT, void* yf, int mc, int B, const int* active,
+                           hipStream_t st) {
   typedef typename Frag<ST>::elem E;
-  const int OH = K::TH - 2, OW = K::TW - 2;
-  const int tx = (m + OW - 1) / OW, ty = (m + OH - 1) / OH;
-  hipLaunchKernelGGL((smooth_out_kernel<ST, UT>), dim3(tx * ty * B), dim3(256), 0, st, (const E*)v,
-                     (const E*)s, W, Wout, (UT*)u, m, tx, tx * ty, active);
-}
-
-void launch_smooth_out(StateType st_, const void* v, const void* s, const float* W, const float* Wout,
-                       void* u, bool u_f64, int m, int B, const int* active, hipStream_t st) {
-  if (st_ == ST_F32) {
-    if (u_f64) smooth_out_launch<ST_F32, double>(v, s, W, Wout, u, m, B, active, st);
-    else smooth_out_launch<ST_F32, float>(v, s, W, Wout, u, m, B, active, st);
-  } else {
-    if (u_f64) smooth_out_launch<ST_BF16, double>(v, s, W, Wout, u, m, B, active, st);
-    else smooth_out_launch<ST_BF16, float>(v, s, W, Wout, u, m, B, active, st);
-  }
+  const int tx = (mc + PL_CW - 1) / PL_CW + 1, ty = (mc + PL_CH - 1) / PL_CH + 1;
+  hipLaunchKernelGGL(prolong_add_kernel<ST>, dim3(tx * ty * B), dim3(256), 0, st, (const E*)xc, WT,
+                     (E*)yf, mc, tx, tx * ty, active);
 }
 
 void launch_prolong_add(StateType st_, const void* xc, const float* WT, void* yf, int mc, int B,
                         const int* active, hipStream_t st) {
-  const int tx = (mc + PL_CW - 1) / PL_CW + 1, ty = (mc + PL_CH - 1) / PL_CH + 1;
-  const dim3 grid(tx * ty * B), blk(256);
-  if (st_ == ST_F32)
-    hipLaunchKernelGGL(prolong_add_kernel<ST_F32>, grid, blk, 0, st, (const float*)xc, WT,
-                       (float*)yf, mc, tx, tx * ty, active);
-  else
-    hipLaunchKernelGGL(prolong_add_kernel<ST_BF16>, grid, blk, 0, st, (const uint16_t*)xc, WT,
-                       (uint16_t*)yf, mc, tx, tx * ty, active);
+  if (st_ == ST_F32 || st_ == ST_F32X) prolong_launch<ST_F32>(xc, WT, yf, mc, B, active, st);
+  else prolong_launch<ST_BF16>(xc, WT, yf, mc, B, active, st);
 }
 
 }  // namespace mg

@@ -1,7 +1,7 @@
 // Batched vector kernels for the Krylov (FGMRES) solve with the MGCNN network as a fixed
 // right preconditioner (Sec. 2.2: the network is linear in its input, so it can precondition
 // a Krylov method).  Every kernel handles a batch of independent problems; problems whose flag
-// in `active` is zero are skipped.
+// not in the `active` list are left out of the grid.
 //
 // Layout: Arnoldi vectors are [B][vpad] float32 with vpad = n*n rounded up to 512; the
 // padding is zero from allocation on and no kernel writes it with anything but zero, so the
@@ -36,8 +36,8 @@ __global__ __launch_bounds__(256) void kstencil_kernel(const float* __restrict__
                                                        int tiles_x, int tiles_per_prob,
                                                        const int* __restrict__ active) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
-  if (active != nullptr && active[b] == 0) return;
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
   const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
   if (i >= n || j >= n) return;
@@ -149,8 +149,8 @@ __global__ __launch_bounds__(KG_THREADS) void kgs_kernel(float* __restrict__ w,
   __shared__ double red[4][S];
   __shared__ double redn[4];
   __shared__ double hs[MAXV];
-  const int b = blockIdx.x / blocks, blk = blockIdx.x % blocks;
-  if (active != nullptr && active[b] == 0) return;
+  const int slot = blockIdx.x / blocks, blk = blockIdx.x % blocks;
+  const int b = active != nullptr ? active[slot] : slot;
   if (MODE != KG_DOTS) {
     if ((int)threadIdx.x < MAXV)
       hs[threadIdx.x] = (int)threadIdx.x < cnt ? h[(size_t)b * KR_LD + threadIdx.x] : 0.0;
@@ -222,11 +222,8 @@ __global__ __launch_bounds__(256) void kgs_reduce_kernel(const double* __restric
   const int id = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (id >= B * total) return;
-  const int b = id / total, i = id % total;
-  if (active != nullptr && active[b] == 0) {
-    if (lane == 0) out[(size_t)b * KR_LD + i] = 0.0;
-    return;
-  }
+  const int slot = id / total, i = id % total;
+  const int b = active != nullptr ? active[slot] : slot;
   const double* p = partial + ((size_t)b * KR_LD + i) * blocks;
   double s = 0.0;
   for (int k = lane; k < blocks; k += 64) s += p[k];
@@ -287,8 +284,8 @@ __global__ __launch_bounds__(256) void knormalize_diag_kernel(const float* __res
                                                               int tiles_x, int tiles_per_prob,
                                                               const int* __restrict__ active) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
-  if (active != nullptr && active[b] == 0) return;
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
   const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
   if (i >= n || j >= n) return;
@@ -317,7 +314,8 @@ void launch_normalize_diag(const float* a, const float* b, float* v, float* rt, 
                      krylov_vpad(n), rt, s, n, tx, tx * ty, active);
 }
 
-// u[b] += sum_{j<cnt} y[b][j] Z_j[b] (terms with y = 0 are skipped: their Z_j may be stale)
+// u[b] += sum_{j<cnt} y[b][j] Z_j[b] for the listed problems (terms with y = 0 are skipped:
+// their Z_j may be stale)
 template <typename UT>
 __global__ void combine_kernel(UT* __restrict__ u, const float* __restrict__ Z, size_t zstride,
                                int cnt, size_t nn, int B, const double* __restrict__ y,
@@ -325,14 +323,15 @@ __global__ void combine_kernel(UT* __restrict__ u, const float* __restrict__ Z, 
   const size_t total = nn * (size_t)B;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
        k += (size_t)gridDim.x * blockDim.x) {
-    const int b = (int)(k / nn);
-    if (active != nullptr && active[b] == 0) continue;
+    const int slot = (int)(k / nn);
+    const int b = active != nullptr ? active[slot] : slot;
+    const size_t e = (size_t)b * nn + (k - (size_t)slot * nn);
     double acc = 0.0;
     for (int j = 0; j < cnt; ++j) {
       const double yj = y[(size_t)b * KR_LD + j];
-      if (yj != 0.0) acc += yj * (double)Z[(size_t)j * zstride + k];
+      if (yj != 0.0) acc += yj * (double)Z[(size_t)j * zstride + e];
     }
-    u[k] = (UT)((double)u[k] + acc);
+    u[e] = (UT)((double)u[e] + acc);
   }
 }
 

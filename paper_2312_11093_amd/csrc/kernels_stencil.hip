@@ -85,8 +85,8 @@ __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__
                                                        int tiles_x, int tiles_per_prob,
                                                        const int* __restrict__ active) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
-  if (active != nullptr && active[b] == 0) return;
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int j = (tile % tiles_x) * 256 + threadIdx.x;
   const int i0 = (tile / tiles_x) * RES_ROWS;
   const size_t base = (size_t)b * n * n;
@@ -252,8 +252,8 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
                                                       int tiles_per_prob,
                                                       const int* __restrict__ active) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
-  if (active != nullptr && active[b] == 0) return;
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
   const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
   if (i >= n || j >= n) return;
@@ -292,14 +292,14 @@ void launch_conv_in(int cin, const float* in, const float* W, void* out, StateTy
   const int tx = (n + 63) / 64, ty = (n + 3) / 4;
   const dim3 grid(tx * ty * B), blk(256);
   if (cin == 1) {
-    if (ot == ST_F32)
+    if (ot != ST_BF16)
       hipLaunchKernelGGL((conv_in_kernel<1, float>), grid, blk, 0, st, in, W, (float*)out, n, tx,
                          tx * ty, active);
     else
       hipLaunchKernelGGL((conv_in_kernel<1, bf16_t>), grid, blk, 0, st, in, W, (bf16_t*)out, n,
                          tx, tx * ty, active);
   } else {
-    if (ot == ST_F32)
+    if (ot != ST_BF16)
       hipLaunchKernelGGL((conv_in_kernel<4, float>), grid, blk, 0, st, in, W, (float*)out, n, tx,
                          tx * ty, active);
     else
@@ -323,11 +323,13 @@ __global__ __launch_bounds__(256) void out_update_kernel(const XT* __restrict__ 
                                                          UT* __restrict__ u, int n, int tiles_x,
                                                          int tiles_per_prob,
                                                          const int* __restrict__ active,
+                                                         const int* __restrict__ flags,
                                                          int accumulate) {
   __shared__ float Y[9][OU_SH * OU_SW];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
-  if (active != nullptr && active[b] == 0) return;
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
+  if (flags != nullptr && flags[b] == 0) return;           // retired since the list was built
   const int i0 = (tile / tiles_x) * OU_TH - 1, j0 = (tile % tiles_x) * OU_TW - 1;
   const XT* X = x + (size_t)b * n * n * C;
   for (int q = threadIdx.x; q < OU_SH * OU_SW; q += 256) {
@@ -364,24 +366,24 @@ __global__ __launch_bounds__(256) void out_update_kernel(const XT* __restrict__ 
 }
 
 void launch_out_update(StateType t, const void* x, const float* Wout, void* u, bool u_f64, int n,
-                       int B, const int* active, hipStream_t st, bool accumulate) {
+                       int B, const int* active, hipStream_t st, bool accumulate, const int* flags) {
   const int tx = (n + OU_TW - 1) / OU_TW, ty = (n + OU_TH - 1) / OU_TH;
   const dim3 grid(tx * ty * B), blk(256);
   const int acc = accumulate ? 1 : 0;
-  if (t == ST_F32) {
+  if (t != ST_BF16) {
     if (u_f64)
       hipLaunchKernelGGL((out_update_kernel<float, double>), grid, blk, 0, st, (const float*)x,
-                         Wout, (double*)u, n, tx, tx * ty, active, acc);
+                         Wout, (double*)u, n, tx, tx * ty, active, flags, acc);
     else
       hipLaunchKernelGGL((out_update_kernel<float, float>), grid, blk, 0, st, (const float*)x,
-                         Wout, (float*)u, n, tx, tx * ty, active, acc);
+                         Wout, (float*)u, n, tx, tx * ty, active, flags, acc);
   } else {
     if (u_f64)
       hipLaunchKernelGGL((out_update_kernel<bf16_t, double>), grid, blk, 0, st, (const bf16_t*)x,
-                         Wout, (double*)u, n, tx, tx * ty, active, acc);
+                         Wout, (double*)u, n, tx, tx * ty, active, flags, acc);
     else
       hipLaunchKernelGGL((out_update_kernel<bf16_t, float>), grid, blk, 0, st, (const bf16_t*)x,
-                         Wout, (float*)u, n, tx, tx * ty, active, acc);
+                         Wout, (float*)u, n, tx, tx * ty, active, flags, acc);
   }
 }
 

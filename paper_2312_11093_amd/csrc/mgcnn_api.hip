@@ -81,6 +81,7 @@ int prof_drain(mgcnn_ctx* c) {
     hit->launches += 1;
     hit->ms_total += ms;
     hit->bytes_per_launch += r.bytes;
+    hit->flops_per_launch += r.flops;
   }
   c->recs.clear();
   c->pool_used = 0;
@@ -104,14 +105,14 @@ void free_problem(mgcnn_ctx* c) {
   drop_graph(c);
   auto fr = [](void* p) { if (p) (void)hipFree(p); };
   fr(c->d_a); fr(c->d_b); fr(c->d_rt); fr(c->d_partial); fr(c->d_nf2);
-  fr(c->d_active); fr(c->d_status); fr(c->d_iters); fr(c->d_relres);
+  fr(c->d_active); fr(c->d_plist); fr(c->d_status); fr(c->d_iters); fr(c->d_relres);
   for (auto p : c->s) fr(p);
   for (auto p : c->xin) fr(p);
   for (auto p : c->xdn) fr(p);
   c->s.clear(); c->xin.clear(); c->xdn.clear();
   c->d_a = c->d_b = c->d_rt = nullptr;
   c->d_partial = c->d_nf2 = c->d_relres = nullptr;
-  c->d_active = c->d_status = c->d_iters = nullptr;
+  c->d_active = c->d_plist = c->d_status = c->d_iters = nullptr;
   c->alloc_n = c->alloc_B = 0;
   c->ready = false;
 }
@@ -142,6 +143,7 @@ int ensure_problem(mgcnn_ctx* c, int n, int B) {
   if ((r = alloc(c, (void**)&c->d_partial, (size_t)c->tiles * B * 8))) return r;
   if ((r = alloc(c, (void**)&c->d_nf2, (size_t)B * 8))) return r;
   if ((r = alloc(c, (void**)&c->d_active, (size_t)B * 4))) return r;
+  if ((r = alloc(c, (void**)&c->d_plist, (size_t)B * 4))) return r;
   if ((r = alloc(c, (void**)&c->d_status, (size_t)B * 4))) return r;
   if ((r = alloc(c, (void**)&c->d_iters, (size_t)B * 4))) return r;
   if ((r = alloc(c, (void**)&c->d_relres, (size_t)B * 8))) return r;
@@ -178,7 +180,7 @@ int run_chunk(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int 
   }
   auto& G = c->gcache;
   const bool hit = G.exec && G.f == f && G.u == u && G.tol == tol && G.maxit == maxit &&
-                   G.chunk == chunk && G.gen == c->gen;
+                   G.chunk == chunk && G.gen == c->gen && G.count == c->plist_count;
   if (!hit) {
     drop_graph(c);
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
@@ -191,6 +193,7 @@ int run_chunk(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int 
     e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) { (void)hipGraphDestroy(g); G.exec = nullptr; return hip_fail(c, e, "hipGraphInstantiate"); }
     G.graph = g; G.f = f; G.u = u; G.tol = tol; G.maxit = maxit; G.chunk = chunk; G.gen = c->gen;
+    G.count = c->plist_count;
   }
   HIP_TRY(c, hipGraphLaunch(G.exec, c->stream));
   return MGCNN_OK;
@@ -198,50 +201,56 @@ int run_chunk(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int 
 
 // One application of the solve network (Alg. 3) to c->d_rt, added into u (u += B(rt)), or
 // stored into u (u = B(rt)) when !accumulate.
-int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, bool accumulate) {
+int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool accumulate,
+           const int* flags) {
   const StateType st = c->st();
-  const int L = c->L, B = c->B;
+  const int L = c->L, B = count;
   hipStream_t s = c->stream;
   const double S = (double)c->state_bytes() * C;        // bytes of one 16-channel pixel
+  // algorithmic flops per node: 16 -> 16 3x3 conv (multiply-add = 2), smoother adds s . x and
+  // the skip, 1 <-> 16 3x3 conv
+  const double FL_CONV = 2.0 * 9 * C * C, FL_SMOOTH = FL_CONV + 2.0 * C, FL_IN = 2.0 * 9 * C;
   auto nodes = [&](int l) { return (double)c->nl[l] * c->nl[l] * B; };
   for (int l = 0; l < L; ++l) {
     if (l == 0) {
       // finest level: reChannel-in folded into the down smoother
-      Prof p(c, MGCNN_K_SMOOTH_IN, 0, nodes(0) * (4.0 + 2.0 * S));
+      Prof p(c, MGCNN_K_SMOOTH_IN, 0, nodes(0) * (4.0 + 2.0 * S), nodes(0) * (FL_SMOOTH + FL_IN));
       launch_smooth_in(st, c->d_rt, c->s[0], c->W(c->off.solve_in), c->W(c->off.smooth_down), c->xdn[0],
                        c->nl[0], B, active, s);
     } else {
-      Prof p(c, MGCNN_K_SMOOTH_DOWN, l, nodes(l) * 3.0 * S);
+      Prof p(c, MGCNN_K_SMOOTH_DOWN, l, nodes(l) * 3.0 * S, nodes(l) * FL_SMOOTH);
       launch_conv16(CM_SMOOTH, st, c->xin[l], c->s[l], c->W(c->off.smooth_down), nullptr, c->xdn[l],
                     c->nl[l], B, active, s);
     }
     if (l < L - 1) {
-      Prof p(c, MGCNN_K_RESTRICT, l, (nodes(l) + nodes(l + 1)) * S);
+      Prof p(c, MGCNN_K_RESTRICT, l, (nodes(l) + nodes(l + 1)) * S, nodes(l + 1) * FL_CONV);
       launch_conv16(CM_RESTRICT, st, c->xdn[l], nullptr, c->W(c->off.restrict_), nullptr,
                     c->xin[l + 1], c->nl[l], B, active, s);
     }
   }
   {
-    Prof p(c, MGCNN_K_SMOOTH_UP, L - 1, nodes(L - 1) * 3.0 * S);
+    Prof p(c, MGCNN_K_SMOOTH_UP, L - 1, nodes(L - 1) * 3.0 * S, nodes(L - 1) * FL_SMOOTH);
     launch_conv16(CM_SMOOTH, st, c->xdn[L - 1], c->s[L - 1], c->W(c->off.smooth_up), nullptr,
                   c->xin[L - 1], c->nl[L - 1], B, active, s);
   }
   for (int l = L - 2; l >= 0; --l) {
     {
-      Prof p(c, MGCNN_K_PROLONG, l, (nodes(l + 1) + 2.0 * nodes(l)) * S);
+      Prof p(c, MGCNN_K_PROLONG, l, (nodes(l + 1) + 2.0 * nodes(l)) * S,
+             nodes(l + 1) * FL_CONV + nodes(l) * C);
       launch_prolong_add(st, c->xin[l + 1], c->W(c->off.prolong), c->xdn[l], c->nl[l + 1], B,
                          active, s);
     }
     {
-      Prof p(c, MGCNN_K_SMOOTH_UP, l, nodes(l) * 3.0 * S);
+      Prof p(c, MGCNN_K_SMOOTH_UP, l, nodes(l) * 3.0 * S, nodes(l) * FL_SMOOTH);
       launch_conv16(CM_SMOOTH, st, c->xdn[l], c->s[l], c->W(c->off.smooth_up), nullptr, c->xin[l],
                     c->nl[l], B, active, s);
     }
   }
   {
-    Prof p(c, MGCNN_K_OUT_UPDATE, 0, nodes(0) * (S + 2.0 * (u_f64 ? 8 : 4)));
+    Prof p(c, MGCNN_K_OUT_UPDATE, 0, nodes(0) * (S + (accumulate ? 2.0 : 1.0) * (u_f64 ? 8 : 4)),
+           nodes(0) * (FL_IN + 1.0));
     launch_out_update(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, active, s,
-                      accumulate);
+                      accumulate, flags);
   }
   LAUNCH_CHECK(c);
   return MGCNN_OK;
@@ -250,17 +259,17 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, bool accumulate
 // residual of the current iterate, stopping test, then one V-cycle for live problems
 int solve_step(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit) {
   {
-    const double nodes = (double)c->n * c->n * c->B;
+    const double nodes = (double)c->n * c->n * c->plist_count;
     Prof p(c, MGCNN_K_RESIDUAL, 0, nodes * (12.0 + (c->u64() ? 8 : 4)));
-    launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->B, c->d_active,
-                    c->stream);
+    launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->plist_count,
+                    c->d_plist, c->stream);
   }
   {
     Prof p(c, MGCNN_K_FINALIZE, 0, (double)c->tiles * c->B * 8.0);
     launch_finalize(c->d_partial, c->tiles, c->d_nf2, tol, maxit, c->d_active, c->d_status,
                     c->d_iters, c->d_relres, c->B, c->stream);
   }
-  return vcycle(c, u, c->u64(), c->d_active);
+  return vcycle(c, u, c->u64(), c->d_plist, c->plist_count, true, c->d_active);
 }
 
 }  // namespace api
@@ -279,6 +288,7 @@ void mgcnn_default_opts(mgcnn_opts* o) {
   o->check_every = 4;
   o->method = MGCNN_METHOD_STATIONARY;
   o->restart = 30;
+  o->f32_split = 1;
 }
 
 size_t mgcnn_num_weights(int channels) {
@@ -297,6 +307,7 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.u_dtype != MGCNN_U_F32 && o.u_dtype != MGCNN_U_F64) return MGCNN_E_ARG;
   if (o.check_every < 1) return MGCNN_E_ARG;
   if (o.method != MGCNN_METHOD_STATIONARY && o.method != MGCNN_METHOD_FGMRES) return MGCNN_E_ARG;
+  if (o.f32_split != 0 && o.f32_split != 1) return MGCNN_E_ARG;
   if (o.method == MGCNN_METHOD_FGMRES && (o.restart < 1 || o.restart > 63)) return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
   if (!c) return MGCNN_E_NOMEM;
@@ -360,7 +371,7 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
     const float* zin = cc;
     float* ping[2] = {za, zb};
     for (int k = 0; k < NUM_SETUP_LAYERS; ++k) {
-      float* zout = (k == NUM_SETUP_LAYERS - 1 && c->st() == ST_F32) ? (float*)c->s[l] : ping[k & 1];
+      float* zout = (k == NUM_SETUP_LAYERS - 1 && c->st() != ST_BF16) ? (float*)c->s[l] : ping[k & 1];
       launch_conv16(CM_TANH, ST_F32, zin, nullptr, c->W(c->off.res_w[k]), c->W(c->off.res_b[k]), zout,
                     m, B, nullptr, s);
       zin = zout;
@@ -411,7 +422,12 @@ int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, in
   launch_solve_init(c->d_nf2, c->d_active, c->d_status, c->d_iters, c->d_relres, B, s);
   launch_zero_if_zero_rhs(u, c->u64(), c->d_nf2, c->n, B, s);
   LAUNCH_CHECK(c);
-  std::vector<int> act(B);
+  // the launches cover a compact list of the problems still iterating, rebuilt at every host
+  // check; problems that finish between checks are held by their flag (u is left unchanged)
+  std::vector<int> act(B), plist(B);
+  for (int b = 0; b < B; ++b) plist[b] = b;
+  c->plist_count = B;
+  HIP_TRY(c, hipMemcpyAsync(c->d_plist, plist.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
   int steps = 0;
   const int max_steps = maxit + 1;
   while (steps < max_steps) {
@@ -422,9 +438,15 @@ int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, in
     HIP_TRY(c, hipMemcpyAsync(act.data(), c->d_active, (size_t)B * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     if (c->prof && (r = prof_drain(c))) return r;
-    bool any = false;
-    for (int b = 0; b < B; ++b) any |= act[b] != 0;
-    if (!any) break;
+    int cnt = 0;
+    for (int b = 0; b < B; ++b)
+      if (act[b] != 0) plist[cnt++] = b;
+    if (cnt == 0) break;
+    if (cnt != c->plist_count) {
+      c->plist_count = cnt;
+      HIP_TRY(c, hipMemcpyAsync(c->d_plist, plist.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, s));
+      HIP_TRY(c, hipStreamSynchronize(s));   // plist is rewritten at the next check
+    }
   }
   std::vector<int> st(B), it(B);
   std::vector<double> rr(B);
@@ -457,7 +479,7 @@ int mgcnn_forward(mgcnn_ctx* c, const float* f, void* u, int K, int record) {
       launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->B, nullptr,
                       c->stream);
     }
-    int r = vcycle(c, u, c->u64(), nullptr);
+    int r = vcycle(c, u, c->u64(), nullptr, c->B);
     if (r) return r;
   }
   LAUNCH_CHECK(c);
@@ -469,7 +491,7 @@ int mgcnn_apply(mgcnn_ctx* c, const float* r, float* z) {
   if (!c->ready) return fail(c, MGCNN_E_STATE, "apply: call mgcnn_setup first");
   if (!r || !z) return fail(c, MGCNN_E_ARG, "apply: null pointer");
   launch_scale_by_diag(c->d_a, c->d_b, r, c->d_rt, c->n, c->B, c->stream);
-  return vcycle(c, z, false, nullptr, false);
+  return vcycle(c, z, false, nullptr, c->B, false);
 }
 
 int mgcnn_residual_norms(mgcnn_ctx* c, const float* f, const void* u, double* relres_host) {
@@ -497,7 +519,7 @@ int mgcnn_get_setup_tensor(mgcnn_ctx* c, int level, float* out) {
   if (level < 1 || level > c->L || !out) return fail(c, MGCNN_E_ARG, "get_setup_tensor: bad level");
   const int m = c->nl[level - 1];
   const size_t cnt = (size_t)m * m * c->B * C;
-  if (c->st() == ST_F32)
+  if (c->st() != ST_BF16)
     HIP_TRY(c, hipMemcpyAsync(out, c->s[level - 1], cnt * 4, hipMemcpyDeviceToDevice, c->stream));
   else
     launch_bf16_to_f32((const bf16_t*)c->s[level - 1], out, cnt, c->stream);
@@ -510,7 +532,6 @@ int mgcnn_profile_begin(mgcnn_ctx* c) {
   c->recs.clear();
   c->agg.clear();
   c->pool_used = 0;
-  c->prof_live = 0;
   c->prof = true;
   return MGCNN_OK;
 }
@@ -522,7 +543,10 @@ int mgcnn_profile_end(mgcnn_ctx* c, mgcnn_kernel_stat* stats, int max_stats, int
   int r = prof_drain(c);
   if (r) return r;
   std::vector<mgcnn_kernel_stat> out = c->agg;
-  for (auto& a : out) a.bytes_per_launch = a.launches ? a.bytes_per_launch / a.launches : 0.0;
+  for (auto& a : out) {
+    a.bytes_per_launch = a.launches ? a.bytes_per_launch / a.launches : 0.0;
+    a.flops_per_launch = a.launches ? a.flops_per_launch / a.launches : 0.0;
+  }
   c->agg.clear();
   if (n_stats) *n_stats = (int)out.size();
   if (stats)

@@ -27,18 +27,19 @@ struct mgcnn_ctx {
   double* d_partial = nullptr;
   int tiles = 0;
   double* d_nf2 = nullptr;
-  int* d_active = nullptr;
+  int* d_active = nullptr;          // per-problem flags of the stationary solve
+  int* d_plist = nullptr;           // compact list of the problems still iterating
+  int plist_count = 0;              // its length (the grid size of the solver launches)
   int* d_status = nullptr;
   int* d_iters = nullptr;
   double* d_relres = nullptr;
   bool ready = false;
 
   // per-launch profiling (HIP events around every kernel launch of the solve loop)
-  struct ProfRec { int kind, level; double bytes; hipEvent_t e0, e1; };
+  struct ProfRec { int kind, level; double bytes, flops; hipEvent_t e0, e1; };
   bool prof = false;
   std::vector<ProfRec> recs;
   std::vector<mgcnn_kernel_stat> agg;   // records already folded in (bytes_per_launch holds the sum)
-  int prof_live = 0;                     // live problems of the next launches (0: all), for bytes
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
 
@@ -49,7 +50,7 @@ struct mgcnn_ctx {
     const void* f = nullptr;
     void* u = nullptr;
     double tol = 0.0;
-    int maxit = -1, chunk = 0, gen = -1;
+    int maxit = -1, chunk = 0, gen = -1, count = -1;
   } gcache;
   int gen = 0;                      // bumped whenever problem buffers are reallocated
   hipStream_t cap_stream = nullptr; // capture stream used when the context stream is the null stream
@@ -86,7 +87,10 @@ struct mgcnn_ctx {
   } tr;
 
   size_t state_bytes() const { return opts.state_dtype == MGCNN_BF16 ? 2 : 4; }
-  mg::StateType st() const { return opts.state_dtype == MGCNN_BF16 ? mg::ST_BF16 : mg::ST_F32; }
+  mg::StateType st() const {
+    if (opts.state_dtype == MGCNN_BF16) return mg::ST_BF16;
+    return opts.f32_split ? mg::ST_F32X : mg::ST_F32;
+  }
   bool u64() const { return opts.u_dtype == MGCNN_U_F64; }
   const float* W(size_t o) const { return d_w + o; }
 };
@@ -101,7 +105,10 @@ int alloc(mgcnn_ctx* c, void** p, size_t bytes);
 hipEvent_t pool_event(mgcnn_ctx* c);
 // Fold completed profiling records into c->agg and recycle their events (stream synchronised).
 int prof_drain(mgcnn_ctx* c);
-int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, bool accumulate = true);
+// list/count: the problems the launches cover (list null: all c->B); flags (optional): problems
+// whose flag is 0 keep u unchanged.
+int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* list, int count, bool accumulate = true,
+           const int* flags = nullptr);
 int forward_record(mgcnn_ctx* c, const float* f, float* u, int K);
 void free_train(mgcnn_ctx* c);
 void free_krylov(mgcnn_ctx* c);
@@ -125,10 +132,11 @@ struct Prof {
   mgcnn_ctx* c;
   mgcnn_ctx::ProfRec r{};
   bool on;
-  Prof(mgcnn_ctx* c_, int kind, int level, double bytes) : c(c_), on(c_->prof) {
+  Prof(mgcnn_ctx* c_, int kind, int level, double bytes, double flops = 0.0) : c(c_), on(c_->prof) {
     if (!on) return;
     r.kind = kind; r.level = level;
-    r.bytes = (c->prof_live > 0 && c->B > 0) ? bytes * c->prof_live / c->B : bytes;
+    r.bytes = bytes;
+    r.flops = flops;
     r.e0 = pool_event(c); r.e1 = pool_event(c);
     if (!r.e0 || !r.e1) { on = false; return; }
     (void)hipEventRecord(r.e0, c->stream);

@@ -55,7 +55,8 @@ static int ensure_krylov(mgcnn_ctx* c, int m) {
 
 // Restarted FGMRES(m), right preconditioned by z = B(v / D), one Arnoldi process per problem.
 // Orthogonalisation: classical Gram-Schmidt applied twice (three passes over the basis).  The
-// small least-squares problems (Givens rotations) run on the host in f64.
+// small least-squares problems (Givens rotations) run on the host in f64.  Every launch covers
+// a compact list of the problems still extending their basis.
 int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int* iters_host,
                  double* relres_host, int* status_host) {
   const int m = std::max(1, std::min(c->opts.restart > 0 ? c->opts.restart : 30, KRYLOV_MAX_BASIS - 1));
@@ -68,7 +69,7 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
   const size_t vs = krylov_vpad(n) * B;      // stride between basis vectors (floats)
   const size_t zs = nn;                      // stride between preconditioned vectors
   const bool u64 = c->u64();
-  const double nodes = (double)nn;           // all problems; retired ones are skipped by the kernels
+  const double nodes1 = (double)n * n;       // nodes of one problem
   const int LD = KRYLOV_LD;
   // ||f||^2
   launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, n, B, nullptr, s);
@@ -88,30 +89,38 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
       sn((size_t)B * HL), hb((size_t)B * LD), hb2((size_t)B * LD), hb3((size_t)B * LD),
       sc((size_t)B * LD, 0.0),
       nw2(B, 0.0);
-  std::vector<int> kb(B);
+  std::vector<int> kb(B), list_live(B), list_cyc(B);
   auto Hij = [&](int b, int i, int j) -> double& { return H[((size_t)b * (HL + 1) + i) * HL + j]; };
   auto gi = [&](int b, int i) -> double& { return g[(size_t)b * (HL + 1) + i]; };
-  auto to_dev = [&](int* d, const std::vector<int>& h) {
-    return hipMemcpyAsync(d, h.data(), (size_t)B * 4, hipMemcpyHostToDevice, s);
+  // upload the compact list of the problems whose flag is set; returns its length.  The host
+  // buffer stays untouched until the next upload, which follows a stream synchronisation.
+  auto to_list = [&](int* d, std::vector<int>& buf, const std::vector<int>& flags, int& count) {
+    count = 0;
+    for (int b = 0; b < B; ++b)
+      if (flags[b]) buf[count++] = b;
+    if (count == 0) return hipSuccess;
+    return hipMemcpyAsync(d, buf.data(), (size_t)count * 4, hipMemcpyHostToDevice, s);
   };
   auto from_dev = [&](std::vector<double>& h) {
     return hipMemcpyAsync(h.data(), K.h, (size_t)B * LD * 8, hipMemcpyDeviceToHost, s);
   };
   while (true) {
     // true residual of every live problem, its norm, and the stopping rule
-    c->prof_live = 0;
+    int nact = 0;
+    HIP_TRY(c, to_list(K.act, list_live, act, nact));
+    if (nact == 0) break;
     {
-      Prof p(c, MGCNN_K_KRYLOV_RESIDUAL, 0, nodes * (12.0 + (u64 ? 8 : 4)));
-      launch_krylov_residual(c->d_a, c->d_b, f, u, u64, K.V, krylov_vpad(n), n, B, nullptr, s);
+      Prof p(c, MGCNN_K_KRYLOV_RESIDUAL, 0, nodes1 * nact * (12.0 + (u64 ? 8 : 4)));
+      launch_krylov_residual(c->d_a, c->d_b, f, u, u64, K.V, krylov_vpad(n), n, nact, K.act, s);
     }
-    HIP_TRY(c, to_dev(K.act, act));
     {
-      Prof p(c, MGCNN_K_KRYLOV_DOTS, 0, nodes * 4.0);
-      launch_gs_pass(0, K.V, K.V, vs, 0, n, B, nullptr, K.partial, K.h, K.act, s);
+      Prof p(c, MGCNN_K_KRYLOV_DOTS, 0, nodes1 * nact * 4.0);
+      launch_gs_pass(0, K.V, K.V, vs, 0, n, nact, nullptr, K.partial, K.h, K.act, s);
     }
     LAUNCH_CHECK(c);
     HIP_TRY(c, from_dev(hb));
     HIP_TRY(c, hipStreamSynchronize(s));
+    if (c->prof && (r = prof_drain(c))) return r;
     bool any = false;
     for (int b = 0; b < B; ++b) {
       cyc[b] = 0;
@@ -134,41 +143,42 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
     }
     if (!any) break;
     std::vector<int> live = cyc;                 // problems still extending their basis this cycle
-    c->prof_live = (int)std::count(live.begin(), live.end(), 1);
-    HIP_TRY(c, to_dev(K.cyc, cyc));
-    HIP_TRY(c, to_dev(K.act, live));
+    int ncyc = 0, nlive = 0;
+    HIP_TRY(c, to_list(K.cyc, list_cyc, cyc, ncyc));
+    HIP_TRY(c, to_list(K.act, list_live, live, nlive));
     for (int j = 0; j < m; ++j) {
       float* Vj = K.V + (size_t)j * vs;
       float* Vn = K.V + (size_t)(j + 1) * vs;
       float* Zj = K.Z + (size_t)j * zs;
+      const double nodes = nodes1 * nlive;
       // v_j /= |v_j| (in place) and z_j = B(v_j / D)
       HIP_TRY(c, hipMemcpyAsync(K.s, sc.data(), (size_t)B * LD * 8, hipMemcpyHostToDevice, s));
       {
         Prof p(c, MGCNN_K_SCALE_BY_DIAG, 0, nodes * 16.0);
-        launch_normalize_diag(c->d_a, c->d_b, Vj, c->d_rt, K.s, n, B, K.act, s);
+        launch_normalize_diag(c->d_a, c->d_b, Vj, c->d_rt, K.s, n, nlive, K.act, s);
       }
-      if ((r = vcycle(c, Zj, false, K.act, false))) return r;
+      if ((r = vcycle(c, Zj, false, K.act, nlive, false))) return r;
       // w = A z_j
       {
         Prof p(c, MGCNN_K_KRYLOV_APPLY_A, 0, nodes * 12.0);
-        launch_apply_A(c->d_a, c->d_b, Zj, Vn, krylov_vpad(n), n, B, K.act, s);
+        launch_apply_A(c->d_a, c->d_b, Zj, Vn, krylov_vpad(n), n, nlive, K.act, s);
       }
       // classical Gram-Schmidt applied twice, in three passes:
       //   h1 = V^T w ; w -= V h1 and h2 = V^T w ; w -= V h2 and |w|^2
       const int cnt = j + 1;
       {
         Prof p(c, MGCNN_K_KRYLOV_DOTS, cnt, nodes * 4.0 * (cnt + 1));
-        launch_gs_pass(0, Vn, K.V, vs, cnt, n, B, nullptr, K.partial, K.h, K.act, s);
+        launch_gs_pass(0, Vn, K.V, vs, cnt, n, nlive, nullptr, K.partial, K.h, K.act, s);
       }
       HIP_TRY(c, from_dev(hb));
       {
         Prof p(c, MGCNN_K_KRYLOV_ORTH, cnt, nodes * 4.0 * (cnt + 2));
-        launch_gs_pass(1, Vn, K.V, vs, cnt, n, B, K.h, K.partial, K.h, K.act, s);
+        launch_gs_pass(1, Vn, K.V, vs, cnt, n, nlive, K.h, K.partial, K.h, K.act, s);
       }
       HIP_TRY(c, from_dev(hb2));
       {
         Prof p(c, MGCNN_K_KRYLOV_ORTH, cnt, nodes * 4.0 * (cnt + 2));
-        launch_gs_pass(2, Vn, K.V, vs, cnt, n, B, K.h, K.partial, K.h, K.act, s);
+        launch_gs_pass(2, Vn, K.V, vs, cnt, n, nlive, K.h, K.partial, K.h, K.act, s);
       }
       LAUNCH_CHECK(c);
       HIP_TRY(c, from_dev(hb3));
@@ -208,8 +218,7 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
         else more = true;
       }
       if (!more || j == m - 1) break;
-      HIP_TRY(c, to_dev(K.act, live));
-      c->prof_live = (int)std::count(live.begin(), live.end(), 1);
+      HIP_TRY(c, to_list(K.act, list_live, live, nlive));
     }
     // y = R^-1 g (upper triangular, k_b x k_b) and u += Z y
     std::fill(sc.begin(), sc.end(), 0.0);
@@ -225,15 +234,13 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
       }
     }
     HIP_TRY(c, hipMemcpyAsync(K.s, sc.data(), (size_t)B * LD * 8, hipMemcpyHostToDevice, s));
-    c->prof_live = (int)std::count(cyc.begin(), cyc.end(), 1);
     {
-      Prof p(c, MGCNN_K_KRYLOV_COMBINE, kmax, nodes * (4.0 * kmax + 2.0 * (u64 ? 8 : 4)));
-      launch_combine(u, u64, K.Z, zs, kmax, n, B, K.s, K.cyc, s);
+      Prof p(c, MGCNN_K_KRYLOV_COMBINE, kmax, nodes1 * ncyc * (4.0 * kmax + 2.0 * (u64 ? 8 : 4)));
+      launch_combine(u, u64, K.Z, zs, kmax, n, ncyc, K.s, K.cyc, s);
     }
     LAUNCH_CHECK(c);
-    HIP_TRY(c, hipStreamSynchronize(s));      // sc is rewritten by the next cycle
+    HIP_TRY(c, hipStreamSynchronize(s));      // sc and the list buffers are rewritten next cycle
   }
-  c->prof_live = 0;
   bool diverged = false, notconv = false;
   for (int b = 0; b < B; ++b) {
     if (iters_host) iters_host[b] = iters[b];

@@ -11,8 +11,12 @@ namespace mg {
 constexpr int C = 16;                 // hidden channels of every state / setup tensor
 constexpr int NUM_SETUP_LAYERS = 4;   // tanh ResNet layers of the setup network
 
-// State storage type of the solve network (x, s).
-enum StateType : int { ST_F32 = 0, ST_BF16 = 1 };
+// State of the solve network (x, s): storage type and matrix-core arithmetic.
+//   ST_F32   float32 storage, float32 MFMA (16x16x4)
+//   ST_BF16  bf16 storage, bf16 MFMA with f32 accumulation
+//   ST_F32X  float32 storage, bf16 MFMA on a three-way bf16 split of both operands
+//            (float32-level products at the bf16 matrix rate)
+enum StateType : int { ST_F32 = 0, ST_BF16 = 1, ST_F32X = 2 };
 
 // Offsets (in floats) of every parameter tensor inside the flat weight vector.
 struct WeightOffsets {
@@ -25,6 +29,9 @@ WeightOffsets weight_offsets();
 typedef uint16_t bf16_t;
 
 // ---- launchers (all asynchronous on `st`) ------------------------------------------------
+// Batch convention: `active` is either null (the launch covers problems 0..B-1) or a device
+// list of B problem indices (the launch covers exactly those problems; retired problems are
+// left out of the grid instead of being skipped by every workgroup).
 
 // Setup: stencil features F [B][n][n][4] (f32) from a [B][n][n] and b [B][2].
 void launch_features(const float* a, const float* b, float* F, int n, int B, hipStream_t st);
@@ -45,16 +52,16 @@ void launch_conv16(ConvMode mode, StateType t, const void* x, const void* s, con
 void launch_prolong_add(StateType t, const void* xc, const float* WT, void* yf, int mc, int B,
                         const int* active, hipStream_t st);
 
-// Finest-level fused kernels: y = x1 + W*(s.x1) with x1 = W_in * rt computed on the fly;
-// and u += W_out * (v + W*(s.v)) without storing the up-smoothed state.
+// Finest-level down smoother with the reChannel-in conv folded in: y = x1 + W*(s.x1) with
+// x1 = W_in * rt computed on the staged tile.
 void launch_smooth_in(StateType t, const float* rt, const void* s, const float* Win, const float* W,
                       void* y, int m, int B, const int* active, hipStream_t st);
-void launch_smooth_out(StateType t, const void* v, const void* s, const float* W, const float* Wout,
-                       void* u, bool u_f64, int m, int B, const int* active, hipStream_t st);
 
 // u += W_out * x (16 -> 1 same-size conv), u f32 or f64; u = W_out * x when !accumulate.
+// flags (optional, indexed by problem): problems whose flag is 0 keep u unchanged.
 void launch_out_update(StateType t, const void* x, const float* Wout, void* u, bool u_f64,
-                       int n, int B, const int* active, hipStream_t st, bool accumulate = true);
+                       int n, int B, const int* active, hipStream_t st, bool accumulate = true,
+                       const int* flags = nullptr);
 
 // r = f - A(a,b) u ; rt = r / D (f32) ; partial[b][tile] = sum r^2 (f64).
 // u == nullptr means u = 0.  mode64: u is f64 and the arithmetic is f64; otherwise u is f32 and

@@ -71,7 +71,7 @@ static int ensure_train(mgcnn_ctx* c, int K) {
 }
 
 int forward_record(mgcnn_ctx* c, const float* f, float* u, int K) {
-  if (c->st() != ST_F32 || c->u64())
+  if (c->st() == ST_BF16 || c->u64())
     return fail(c, MGCNN_E_ARG, "forward(record): needs f32 state and f32 u");
   int r = ensure_train(c, K);
   if (r) return r;
@@ -80,7 +80,7 @@ int forward_record(mgcnn_ctx* c, const float* f, float* u, int K) {
   for (int k = 0; k < K; ++k) {
     HIP_TRY(c, hipMemcpyAsync(T.uk + (size_t)k * nn, u, nn * 4, hipMemcpyDeviceToDevice, c->stream));
     launch_residual(c->d_a, c->d_b, f, u, false, c->d_rt, c->d_partial, c->n, c->B, nullptr, c->stream);
-    if ((r = vcycle(c, u, false, nullptr))) return r;
+    if ((r = vcycle(c, u, false, nullptr, c->B))) return r;
   }
   T.K = K;
   T.f = f;

@@ -29,12 +29,13 @@ _lib = None
 class mgcnn_opts(ctypes.Structure):
     _fields_ = [("channels", ctypes.c_int), ("state_dtype", ctypes.c_int), ("u_dtype", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("method", ctypes.c_int), ("restart", ctypes.c_int)]
+                ("method", ctypes.c_int), ("restart", ctypes.c_int), ("f32_split", ctypes.c_int)]
 
 
 class mgcnn_kernel_stat(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("level", ctypes.c_int), ("launches", ctypes.c_int),
-                ("ms_total", ctypes.c_double), ("bytes_per_launch", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("bytes_per_launch", ctypes.c_double),
+                ("flops_per_launch", ctypes.c_double)]
 
 
 KERNEL_KINDS = {0: "residual", 1: "finalize", 2: "conv_in", 3: "smooth_down", 4: "restrict",
@@ -114,7 +115,8 @@ class Solver:
     """One library context (weights + workspace for one problem set)."""
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", use_graph: bool = False,
-                 check_every: int = 4, stream=None, method: str = "stationary", restart: int = 30):
+                 check_every: int = 4, stream=None, method: str = "stationary", restart: int = 30,
+                 f32_split: bool = True):
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -126,6 +128,7 @@ class Solver:
         o.check_every = int(check_every)
         o.method = {"stationary": 0, "fgmres": 1}[method]
         o.restart = int(restart)
+        o.f32_split = int(bool(f32_split))
         self.opts = o
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
@@ -262,7 +265,8 @@ class Solver:
         self._raise(self._L.mgcnn_profile_end(self._h, arr, max_stats, ctypes.byref(cnt)))
         return [dict(kind=KERNEL_KINDS.get(arr[i].kind, str(arr[i].kind)), level=arr[i].level,
                      launches=arr[i].launches, ms_total=arr[i].ms_total,
-                     bytes_per_launch=arr[i].bytes_per_launch) for i in range(min(cnt.value, max_stats))]
+                     bytes_per_launch=arr[i].bytes_per_launch, flops_per_launch=arr[i].flops_per_launch)
+                for i in range(min(cnt.value, max_stats))]
 
     @property
     def levels(self) -> int:

@@ -84,32 +84,36 @@ def test_residual_norms(udt):
     S.close()
 
 
+@pytest.mark.parametrize("split", [True, False])
 @pytest.mark.parametrize("n,B", [(3, 1), (15, 2), (31, 1), (63, 2), (127, 2)])
-def test_apply_network(n, B):
-    """One application of the solve network z = B(r / D)."""
-    say("apply", n, B)
+def test_apply_network(n, B, split):
+    """One application of the solve network z = B(r / D), f32 state with float32 matrix
+    instructions and with the three-way bf16 split."""
+    say("apply", n, B, "split" if split else "f32 mfma")
     a, b, f = batch("mixture127", n, B, seed=3)
     w = datagen.xavier_weights(16, 1)
     rng = np.random.default_rng(n)
     r = rng.standard_normal((B, n, n)).astype(np.float32)
-    S = Solver(w, state="f32")
+    S = Solver(w, state="f32", f32_split=split)
     S.setup(dev(a), b)
     z = S.apply(dev(r)).cpu().numpy()
     for p in range(B):
         ref = osv.Solver(w, a[p], b[p])
         exp = ref.correction(r[p].astype(np.float64))
+        say("  rel err", rel(z[p], exp))
         assert rel(z[p], exp) <= F32_TOL, (p, rel(z[p], exp))
     S.close()
 
 
+@pytest.mark.parametrize("split", [True, False])
 @pytest.mark.parametrize("K", [1, 2, 8])
-def test_forward_grf31(K):
+def test_forward_grf31(K, split):
     """31x31 lognormal GRF, b = (1,1), f ~ U(-1,1), Xavier weights: K fixed iterations."""
-    say("forward grf31 K", K)
+    say("forward grf31 K", K, "split" if split else "f32 mfma")
     a, b, f = batch("grf31", 31, 1)
     w = datagen.xavier_weights(16, 0)
     for udt in ("f32", "f64"):
-        S = Solver(w, state="f32", u=udt)
+        S = Solver(w, state="f32", u=udt, f32_split=split)
         S.setup(dev(a), b)
         u = torch.zeros((1, 31, 31), dtype=S.u_dtype, device="cuda")
         S.forward(dev(f), u, K)
