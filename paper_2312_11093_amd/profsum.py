@@ -2,8 +2,8 @@
 
     python -m paper_2312_11093_amd.profsum <run_kernel_trace.csv> [top]
 
-Prints launches, average and total duration per (kernel, grid size); the grid size
-separates the levels of the multigrid hierarchy.
+Prints launches, average and total duration per kernel, then per (kernel, grid size); the
+grid size separates the levels of the multigrid hierarchy and the number of live problems.
 """
 from __future__ import annotations
 
@@ -15,12 +15,22 @@ import sys
 def summarize(path: str, top: int = 25) -> str:
     rows = list(csv.DictReader(open(path)))
     agg = collections.defaultdict(lambda: [0, 0.0])
+    byname = collections.defaultdict(lambda: [0, 0.0])
     for r in rows:
-        key = (r["Kernel_Name"].split("(")[0], int(r["Grid_Size_X"]))
+        name = r["Kernel_Name"].split("(")[0]
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        key = (name, int(r["Grid_Size_X"]))
         agg[key][0] += 1
-        agg[key][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        agg[key][1] += us
+        byname[name][0] += 1
+        byname[name][1] += us
     total = sum(v[1] for v in agg.values())
-    out = [f"{'kernel':60s} {'grid_x':>10s} {'launches':>8s} {'avg_us':>10s} {'total_ms':>10s} {'share':>6s}"]
+    out = ["per kernel (all grid sizes):",
+           f"{'kernel':60s} {'launches':>8s} {'avg_us':>10s} {'total_ms':>10s} {'share':>6s}"]
+    for name, (cnt, us) in sorted(byname.items(), key=lambda kv: -kv[1][1])[:top]:
+        out.append(f"{name[:60]:60s} {cnt:8d} {us / cnt:10.1f} {us / 1e3:10.2f} {us / total:6.3f}")
+    out += ["", "per kernel and grid size (the grid separates levels and batch sizes):",
+            f"{'kernel':60s} {'grid_x':>10s} {'launches':>8s} {'avg_us':>10s} {'total_ms':>10s} {'share':>6s}"]
     for (name, grid), (cnt, us) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
         out.append(f"{name[:60]:60s} {grid:10d} {cnt:8d} {us / cnt:10.1f} {us / 1e3:10.2f} {us / total:6.3f}")
     out.append(f"total kernel time {total / 1e3:.2f} ms over {sum(v[0] for v in agg.values())} launches")
