@@ -24,63 +24,125 @@ size_t krylov_vpad(int n) {
 }
 int krylov_blocks(int n) { return (int)(krylov_vpad(n) / ((size_t)KG_ELEMS * KG_ITERS)); }
 
-// ---- stencil: y = A x, or y = f - A u ------------------------------------------------------
-// Divergence-form 5-point diffusion with harmonic face means plus first-order upwind
-// convection, f64 arithmetic; y is written with per-problem stride ystride.
-template <typename UT, bool RESIDUAL>
-__global__ __launch_bounds__(256) void kstencil_kernel(const float* __restrict__ a,
-                                                       const float* __restrict__ bvec,
-                                                       const float* __restrict__ f,
-                                                       const UT* __restrict__ x,
-                                                       float* __restrict__ y, size_t ystride, int n,
-                                                       int tiles_x, int tiles_per_prob,
-                                                       const int* __restrict__ active) {
+// ---- stencil passes ----------------------------------------------------------------------------
+// Divergence-form 5-point diffusion with harmonic face means plus first-order upwind convection,
+// f64 arithmetic.  Tiles of 256 columns x KW_ROWS rows; each thread walks one column, keeping the
+// rows above, at and below in registers, so every vertical face coefficient is formed once and
+// every value comes from HBM once.  Reciprocals: hardware estimate refined by two Newton steps.
+//   KW_APPLY:     y[b][ystride] = A x                      (x f32 [B][n][n])
+//   KW_RESIDUAL:  y[b][ystride] = f - A u                  (u f32 or f64 [B][n][n])
+//   KW_NORMALIZE: v[b][ystride] *= s[b];  rt = v / D       (rt [B][n][n])
+constexpr int KW_ROWS = 8;
+enum KwMode : int { KW_APPLY = 0, KW_RESIDUAL = 1, KW_NORMALIZE = 2 };
+
+__device__ __forceinline__ double krcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double kharm(double p, double q) { return (2.0 * p * q) * krcp(p + q); }
+
+template <typename XT, int MODE>
+__global__ __launch_bounds__(256) void kwalk_kernel(const float* __restrict__ a,
+                                                    const float* __restrict__ bvec,
+                                                    const float* __restrict__ f,
+                                                    const XT* __restrict__ x,
+                                                    float* __restrict__ y, size_t ystride,
+                                                    float* __restrict__ rt,
+                                                    const double* __restrict__ sc, int n,
+                                                    int tiles_x, int tiles_per_prob,
+                                                    const int* __restrict__ active) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
-  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
-  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
-  if (i >= n || j >= n) return;
+  const int j = (tile % tiles_x) * 256 + threadIdx.x;
+  const int i0 = (tile / tiles_x) * KW_ROWS;
+  if (j >= n) return;
   const size_t base = (size_t)b * n * n;
   const float* A = a + base;
-  const UT* X = x + base;
-  const int ij = i * n + j;
-  auto H = [](double p, double q) { return 2.0 * p * q / (p + q); };
-  const double ac = A[ij];
-  const double aE = (j + 1 < n) ? H(ac, A[ij + 1]) : ac;
-  const double aW = (j > 0) ? H(ac, A[ij - 1]) : ac;
-  const double aN = (i + 1 < n) ? H(ac, A[ij + n]) : ac;
-  const double aS = (i > 0) ? H(ac, A[ij - n]) : ac;
-  const double xc = X[ij];
-  const double xE = (j + 1 < n) ? (double)X[ij + 1] : 0.0;
-  const double xW = (j > 0) ? (double)X[ij - 1] : 0.0;
-  const double xN = (i + 1 < n) ? (double)X[ij + n] : 0.0;
-  const double xS = (i > 0) ? (double)X[ij - n] : 0.0;
   const double ih = (double)(n + 1), ih2 = ih * ih;
   const double bx = bvec[2 * b], by = bvec[2 * b + 1];
   const double bxp = bx > 0 ? bx : 0, bxm = bx < 0 ? bx : 0;
   const double byp = by > 0 ? by : 0, bym = by < 0 ? by : 0;
-  const double v = ((aE + aW + aN + aS) * xc - aE * xE - aW * xW - aN * xN - aS * xS) * ih2 +
-                   (bxp * (xc - xW) + bxm * (xE - xc) + byp * (xc - xS) + bym * (xN - xc)) * ih;
-  y[(size_t)b * ystride + ij] = RESIDUAL ? (float)((double)f[base + ij] - v) : (float)v;
+  const double conv_diag = (bxp - bxm + byp - bym) * ih;
+  const bool hasE = j + 1 < n, hasW = j > 0;
+  const int dE = hasE ? 1 : 0, dW = hasW ? 1 : 0;          // clamped offsets: branch-free loads
+  const XT* X = (MODE == KW_NORMALIZE) ? nullptr : x + base;
+  double ac = A[i0 * n + j];
+  double aS = (i0 > 0) ? kharm(ac, (double)A[(i0 - 1) * n + j]) : ac;
+  double xc = 0.0, xs = 0.0;
+  if constexpr (MODE != KW_NORMALIZE) {
+    xc = X[i0 * n + j];
+    xs = (i0 > 0) ? (double)X[(i0 - 1) * n + j] : 0.0;
+  }
+  const double sb = (MODE == KW_NORMALIZE) ? sc[(size_t)b * KR_LD] : 0.0;
+#pragma unroll 2
+  for (int r = 0; r < KW_ROWS; ++r) {
+    const int i = i0 + r;
+    if (i >= n) break;
+    const int ij = i * n + j;
+    const bool hasN = i + 1 < n;
+    const int dN = hasN ? n : 0;
+    const double an = A[ij + dN];
+    const double aN = hasN ? kharm(ac, an) : ac;
+    const double aE = hasE ? kharm(ac, (double)A[ij + dE]) : ac;
+    const double aW = hasW ? kharm(ac, (double)A[ij - dW]) : ac;
+    const double sa = aE + aW + aN + aS;
+    if constexpr (MODE == KW_NORMALIZE) {
+      float* vp = y + (size_t)b * ystride + ij;
+      const double v = (double)*vp * sb;
+      *vp = (float)v;
+      rt[base + ij] = (float)(v * krcp(sa * ih2 + conv_diag));
+    } else {
+      const double xn = hasN ? (double)X[ij + dN] : 0.0;
+      const double xE = hasE ? (double)X[ij + dE] : 0.0;
+      const double xW = hasW ? (double)X[ij - dW] : 0.0;
+      const double Ax = (sa * xc - aE * xE - aW * xW - aN * xn - aS * xs) * ih2 +
+                        (bxp * (xc - xW) + bxm * (xE - xc) + byp * (xc - xs) + bym * (xn - xc)) * ih;
+      y[(size_t)b * ystride + ij] = (MODE == KW_RESIDUAL) ? (float)((double)f[base + ij] - Ax) : (float)Ax;
+      xs = xc; xc = xn;
+    }
+    ac = an; aS = aN;
+  }
+}
+
+static void kwalk_grid(int n, int B, dim3& grid, int& tx, int& tpp) {
+  tx = (n + 255) / 256;
+  tpp = tx * ((n + KW_ROWS - 1) / KW_ROWS);
+  grid = dim3(tpp * B);
 }
 
 void launch_apply_A(const float* a, const float* b, const float* x, float* y, size_t ystride, int n,
                     int B, const int* active, hipStream_t st) {
-  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
-  hipLaunchKernelGGL((kstencil_kernel<float, false>), dim3(tx * ty * B), dim3(256), 0, st, a, b,
-                     (const float*)nullptr, x, y, ystride, n, tx, tx * ty, active);
+  dim3 grid; int tx, tpp;
+  kwalk_grid(n, B, grid, tx, tpp);
+  hipLaunchKernelGGL((kwalk_kernel<float, KW_APPLY>), grid, dim3(256), 0, st, a, b, (const float*)nullptr,
+                     x, y, ystride, (float*)nullptr, (const double*)nullptr, n, tx, tpp, active);
 }
 
 void launch_krylov_residual(const float* a, const float* b, const float* f, const void* u, bool u_f64,
                             float* r, size_t rstride, int n, int B, const int* active, hipStream_t st) {
-  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
+  dim3 grid; int tx, tpp;
+  kwalk_grid(n, B, grid, tx, tpp);
   if (u_f64)
-    hipLaunchKernelGGL((kstencil_kernel<double, true>), dim3(tx * ty * B), dim3(256), 0, st, a, b, f,
-                       (const double*)u, r, rstride, n, tx, tx * ty, active);
+    hipLaunchKernelGGL((kwalk_kernel<double, KW_RESIDUAL>), grid, dim3(256), 0, st, a, b, f,
+                       (const double*)u, r, rstride, (float*)nullptr, (const double*)nullptr, n, tx, tpp,
+                       active);
   else
-    hipLaunchKernelGGL((kstencil_kernel<float, true>), dim3(tx * ty * B), dim3(256), 0, st, a, b, f,
-                       (const float*)u, r, rstride, n, tx, tx * ty, active);
+    hipLaunchKernelGGL((kwalk_kernel<float, KW_RESIDUAL>), grid, dim3(256), 0, st, a, b, f,
+                       (const float*)u, r, rstride, (float*)nullptr, (const double*)nullptr, n, tx, tpp,
+                       active);
+}
+
+void launch_normalize_diag(const float* a, const float* b, float* v, float* rt, const double* s, int n,
+                           int B, const int* active, hipStream_t st) {
+  dim3 grid; int tx, tpp;
+  kwalk_grid(n, B, grid, tx, tpp);
+  hipLaunchKernelGGL((kwalk_kernel<float, KW_NORMALIZE>), grid, dim3(256), 0, st, a, b,
+                     (const float*)nullptr, (const float*)nullptr, v, krylov_vpad(n), rt, s, n, tx, tpp,
+                     active);
 }
 
 // ---- Gram-Schmidt passes -----------------------------------------------------------------------
@@ -272,46 +334,6 @@ int launch_gs_pass(int mode, float* w, const float* V, size_t vstride, int cnt, 
   hipLaunchKernelGGL(kgs_reduce_kernel, dim3((waves + 3) / 4), dim3(256), 0, st, partial, blocks, total,
                      B, out, active);
   return 0;
-}
-
-// v *= s[b] in place (stride vpad) and rt = v / D ([B][n][n]).  D as in the operator: sum of
-// face coefficients / h^2 + (|bx| + |by|) / h.
-__global__ __launch_bounds__(256) void knormalize_diag_kernel(const float* __restrict__ a,
-                                                              const float* __restrict__ bvec,
-                                                              float* __restrict__ v, size_t vpad,
-                                                              float* __restrict__ rt,
-                                                              const double* __restrict__ s, int n,
-                                                              int tiles_x, int tiles_per_prob,
-                                                              const int* __restrict__ active) {
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
-  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
-  const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
-  const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
-  if (i >= n || j >= n) return;
-  const size_t base = (size_t)b * n * n;
-  const float* A = a + base;
-  const int ij = i * n + j;
-  auto H = [](double p, double q) { return 2.0 * p * q / (p + q); };
-  const double ac = A[ij];
-  const double aE = (j + 1 < n) ? H(ac, A[ij + 1]) : ac;
-  const double aW = (j > 0) ? H(ac, A[ij - 1]) : ac;
-  const double aN = (i + 1 < n) ? H(ac, A[ij + n]) : ac;
-  const double aS = (i > 0) ? H(ac, A[ij - n]) : ac;
-  const double ih = (double)(n + 1);
-  const double D = (aE + aW + aN + aS) * ih * ih +
-                   (fabs((double)bvec[2 * b]) + fabs((double)bvec[2 * b + 1])) * ih;
-  float* vp = v + (size_t)b * vpad + ij;
-  const double x = (double)*vp * s[(size_t)b * KR_LD];
-  *vp = (float)x;
-  rt[base + ij] = (float)(x / D);
-}
-
-void launch_normalize_diag(const float* a, const float* b, float* v, float* rt, const double* s, int n,
-                           int B, const int* active, hipStream_t st) {
-  const int tx = (n + 63) / 64, ty = (n + 3) / 4;
-  hipLaunchKernelGGL(knormalize_diag_kernel, dim3(tx * ty * B), dim3(256), 0, st, a, b, v,
-                     krylov_vpad(n), rt, s, n, tx, tx * ty, active);
 }
 
 // u[b] += sum_{j<cnt} y[b][j] Z_j[b] for the listed problems (terms with y = 0 are skipped:
