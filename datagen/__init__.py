@@ -33,11 +33,12 @@ import numpy as np
 __all__ = [
     "rng_for", "grf", "blocks_lognormal", "checkerboard", "inclusions",
     "mixture", "velocity", "rhs", "mldata", "weight_shapes", "num_weights",
-    "xavier_weights", "Problem", "make_batch", "WORKLOADS", "levels_for",
+    "xavier_weights", "Problem", "make_batch", "WORKLOADS", "levels_for", "var_sizes", "VAR_SIZES",
 ]
 
 WEIGHT_STREAM = 0x5EED
-STREAM_A, STREAM_B, STREAM_F = 0, 1, 2
+STREAM_A, STREAM_B, STREAM_F, STREAM_N = 0, 1, 2, 3
+VAR_SIZES = (63, 127, 255, 511, 1023, 2047)
 
 
 def rng_for(seed: int, workload: int, problem: int, stream: int) -> np.random.Generator:
@@ -253,6 +254,13 @@ def make_problem(workload: str, n: int, index: int, seed: int = 0) -> Problem:
     b = velocity(rng_for(seed, w.wid, index, STREAM_B), w.vel)
     f = rhs(n, rng_for(seed, w.wid, index, STREAM_F), w.f_kind)
     return Problem(n, a.astype(np.float32), b.astype(np.float32), f.astype(np.float32))
+
+
+def var_sizes(count: int, seed: int = 0, sizes=VAR_SIZES, workload: str = "mixture_var") -> list[int]:
+    """Grid sizes of an uneven-size batch: problem i draws its n uniformly from `sizes` with the
+    generator of (seed, workload, i, size stream)."""
+    w = WORKLOADS[workload]
+    return [int(sizes[rng_for(seed, w.wid, i, STREAM_N).integers(0, len(sizes))]) for i in range(count)]
 
 
 def make_batch(workload: str, n: int, batch: int, seed: int = 0, first: int = 0):

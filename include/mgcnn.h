@@ -194,6 +194,34 @@ const char *mgcnn_status_string(int status);
 const char *mgcnn_last_error(const mgcnn_ctx *ctx);
 void mgcnn_destroy(mgcnn_ctx *ctx);
 
+/* ---- Uneven-size batches ---------------------------------------------------------------
+ * One call for problems of different sizes n_i = 2^k - 1 (each still the method of Sec. 2.2
+ * and Alg. 2 / Alg. 3 per problem).  The group buckets the problems by size; every bucket is
+ * one batched problem set on its own HIP stream (default priority), and the buckets are solved
+ * concurrently, each from its own host thread.  Results per problem are identical to solving
+ * that problem on its own with the same options. */
+typedef struct mgcnn_group mgcnn_group;
+
+/* Create a group: options and weights as for mgcnn_create (copied).  The group's streams are
+ * its own; `hip_stream` (NULL = default) is the stream the inputs were produced on: setup and
+ * solve wait for it before reading them. */
+int mgcnn_group_create(mgcnn_group **group, const mgcnn_opts *opts, const float *weights_host,
+                       void *hip_stream);
+/* Setup for `count` problems: a[i] device pointer to the n_host[i] x n_host[i] coefficients of
+ * problem i (a > 0), b_host [count][2].  Coefficients are copied into per-size buckets.
+ * E_SIZE if some n is not 2^k - 1 or above 4095; E_ARG for null pointers or count < 1. */
+int mgcnn_group_setup(mgcnn_group *group, const float *const *a, const float *b_host,
+                      const int *n_host, int count);
+/* Solve every problem of the last setup: f[i] (float32) and u[i] (float32 or float64 per
+ * opts.u_dtype; initial guess in, last iterate out) are device pointers of problem i.  Stopping
+ * rule, per-problem outputs and return value as for mgcnn_solve.  Blocks the host. */
+int mgcnn_group_solve(mgcnn_group *group, const float *const *f, void *const *u, double tol,
+                      int maxit, int *iters_host, double *relres_host, int *status_host);
+/* Number of size buckets of the last setup. */
+int mgcnn_group_buckets(const mgcnn_group *group);
+const char *mgcnn_group_last_error(const mgcnn_group *group);
+void mgcnn_group_destroy(mgcnn_group *group);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,4 +3,4 @@ library (include/mgcnn.h), with a thin ctypes binding.
 
     from paper_2312_11093_amd import Solver
 """
-from .mgcnn import Solver, MGCNNError, lib  # noqa: F401
+from .mgcnn import GroupSolver, Solver, MGCNNError, lib  # noqa: F401

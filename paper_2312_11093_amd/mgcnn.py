@@ -73,6 +73,16 @@ EXPORTS = {
     "mgcnn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mgcnn_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "mgcnn_destroy": (None, [ctypes.c_void_p]),
+    "mgcnn_group_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(mgcnn_opts),
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "mgcnn_group_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int]),
+    "mgcnn_group_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "mgcnn_group_buckets": (ctypes.c_int, [ctypes.c_void_p]),
+    "mgcnn_group_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "mgcnn_group_destroy": (None, [ctypes.c_void_p]),
 }
 
 
@@ -271,3 +281,83 @@ class Solver:
     @property
     def levels(self) -> int:
         return self._L.mgcnn_levels(self._h)
+
+
+class GroupSolver:
+    """Problems of different sizes in one call (mgcnn_group_*): bucketed by size, one batched
+    problem set per size on its own stream, buckets solved concurrently."""
+
+    def __init__(self, weights, state: str = "f32", u: str = "f64", method: str = "stationary",
+                 restart: int = 30, check_every: int = 4, f32_split: bool = True, stream=None):
+        import torch
+        self._L = lib()
+        o = mgcnn_opts()
+        self._L.mgcnn_default_opts(ctypes.byref(o))
+        o.state_dtype = {"f32": F32, "bf16": BF16}[state]
+        o.u_dtype = {"f32": U_F32, "f64": U_F64}[u]
+        o.method = {"stationary": 0, "fgmres": 1}[method]
+        o.restart = int(restart)
+        o.check_every = int(check_every)
+        o.f32_split = int(bool(f32_split))
+        self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        st = self._L.mgcnn_group_create(ctypes.byref(h), ctypes.byref(o), w.ctypes.data,
+                                        ctypes.c_void_p(self._stream.cuda_stream))
+        if st != OK:
+            raise MGCNNError(st, self._L.mgcnn_status_string(st).decode())
+        self._h = h
+        self.count = 0
+
+    def _raise(self, st):
+        if st not in (OK, NOT_CONVERGED):
+            raise MGCNNError(st, self._L.mgcnn_group_last_error(self._h).decode())
+        return st
+
+    @staticmethod
+    def _ptrs(ts):
+        return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def setup(self, a_list, b):
+        """a_list: list of (n_i, n_i) float32 device tensors; b: (count, 2) host array."""
+        import torch
+        for t in a_list:
+            _check_dev(t, torch.float32, "a")
+        n = np.asarray([t.shape[-1] for t in a_list], dtype=np.int32)
+        bh = np.ascontiguousarray(np.asarray(b, dtype=np.float32).reshape(len(a_list), 2))
+        self._a = list(a_list)
+        self._raise(self._L.mgcnn_group_setup(self._h, self._ptrs(self._a), bh.ctypes.data,
+                                              n.ctypes.data, len(a_list)))
+        self.count = len(a_list)
+
+    def solve(self, f_list, u_list, tol: float, maxit: int):
+        """Returns (status, iters[count], relres[count], per-problem status[count])."""
+        import torch
+        for t in f_list:
+            _check_dev(t, torch.float32, "f")
+        for t in u_list:
+            _check_dev(t, self.u_dtype, "u")
+        it = np.zeros(self.count, np.int32)
+        rr = np.zeros(self.count, np.float64)
+        ps = np.zeros(self.count, np.int32)
+        st = self._L.mgcnn_group_solve(self._h, self._ptrs(f_list), self._ptrs(u_list), float(tol), int(maxit),
+                                       it.ctypes.data, rr.ctypes.data, ps.ctypes.data)
+        if st not in (OK, NOT_CONVERGED, E_DIVERGED):
+            self._raise(st)
+        return st, it, rr, ps
+
+    @property
+    def buckets(self) -> int:
+        return self._L.mgcnn_group_buckets(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mgcnn_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

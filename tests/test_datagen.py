@@ -64,3 +64,11 @@ def test_levels():
     assert datagen.levels_for(1023) == 10 and datagen.levels_for(31) == 5
     with pytest.raises(ValueError):
         datagen.levels_for(1000)
+
+
+def test_var_sizes_seeded_and_in_range():
+    s1 = datagen.var_sizes(256, seed=0)
+    s2 = datagen.var_sizes(256, seed=0)
+    assert s1 == s2 and set(s1) <= set(datagen.VAR_SIZES)
+    assert len(set(s1)) == len(datagen.VAR_SIZES)          # 256 draws hit every size
+    assert datagen.var_sizes(8, seed=1) != datagen.var_sizes(8, seed=0)

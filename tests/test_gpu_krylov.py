@@ -93,3 +93,20 @@ def test_fgmres_maxit_and_args():
     S.close()
     with pytest.raises(M.MGCNNError):
         Solver(vcycle_weights(), method="fgmres", restart=64)
+
+
+def test_single_4095_to_1e10():
+    """One 4095^2 problem (lognormal GRF, length 0.05, variance 2, b = (1, 1)) to relative
+    residual 1e-10 with FGMRES and f32 state; the oracle recomputes the residual in f64."""
+    say("4095^2 to 1e-10")
+    p = datagen.make_problem("grf4095", 4095, 0, 0)
+    S = Solver(vcycle_weights(), state="f32", u="f64", method="fgmres", restart=30)
+    S.setup(dev(p.a).view(1, 4095, 4095), p.b.reshape(1, 2))
+    u = torch.zeros((1, 4095, 4095), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(p.f).view(1, 4095, 4095), u, 1e-10, 1000)
+    say("  iters", int(it[0]), "relres", float(rr[0]))
+    assert st == M.OK
+    rho = osv.relres(p.a, p.b, p.f, u[0].cpu().numpy())
+    say("  oracle relres", rho)
+    assert rho <= 1e-10 * (1 + 1e-5)
+    S.close()
