@@ -38,7 +38,9 @@ def load_weights(spec):
     import datagen
     from paper_2312_11093_amd.handbuilt import vcycle_weights
     if spec == "handbuilt":
-        return vcycle_weights(), "hand-set coefficient-aware V(1,1) cycle (omega 0.8)"
+        import inspect
+        om = inspect.signature(vcycle_weights).parameters["omega"].default
+        return vcycle_weights(), f"hand-set coefficient-aware V(1,1) cycle (omega {om})"
     if spec == "xavier":
         return datagen.xavier_weights(16, 0), "xavier-seed0 (untrained)"
     return np.load(spec, allow_pickle=False).astype(np.float32), os.path.relpath(os.path.abspath(spec), ROOT)

@@ -77,6 +77,9 @@ typedef struct {
   int f32_split;    /* MGCNN_F32 state only: 1 = 16->16 convs on bf16 matrix cores with both
                        operands split into three bf16 parts (float32-level products, several
                        times the f32 matrix rate); 0 = float32 matrix instructions */
+  int s_bf16;       /* MGCNN_F32 state only: 1 = keep the setup tensors s_l in bf16 (rounded once
+                       after the setup network; the network stays a fixed linear operator, so a
+                       solve still reaches its tolerance), halving their HBM traffic; 0 = f32 */
 } mgcnn_opts;
 
 /* Default options: 16 channels, f32 state (split-bf16 matrix arithmetic), f64 u, graphs off,

@@ -16,6 +16,8 @@
 //                    setup layer y = x + tanh(W * x + beta)  (Alg. 2, Eq. (6))
 //   conv16_restrict: y = W *_{stride 2, no padding} x       (RCNN, Sec. 2.4)
 //   prolong_add    : y += W^T-conv_{stride 2} x              (TCNN, Sec. 2.4, Eq. (3))
+#include <type_traits>
+
 #include "mgcnn_internal.h"
 #include "mgcnn_device.h"
 
@@ -230,9 +232,10 @@ struct SameCfg {
   static constexpr int NSEG = TW / 16, NTASK = TH * NSEG, TPW = NTASK / 4;
 };
 
-template <int ST, int MODE>
+// SBF: s stored as bf16 while the state is f32 (f32 storage only; the bf16 state has bf16 s).
+template <int ST, int MODE, bool SBF = false>
 __global__ __launch_bounds__(256) void conv16_same_kernel(
-    const typename Frag<ST>::elem* __restrict__ x, const typename Frag<ST>::elem* __restrict__ s,
+    const typename Frag<ST>::elem* __restrict__ x, const void* __restrict__ s,
     const float* __restrict__ W, const float* __restrict__ bias,
     typename Frag<ST>::elem* __restrict__ y, int m, int tiles_x, int tiles_per_prob,
     const int* __restrict__ active) {
@@ -247,7 +250,8 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
   const int row0 = (tile / tiles_x) * K::TH, col0 = (tile % tiles_x) * K::TW;
   const size_t pbase = (size_t)b * m * m * C;     // problem offset in elements
   const E* Xb = x + pbase;
-  const E* Sb = (MODE == CM_SMOOTH) ? s + pbase : nullptr;
+  const E* Sb = (MODE == CM_SMOOTH && !SBF) ? (const E*)s + pbase : nullptr;
+  const uint16_t* Sh = (MODE == CM_SMOOTH && SBF) ? (const uint16_t*)s + pbase : nullptr;
   E* Yb = y + pbase;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int px = lane & 15, g = lane >> 4;
@@ -262,7 +266,8 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
     const bool ok = k < K::NCHUNK && gi >= 0 && gi < m && gj >= 0 && gj < m;
     const int gp = ok ? gi * m + gj : 0;
     xv[r] = ok ? CK::load(Xb, gp, h) : CK::zero();
-    if constexpr (MODE == CM_SMOOTH) sv[r] = ok ? CK::load(Sb, gp, h) : CK::zero();
+    if constexpr (MODE == CM_SMOOTH && !SBF) sv[r] = ok ? CK::load(Sb, gp, h) : CK::zero();
+    if constexpr (MODE == CM_SMOOTH && SBF) sv[r] = ok ? ld4(Sh, gp, h) : CK::zero();   // 4 bf16 channels
   }
   // 2. prefetch the skip operand (centre pixels) of this wave's output segments
   float4 xc[K::TPW];
@@ -487,9 +492,9 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
 // rt with a two-pixel halo, so x1 never travels through HBM; x1 at the output pixels is kept in
 // LDS for the skip term.
 // ------------------------------------------------------------------------------------------
-template <int ST>
+template <int ST, bool SBF = false>
 __global__ __launch_bounds__(256) void smooth_in_kernel(
-    const float* __restrict__ rt, const typename Frag<ST>::elem* __restrict__ s,
+    const float* __restrict__ rt, const void* __restrict__ s,
     const float* __restrict__ Win, const float* __restrict__ W,
     typename Frag<ST>::elem* __restrict__ y, int m, int tiles_x, int tiles_per_prob,
     const int* __restrict__ active) {
@@ -507,7 +512,8 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
   const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int row0 = (tile / tiles_x) * K::TH, col0 = (tile % tiles_x) * K::TW;
   const size_t pbase = (size_t)b * m * m;
-  const E* Sb = s + pbase * C;
+  typedef typename std::conditional<SBF, uint16_t, E>::type SE;   // storage type of s
+  const SE* Sb = (const SE*)s + pbase * C;
   E* Yb = y + pbase * C;
   const float* Rb = rt + pbase;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -610,7 +616,7 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
 // ------------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------------
-template <int ST>
+template <int ST, bool SBF = false>
 static void conv16_launch(ConvMode mode, const void* x, const void* s, const float* W, const float* bias,
                           void* y, int m, int B, const int* active, hipStream_t st) {
   typedef typename Frag<ST>::elem E;
@@ -625,40 +631,51 @@ static void conv16_launch(ConvMode mode, const void* x, const void* s, const flo
   typedef SameCfg<ST> K;
   const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
   if (mode == CM_SMOOTH)
-    hipLaunchKernelGGL((conv16_same_kernel<ST, CM_SMOOTH>), dim3(tx * ty * B), dim3(256), 0, st,
-                       (const E*)x, (const E*)s, W, bias, (E*)y, m, tx, tx * ty, active);
-  else if constexpr (ST != ST_BF16)
+    hipLaunchKernelGGL((conv16_same_kernel<ST, CM_SMOOTH, SBF>), dim3(tx * ty * B), dim3(256), 0, st,
+                       (const E*)x, s, W, bias, (E*)y, m, tx, tx * ty, active);
+  else if constexpr (ST != ST_BF16 && !SBF)
     hipLaunchKernelGGL((conv16_same_kernel<ST, CM_TANH>), dim3(tx * ty * B), dim3(256), 0, st,
-                       (const E*)x, (const E*)nullptr, W, bias, (E*)y, m, tx, tx * ty, active);
+                       (const E*)x, (const void*)nullptr, W, bias, (E*)y, m, tx, tx * ty, active);
 }
 
 void launch_conv16(ConvMode mode, StateType st_, const void* x, const void* s, const float* W,
-                   const float* bias, void* y, int m, int B, const int* active, hipStream_t st) {
+                   const float* bias, void* y, int m, int B, const int* active, hipStream_t st,
+                   bool s_bf16) {
   // the setup network's tanh layers run in f32.  With f32 storage only the same-size smoothers
   // use the split (measured faster there); the restriction keeps f32 MFMA (larger LDS tile,
   // lower occupancy with three planes).
-  if (mode == CM_TANH || st_ == ST_F32 || (st_ == ST_F32X && mode == CM_RESTRICT))
-    conv16_launch<ST_F32>(mode, x, s, W, bias, y, m, B, active, st);
-  else if (st_ == ST_F32X) conv16_launch<ST_F32X>(mode, x, s, W, bias, y, m, B, active, st);
-  else conv16_launch<ST_BF16>(mode, x, s, W, bias, y, m, B, active, st);
+  const bool sb = s_bf16 && st_ != ST_BF16 && mode == CM_SMOOTH;
+  if (mode == CM_TANH || st_ == ST_F32 || (st_ == ST_F32X && mode == CM_RESTRICT)) {
+    if (sb) conv16_launch<ST_F32, true>(mode, x, s, W, bias, y, m, B, active, st);
+    else conv16_launch<ST_F32>(mode, x, s, W, bias, y, m, B, active, st);
+  } else if (st_ == ST_F32X) {
+    if (sb) conv16_launch<ST_F32X, true>(mode, x, s, W, bias, y, m, B, active, st);
+    else conv16_launch<ST_F32X>(mode, x, s, W, bias, y, m, B, active, st);
+  } else {
+    conv16_launch<ST_BF16>(mode, x, s, W, bias, y, m, B, active, st);
+  }
 }
 
-template <int ST>
+template <int ST, bool SBF = false>
 static void smooth_in_launch(const float* rt, const void* s, const float* Win, const float* W, void* y,
                              int m, int B, const int* active, hipStream_t st) {
   typedef SameCfg<ST> K;
   typedef typename Frag<ST>::elem E;
   const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
-  hipLaunchKernelGGL(smooth_in_kernel<ST>, dim3(tx * ty * B), dim3(256), 0, st, rt, (const E*)s, Win, W,
+  hipLaunchKernelGGL((smooth_in_kernel<ST, SBF>), dim3(tx * ty * B), dim3(256), 0, st, rt, s, Win, W,
                      (E*)y, m, tx, tx * ty, active);
 }
 
 void launch_smooth_in(StateType st_, const float* rt, const void* s, const float* Win, const float* W,
-                      void* y, int m, int B, const int* active, hipStream_t st) {
+                      void* y, int m, int B, const int* active, hipStream_t st, bool s_bf16) {
   // f32 storage: f32 MFMA (the split variant measured slower: its three LDS planes halve the
   // occupancy of this kernel)
-  if (st_ == ST_F32 || st_ == ST_F32X) smooth_in_launch<ST_F32>(rt, s, Win, W, y, m, B, active, st);
-  else smooth_in_launch<ST_BF16>(rt, s, Win, W, y, m, B, active, st);
+  if (st_ == ST_F32 || st_ == ST_F32X) {
+    if (s_bf16) smooth_in_launch<ST_F32, true>(rt, s, Win, W, y, m, B, active, st);
+    else smooth_in_launch<ST_F32>(rt, s, Win, W, y, m, B, active, st);
+  } else {
+    smooth_in_launch<ST_BF16>(rt, s, Win, W, y, m, B, active, st);
+  }
 }
 
 template <int ST>

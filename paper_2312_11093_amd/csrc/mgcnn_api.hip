@@ -150,7 +150,7 @@ int ensure_problem(mgcnn_ctx* c, int n, int B) {
   c->s.assign(L, nullptr); c->xin.assign(L, nullptr); c->xdn.assign(L, nullptr);
   for (int l = 0; l < L; ++l) {
     const size_t bytes = (size_t)c->nl[l] * c->nl[l] * B * C * c->state_bytes();
-    if ((r = alloc(c, &c->s[l], bytes))) return r;
+    if ((r = alloc(c, &c->s[l], (size_t)c->nl[l] * c->nl[l] * B * C * c->s_bytes()))) return r;
     if ((r = alloc(c, &c->xin[l], bytes))) return r;
     if ((r = alloc(c, &c->xdn[l], bytes))) return r;
   }
@@ -207,6 +207,8 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool
   const int L = c->L, B = count;
   hipStream_t s = c->stream;
   const double S = (double)c->state_bytes() * C;        // bytes of one 16-channel pixel
+  const double SS = (double)c->s_bytes() * C;            // bytes of one pixel of s
+  const bool sb = c->s16() && st != ST_BF16;             // f32 state reading bf16 s
   // algorithmic flops per node: 16 -> 16 3x3 conv (multiply-add = 2), smoother adds s . x and
   // the skip, 1 <-> 16 3x3 conv
   const double FL_CONV = 2.0 * 9 * C * C, FL_SMOOTH = FL_CONV + 2.0 * C, FL_IN = 2.0 * 9 * C;
@@ -214,13 +216,13 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool
   for (int l = 0; l < L; ++l) {
     if (l == 0) {
       // finest level: reChannel-in folded into the down smoother
-      Prof p(c, MGCNN_K_SMOOTH_IN, 0, nodes(0) * (4.0 + 2.0 * S), nodes(0) * (FL_SMOOTH + FL_IN));
+      Prof p(c, MGCNN_K_SMOOTH_IN, 0, nodes(0) * (4.0 + S + SS), nodes(0) * (FL_SMOOTH + FL_IN));
       launch_smooth_in(st, c->d_rt, c->s[0], c->W(c->off.solve_in), c->W(c->off.smooth_down), c->xdn[0],
-                       c->nl[0], B, active, s);
+                       c->nl[0], B, active, s, sb);
     } else {
-      Prof p(c, MGCNN_K_SMOOTH_DOWN, l, nodes(l) * 3.0 * S, nodes(l) * FL_SMOOTH);
+      Prof p(c, MGCNN_K_SMOOTH_DOWN, l, nodes(l) * (2.0 * S + SS), nodes(l) * FL_SMOOTH);
       launch_conv16(CM_SMOOTH, st, c->xin[l], c->s[l], c->W(c->off.smooth_down), nullptr, c->xdn[l],
-                    c->nl[l], B, active, s);
+                    c->nl[l], B, active, s, sb);
     }
     if (l < L - 1) {
       Prof p(c, MGCNN_K_RESTRICT, l, (nodes(l) + nodes(l + 1)) * S, nodes(l + 1) * FL_CONV);
@@ -229,9 +231,9 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool
     }
   }
   {
-    Prof p(c, MGCNN_K_SMOOTH_UP, L - 1, nodes(L - 1) * 3.0 * S, nodes(L - 1) * FL_SMOOTH);
+    Prof p(c, MGCNN_K_SMOOTH_UP, L - 1, nodes(L - 1) * (2.0 * S + SS), nodes(L - 1) * FL_SMOOTH);
     launch_conv16(CM_SMOOTH, st, c->xdn[L - 1], c->s[L - 1], c->W(c->off.smooth_up), nullptr,
-                  c->xin[L - 1], c->nl[L - 1], B, active, s);
+                  c->xin[L - 1], c->nl[L - 1], B, active, s, sb);
   }
   for (int l = L - 2; l >= 0; --l) {
     {
@@ -241,9 +243,9 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool
                          active, s);
     }
     {
-      Prof p(c, MGCNN_K_SMOOTH_UP, l, nodes(l) * 3.0 * S, nodes(l) * FL_SMOOTH);
+      Prof p(c, MGCNN_K_SMOOTH_UP, l, nodes(l) * (2.0 * S + SS), nodes(l) * FL_SMOOTH);
       launch_conv16(CM_SMOOTH, st, c->xdn[l], c->s[l], c->W(c->off.smooth_up), nullptr, c->xin[l],
-                    c->nl[l], B, active, s);
+                    c->nl[l], B, active, s, sb);
     }
   }
   {
@@ -289,6 +291,7 @@ void mgcnn_default_opts(mgcnn_opts* o) {
   o->method = MGCNN_METHOD_STATIONARY;
   o->restart = 30;
   o->f32_split = 1;
+  o->s_bf16 = 0;
 }
 
 size_t mgcnn_num_weights(int channels) {
@@ -308,6 +311,7 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.check_every < 1) return MGCNN_E_ARG;
   if (o.method != MGCNN_METHOD_STATIONARY && o.method != MGCNN_METHOD_FGMRES) return MGCNN_E_ARG;
   if (o.f32_split != 0 && o.f32_split != 1) return MGCNN_E_ARG;
+  if (o.s_bf16 != 0 && o.s_bf16 != 1) return MGCNN_E_ARG;
   if (o.method == MGCNN_METHOD_FGMRES && (o.restart < 1 || o.restart > 63)) return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
   if (!c) return MGCNN_E_NOMEM;
@@ -371,12 +375,12 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
     const float* zin = cc;
     float* ping[2] = {za, zb};
     for (int k = 0; k < NUM_SETUP_LAYERS; ++k) {
-      float* zout = (k == NUM_SETUP_LAYERS - 1 && c->st() != ST_BF16) ? (float*)c->s[l] : ping[k & 1];
+      float* zout = (k == NUM_SETUP_LAYERS - 1 && !c->s16()) ? (float*)c->s[l] : ping[k & 1];
       launch_conv16(CM_TANH, ST_F32, zin, nullptr, c->W(c->off.res_w[k]), c->W(c->off.res_b[k]), zout,
                     m, B, nullptr, s);
       zin = zout;
     }
-    if (c->st() == ST_BF16) launch_f32_to_bf16(zin, (bf16_t*)c->s[l], cnt, s);
+    if (c->s16()) launch_f32_to_bf16(zin, (bf16_t*)c->s[l], cnt, s);
     if (l < c->L - 1) {
       launch_conv16(CM_RESTRICT, ST_F32, cc, nullptr, c->W(c->off.setup_restrict), nullptr, cn, m, B,
                     nullptr, s);
@@ -519,7 +523,7 @@ int mgcnn_get_setup_tensor(mgcnn_ctx* c, int level, float* out) {
   if (level < 1 || level > c->L || !out) return fail(c, MGCNN_E_ARG, "get_setup_tensor: bad level");
   const int m = c->nl[level - 1];
   const size_t cnt = (size_t)m * m * c->B * C;
-  if (c->st() != ST_BF16)
+  if (!c->s16())
     HIP_TRY(c, hipMemcpyAsync(out, c->s[level - 1], cnt * 4, hipMemcpyDeviceToDevice, c->stream));
   else
     launch_bf16_to_f32((const bf16_t*)c->s[level - 1], out, cnt, c->stream);

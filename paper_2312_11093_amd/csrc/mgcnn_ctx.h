@@ -87,6 +87,9 @@ struct mgcnn_ctx {
   } tr;
 
   size_t state_bytes() const { return opts.state_dtype == MGCNN_BF16 ? 2 : 4; }
+  // setup tensors s_l in bf16 (bf16 state, or f32 state with opts.s_bf16)
+  bool s16() const { return opts.state_dtype == MGCNN_BF16 || opts.s_bf16 != 0; }
+  size_t s_bytes() const { return s16() ? 2 : 4; }
   mg::StateType st() const {
     if (opts.state_dtype == MGCNN_BF16) return mg::ST_BF16;
     return opts.f32_split ? mg::ST_F32X : mg::ST_F32;

@@ -45,8 +45,10 @@ void launch_conv_in(int cin, const float* in, const float* W, void* out, StateTy
 //                           TANH    y = x + tanh(W*x + bias) (same size, f32 only)
 //                           RESTRICT y = W *_{stride 2} x    (m -> (m-1)/2)
 enum ConvMode : int { CM_SMOOTH = 0, CM_TANH = 1, CM_RESTRICT = 2 };
+// s_bf16: s is stored as bf16 while the state is f32 (smoother only).
 void launch_conv16(ConvMode mode, StateType t, const void* x, const void* s, const float* W,
-                   const float* bias, void* y, int m, int B, const int* active, hipStream_t st);
+                   const float* bias, void* y, int m, int B, const int* active, hipStream_t st,
+                   bool s_bf16 = false);
 
 // y_fine += convT_{stride 2}(W_T, x_coarse), fine side m = 2 mc + 1, in place on y_fine.
 void launch_prolong_add(StateType t, const void* xc, const float* WT, void* yf, int mc, int B,
@@ -55,7 +57,7 @@ void launch_prolong_add(StateType t, const void* xc, const float* WT, void* yf, 
 // Finest-level down smoother with the reChannel-in conv folded in: y = x1 + W*(s.x1) with
 // x1 = W_in * rt computed on the staged tile.
 void launch_smooth_in(StateType t, const float* rt, const void* s, const float* Win, const float* W,
-                      void* y, int m, int B, const int* active, hipStream_t st);
+                      void* y, int m, int B, const int* active, hipStream_t st, bool s_bf16 = false);
 
 // u += W_out * x (16 -> 1 same-size conv), u f32 or f64; u = W_out * x when !accumulate.
 // flags (optional, indexed by problem): problems whose flag is 0 keep u unchanged.

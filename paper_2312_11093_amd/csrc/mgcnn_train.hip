@@ -71,7 +71,7 @@ static int ensure_train(mgcnn_ctx* c, int K) {
 }
 
 int forward_record(mgcnn_ctx* c, const float* f, float* u, int K) {
-  if (c->st() == ST_BF16 || c->u64())
+  if (c->st() == ST_BF16 || c->s16() || c->u64())
     return fail(c, MGCNN_E_ARG, "forward(record): needs f32 state and f32 u");
   int r = ensure_train(c, K);
   if (r) return r;

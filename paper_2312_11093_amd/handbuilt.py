@@ -53,11 +53,13 @@ def parameter_shapes(C: int) -> list[tuple[str, tuple[int, ...]]]:
     return s
 
 
-def vcycle_weights(C: int = 16, omega: float = 0.8, alpha: float = 0.05) -> np.ndarray:
+def vcycle_weights(C: int = 16, omega: float = 0.9, alpha: float = 0.05) -> np.ndarray:
     """Flat float32 weights of the hand-set V(1,1) cycle described in the module docstring.
 
-    omega: Jacobi damping of both smoothers; alpha: scale of the coupling features carried
-    through the tanh layers (the smoother taps divide it out again)."""
+    omega: Jacobi damping of both smoothers (0.9 measured best as an FGMRES preconditioner on
+    the 10^4-contrast block workload; 0.8 converges faster as a stationary cycle on Poisson);
+    alpha: scale of the coupling features carried through the tanh layers (the smoother taps
+    divide it out again)."""
     if C < 15:
         raise ValueError("the hand-set cycle needs at least 15 channels")
     P = {name: np.zeros(sh, dtype=np.float64) for name, sh in parameter_shapes(C)}

@@ -29,7 +29,8 @@ _lib = None
 class mgcnn_opts(ctypes.Structure):
     _fields_ = [("channels", ctypes.c_int), ("state_dtype", ctypes.c_int), ("u_dtype", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("method", ctypes.c_int), ("restart", ctypes.c_int), ("f32_split", ctypes.c_int)]
+                ("method", ctypes.c_int), ("restart", ctypes.c_int), ("f32_split", ctypes.c_int),
+                ("s_bf16", ctypes.c_int)]
 
 
 class mgcnn_kernel_stat(ctypes.Structure):
@@ -126,7 +127,7 @@ class Solver:
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", use_graph: bool = False,
                  check_every: int = 4, stream=None, method: str = "stationary", restart: int = 30,
-                 f32_split: bool = True):
+                 f32_split: bool = True, s_bf16: bool = False):
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -139,6 +140,7 @@ class Solver:
         o.method = {"stationary": 0, "fgmres": 1}[method]
         o.restart = int(restart)
         o.f32_split = int(bool(f32_split))
+        o.s_bf16 = int(bool(s_bf16))
         self.opts = o
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
@@ -288,7 +290,8 @@ class GroupSolver:
     problem set per size on its own stream, buckets solved concurrently."""
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", method: str = "stationary",
-                 restart: int = 30, check_every: int = 4, f32_split: bool = True, stream=None):
+                 restart: int = 30, check_every: int = 4, f32_split: bool = True, s_bf16: bool = False,
+                 stream=None):
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -299,6 +302,7 @@ class GroupSolver:
         o.restart = int(restart)
         o.check_every = int(check_every)
         o.f32_split = int(bool(f32_split))
+        o.s_bf16 = int(bool(s_bf16))
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
         self._stream = stream if stream is not None else torch.cuda.current_stream()

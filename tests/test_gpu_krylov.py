@@ -110,3 +110,30 @@ def test_single_4095_to_1e10():
     say("  oracle relres", rho)
     assert rho <= 1e-10 * (1 + 1e-5)
     S.close()
+
+
+def test_bf16_setup_tensors_option():
+    """opts.s_bf16: the setup tensors are the f32 ones rounded once to bf16 (round to nearest
+    even), and an FGMRES solve still reaches the tolerance (the oracle re-checks)."""
+    say("s_bf16")
+    n, B = 127, 3
+    a, b, f = datagen.make_batch("blocks1023", n, B, seed=14)
+    w = vcycle_weights()
+    S32 = Solver(w, state="f32", u="f64")
+    S16 = Solver(w, state="f32", u="f64", s_bf16=True, method="fgmres", restart=30)
+    S32.setup(dev(a), b)
+    S16.setup(dev(a), b)
+    for lvl in (1, 2, S32.levels):
+        ref = S32.get_setup_tensor(lvl).cpu().numpy().astype(np.float32)
+        bits = ref.view(np.uint32).astype(np.uint64)
+        rnd = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16 << 16).astype(np.uint32).view(np.float32)
+        got = S16.get_setup_tensor(lvl).cpu().numpy()
+        assert np.array_equal(got, rnd), lvl
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S16.solve(dev(f), u, 1e-8, 3000)
+    say("  iters", list(it))
+    assert st == M.OK
+    for p in range(B):
+        assert osv.relres(a[p], b[p], f[p], u[p].cpu().numpy()) <= 1e-8 * (1 + 1e-6)
+    S32.close()
+    S16.close()

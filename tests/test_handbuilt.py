@@ -10,7 +10,7 @@ from oracle import operator as oop
 from oracle import solve as osv
 from paper_2312_11093_amd.handbuilt import DC, DE, E, FCH, R, RC, parameter_shapes, vcycle_weights
 
-OMEGA, ALPHA = float(np.float32(0.8)), 0.05          # the weights are stored as float32
+OMEGA, ALPHA = float(np.float32(0.9)), 0.05          # the weights are stored as float32
 
 
 def test_layout_matches_oracle_order():
@@ -66,6 +66,8 @@ def test_cycle_converges_on_poisson():
     n = 31
     a = np.ones((n, n))
     f = np.random.default_rng(3).standard_normal((n, n))
-    u, st, it, rho, hist = osv.Solver(vcycle_weights(), a, (0.0, 0.0)).solve(f, 1e-8, 60)
+    # omega = 0.8 is the classical choice for this cycle on Poisson (the default, 0.9, was
+    # chosen for the Krylov-wrapped block workload)
+    u, st, it, rho, hist = osv.Solver(vcycle_weights(omega=0.8), a, (0.0, 0.0)).solve(f, 1e-8, 60)
     assert st == osv.OK and it <= 25
     assert osv.relres(a, (0.0, 0.0), f, u) <= 1e-8
