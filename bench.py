@@ -114,7 +114,9 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--workload", default="blocks1023")
     ap.add_argument("--method", default="fgmres", choices=["fgmres", "stationary"])
-    ap.add_argument("--restart", type=int, default=60)
+    ap.add_argument("--restart", type=int, default=63)
+    ap.add_argument("--gs-passes", type=int, default=1, choices=[1, 2],
+                    help="classical Gram-Schmidt passes per Arnoldi step")
     ap.add_argument("--state", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=10000)
@@ -146,7 +148,7 @@ def main():
     def make(state, use_graph):
         return Solver(weights, state=state, u="f64", check_every=args.check_every,
                       use_graph=use_graph and args.method == "stationary", method=args.method,
-                      restart=args.restart)
+                      restart=args.restart, gs_passes=args.gs_passes)
 
     S = make(args.state, not args.no_graph)
 
@@ -206,7 +208,9 @@ def main():
     plain = None
     if not args.no_plain:
         P = min(args.plain_sample, B)
-        Sp = Solver(weights, state="f32", u="f64", check_every=1, method=args.method, restart=args.restart)
+        # plain FP32: float32 matrix instructions, one problem per call, no graphs
+        Sp = Solver(weights, state="f32", u="f64", check_every=1, method=args.method, restart=args.restart,
+                    gs_passes=args.gs_passes, f32_split=False)
         up = torch.zeros((1, n, n), dtype=torch.float64, device="cuda")
         Sp.setup(da[0:1].contiguous(), b[0:1])
         Sp.solve(df[0:1].contiguous(), up, args.tol, min(args.maxit, 2 * args.restart))   # warm-up
@@ -231,7 +235,7 @@ def main():
         # setup time and time per iteration to the batch's own iteration counts
         t_batch_seq = B * float(np.mean(tset)) + per_iter * float(np.sum(its[-1]))
         plain = {"value": B / t_batch_seq, "unit": "solves/s",
-                 "how": (f"problems 0..{P - 1} solved one at a time (FP32 state, f64 u, no graphs); "
+                 "how": (f"problems 0..{P - 1} solved one at a time (FP32 state on f32 MFMA, f64 u, no graphs); "
                          f"their setup time and time per iteration, applied to the iteration counts "
                          f"of all {B} problems"),
                  "problems_timed": P, "iters": pit, "batched_iters_same_problems": [int(its[-1][p]) for p in range(P)],
@@ -255,6 +259,7 @@ def main():
                                f"{datagen.levels_for(n)} levels, tol {args.tol:g}",
                    "global_batch": B, "n": n, "method": args.method,
                    "restart": args.restart if args.method == "fgmres" else None,
+                   "gs_passes": args.gs_passes if args.method == "fgmres" else None,
                    "state": args.state, "u": "f64", "weights": wsrc, "parallelism": "single GPU"},
         "converged": converged, "mean_iters": mean_iters, "max_iters": int(np.max(its[-1])),
         "ms_per_stationary_iteration": round(iter_ms, 3),

@@ -80,6 +80,10 @@ typedef struct {
   int s_bf16;       /* MGCNN_F32 state only: 1 = keep the setup tensors s_l in bf16 (rounded once
                        after the setup network; the network stays a fixed linear operator, so a
                        solve still reaches its tolerance), halving their HBM traffic; 0 = f32 */
+  int inner_steps;  /* FGMRES only: the preconditioner is this many steps (1..16) of the stationary
+                       iteration of Eq. (1) on v from zero, z = B(v/D) then z += B((v - A z)/D) */
+  int gs_passes;    /* FGMRES only: classical Gram-Schmidt applied 2 (default) or 1 times per
+                       Arnoldi step */
 } mgcnn_opts;
 
 /* Default options: 16 channels, f32 state (split-bf16 matrix arithmetic), f64 u, graphs off,
@@ -113,7 +117,8 @@ int mgcnn_setup(mgcnn_ctx *ctx, const float *a, const float *b_host, int n, int 
  * (iters = k), NOT_CONVERGED if k == maxit, DIVERGED if rho_k is not finite or > 1e10;
  * otherwise apply one V-cycle.  A zero f gives u = 0, iters = 0, OK.
  * With opts.method = MGCNN_METHOD_FGMRES the same stopping rule is applied to the true
- * residual at every restart (and iters counts network applications); the Arnoldi estimate
+ * residual at every restart (and iters counts Arnoldi steps, each applying the network
+ * opts.inner_steps times); the Arnoldi estimate
  * ends a restart cycle early.
  * iters_host [batch], relres_host [batch], status_host [batch] (each may be NULL) receive the
  * per-problem results.  Return: OK if every problem converged, else E_DIVERGED if any

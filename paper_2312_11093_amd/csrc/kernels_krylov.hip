@@ -32,8 +32,9 @@ int krylov_blocks(int n) { return (int)(krylov_vpad(n) / ((size_t)KG_ELEMS * KG_
 //   KW_APPLY:     y[b][ystride] = A x                      (x f32 [B][n][n])
 //   KW_RESIDUAL:  y[b][ystride] = f - A u                  (u f32 or f64 [B][n][n])
 //   KW_NORMALIZE: v[b][ystride] *= s[b];  rt = v / D       (rt [B][n][n])
+//   KW_INNER:     rt = (v[b][ystride] - A x) / D           (x f32, rt [B][n][n])
 constexpr int KW_ROWS = 8;
-enum KwMode : int { KW_APPLY = 0, KW_RESIDUAL = 1, KW_NORMALIZE = 2 };
+enum KwMode : int { KW_APPLY = 0, KW_RESIDUAL = 1, KW_NORMALIZE = 2, KW_INNER = 3 };
 
 __device__ __forceinline__ double krcp(double x) {
   double y = __builtin_amdgcn_rcp(x);
@@ -101,7 +102,10 @@ __global__ __launch_bounds__(256) void kwalk_kernel(const float* __restrict__ a,
       const double xW = hasW ? (double)X[ij - dW] : 0.0;
       const double Ax = (sa * xc - aE * xE - aW * xW - aN * xn - aS * xs) * ih2 +
                         (bxp * (xc - xW) + bxm * (xE - xc) + byp * (xc - xs) + bym * (xn - xc)) * ih;
-      y[(size_t)b * ystride + ij] = (MODE == KW_RESIDUAL) ? (float)((double)f[base + ij] - Ax) : (float)Ax;
+      if constexpr (MODE == KW_INNER)
+        rt[base + ij] = (float)(((double)y[(size_t)b * ystride + ij] - Ax) * krcp(sa * ih2 + conv_diag));
+      else
+        y[(size_t)b * ystride + ij] = (MODE == KW_RESIDUAL) ? (float)((double)f[base + ij] - Ax) : (float)Ax;
       xs = xc; xc = xn;
     }
     ac = an; aS = aN;
@@ -134,6 +138,14 @@ void launch_krylov_residual(const float* a, const float* b, const float* f, cons
     hipLaunchKernelGGL((kwalk_kernel<float, KW_RESIDUAL>), grid, dim3(256), 0, st, a, b, f,
                        (const float*)u, r, rstride, (float*)nullptr, (const double*)nullptr, n, tx, tpp,
                        active);
+}
+
+void launch_inner_residual(const float* a, const float* b, const float* v, const float* x, float* rt, int n,
+                           int B, const int* active, hipStream_t st) {
+  dim3 grid; int tx, tpp;
+  kwalk_grid(n, B, grid, tx, tpp);
+  hipLaunchKernelGGL((kwalk_kernel<float, KW_INNER>), grid, dim3(256), 0, st, a, b, (const float*)nullptr,
+                     x, (float*)v, krylov_vpad(n), rt, (const double*)nullptr, n, tx, tpp, active);
 }
 
 void launch_normalize_diag(const float* a, const float* b, float* v, float* rt, const double* s, int n,

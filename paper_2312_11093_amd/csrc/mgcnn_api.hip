@@ -292,6 +292,8 @@ void mgcnn_default_opts(mgcnn_opts* o) {
   o->restart = 30;
   o->f32_split = 1;
   o->s_bf16 = 0;
+  o->inner_steps = 1;
+  o->gs_passes = 2;
 }
 
 size_t mgcnn_num_weights(int channels) {
@@ -312,6 +314,8 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.method != MGCNN_METHOD_STATIONARY && o.method != MGCNN_METHOD_FGMRES) return MGCNN_E_ARG;
   if (o.f32_split != 0 && o.f32_split != 1) return MGCNN_E_ARG;
   if (o.s_bf16 != 0 && o.s_bf16 != 1) return MGCNN_E_ARG;
+  if (o.inner_steps < 1 || o.inner_steps > 16) return MGCNN_E_ARG;
+  if (o.gs_passes != 1 && o.gs_passes != 2) return MGCNN_E_ARG;
   if (o.method == MGCNN_METHOD_FGMRES && (o.restart < 1 || o.restart > 63)) return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
   if (!c) return MGCNN_E_NOMEM;

@@ -71,6 +71,7 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
   const bool u64 = c->u64();
   const double nodes1 = (double)n * n;       // nodes of one problem
   const int LD = KRYLOV_LD;
+  const bool two_pass = c->opts.gs_passes != 1;
   // ||f||^2
   launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, n, B, nullptr, s);
   launch_sum_partials(c->d_partial, c->tiles, c->d_nf2, B, s);
@@ -158,6 +159,14 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
         launch_normalize_diag(c->d_a, c->d_b, Vj, c->d_rt, K.s, n, nlive, K.act, s);
       }
       if ((r = vcycle(c, Zj, false, K.act, nlive, false))) return r;
+      // optional further stationary steps on v_j: z_j += B((v_j - A z_j) / D)
+      for (int k = 1; k < c->opts.inner_steps; ++k) {
+        {
+          Prof p(c, MGCNN_K_KRYLOV_APPLY_A, 1, nodes * 16.0);
+          launch_inner_residual(c->d_a, c->d_b, Vj, Zj, c->d_rt, n, nlive, K.act, s);
+        }
+        if ((r = vcycle(c, Zj, false, K.act, nlive, true))) return r;
+      }
       // w = A z_j
       {
         Prof p(c, MGCNN_K_KRYLOV_APPLY_A, 0, nodes * 12.0);
@@ -165,17 +174,18 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
       }
       // classical Gram-Schmidt applied twice, in three passes:
       //   h1 = V^T w ; w -= V h1 and h2 = V^T w ; w -= V h2 and |w|^2
+      // (once, in two passes, when opts.gs_passes = 1: h1 = V^T w ; w -= V h1 and |w|^2)
       const int cnt = j + 1;
       {
         Prof p(c, MGCNN_K_KRYLOV_DOTS, cnt, nodes * 4.0 * (cnt + 1));
         launch_gs_pass(0, Vn, K.V, vs, cnt, n, nlive, nullptr, K.partial, K.h, K.act, s);
       }
       HIP_TRY(c, from_dev(hb));
-      {
+      if (two_pass) {
         Prof p(c, MGCNN_K_KRYLOV_ORTH, cnt, nodes * 4.0 * (cnt + 2));
         launch_gs_pass(1, Vn, K.V, vs, cnt, n, nlive, K.h, K.partial, K.h, K.act, s);
       }
-      HIP_TRY(c, from_dev(hb2));
+      if (two_pass) HIP_TRY(c, from_dev(hb2));
       {
         Prof p(c, MGCNN_K_KRYLOV_ORTH, cnt, nodes * 4.0 * (cnt + 2));
         launch_gs_pass(2, Vn, K.V, vs, cnt, n, nlive, K.h, K.partial, K.h, K.act, s);
@@ -186,7 +196,7 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
       for (int b = 0; b < B; ++b) {
         if (!live[b]) continue;
         for (int i = 0; i < cnt; ++i)
-          Hij(b, i, j) = hb[(size_t)b * LD + i] + hb2[(size_t)b * LD + i];
+          Hij(b, i, j) = hb[(size_t)b * LD + i] + (two_pass ? hb2[(size_t)b * LD + i] : 0.0);
         nw2[b] = hb3[(size_t)b * LD];
       }
       if (c->prof && (r = prof_drain(c))) return r;   // the stream is idle here

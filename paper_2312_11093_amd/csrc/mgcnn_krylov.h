@@ -28,6 +28,9 @@ void launch_krylov_residual(const float* a, const float* b, const float* f, cons
 // partial: B * KRYLOV_LD * krylov_blocks(n) doubles.  Returns -1 if cnt is out of range.
 int launch_gs_pass(int mode, float* w, const float* V, size_t vstride, int cnt, int n, int B,
                    const double* h, double* partial, double* out, const int* active, hipStream_t st);
+// rt = (v - A x) / D: v a basis vector (stride krylov_vpad(n)), x and rt [B][n][n]
+void launch_inner_residual(const float* a, const float* b, const float* v, const float* x, float* rt, int n,
+                           int B, const int* active, hipStream_t st);
 // v *= s[b * KRYLOV_LD] in place (stride krylov_vpad(n)) and rt = v / D ([B][n][n])
 void launch_normalize_diag(const float* a, const float* b, float* v, float* rt, const double* s, int n,
                            int B, const int* active, hipStream_t st);

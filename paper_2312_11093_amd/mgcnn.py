@@ -30,7 +30,7 @@ class mgcnn_opts(ctypes.Structure):
     _fields_ = [("channels", ctypes.c_int), ("state_dtype", ctypes.c_int), ("u_dtype", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("method", ctypes.c_int), ("restart", ctypes.c_int), ("f32_split", ctypes.c_int),
-                ("s_bf16", ctypes.c_int)]
+                ("s_bf16", ctypes.c_int), ("inner_steps", ctypes.c_int), ("gs_passes", ctypes.c_int)]
 
 
 class mgcnn_kernel_stat(ctypes.Structure):
@@ -127,7 +127,8 @@ class Solver:
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", use_graph: bool = False,
                  check_every: int = 4, stream=None, method: str = "stationary", restart: int = 30,
-                 f32_split: bool = True, s_bf16: bool = False):
+                 f32_split: bool = True, s_bf16: bool = False, inner_steps: int = 1,
+                 gs_passes: int = 2):
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -141,6 +142,8 @@ class Solver:
         o.restart = int(restart)
         o.f32_split = int(bool(f32_split))
         o.s_bf16 = int(bool(s_bf16))
+        o.inner_steps = int(inner_steps)
+        o.gs_passes = int(gs_passes)
         self.opts = o
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
@@ -291,7 +294,7 @@ class GroupSolver:
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", method: str = "stationary",
                  restart: int = 30, check_every: int = 4, f32_split: bool = True, s_bf16: bool = False,
-                 stream=None):
+                 inner_steps: int = 1, gs_passes: int = 2, stream=None):
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -303,6 +306,8 @@ class GroupSolver:
         o.check_every = int(check_every)
         o.f32_split = int(bool(f32_split))
         o.s_bf16 = int(bool(s_bf16))
+        o.inner_steps = int(inner_steps)
+        o.gs_passes = int(gs_passes)
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
         self._stream = stream if stream is not None else torch.cuda.current_stream()

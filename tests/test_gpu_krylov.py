@@ -52,17 +52,18 @@ def test_stationary_handbuilt_matches_oracle():
     S.close()
 
 
-@pytest.mark.parametrize("workload,n,B,state,restart", [
-    ("grf31", 31, 3, "f32", 30),
-    ("mixture127", 127, 4, "bf16", 20),
-    ("blocks1023", 127, 4, "bf16", 30),
-    ("blocks1023", 255, 2, "f32", 8),
+@pytest.mark.parametrize("workload,n,B,state,restart,gs", [
+    ("grf31", 31, 3, "f32", 30, 2),
+    ("mixture127", 127, 4, "bf16", 20, 2),
+    ("blocks1023", 127, 4, "bf16", 30, 2),
+    ("blocks1023", 255, 2, "f32", 8, 2),
+    ("blocks1023", 255, 3, "f32", 63, 1),
 ])
-def test_fgmres_converges_to_tol(workload, n, B, state, restart):
-    say("fgmres", workload, n, B, state, restart)
+def test_fgmres_converges_to_tol(workload, n, B, state, restart, gs):
+    say("fgmres", workload, n, B, state, restart, "gs passes", gs)
     a, b, f = datagen.make_batch(workload, n, B, seed=12)
     f[B - 1] = 0.0                                   # a zero right-hand side in the batch
-    S = Solver(vcycle_weights(), state=state, u="f64", method="fgmres", restart=restart)
+    S = Solver(vcycle_weights(), state=state, u="f64", method="fgmres", restart=restart, gs_passes=gs)
     S.setup(dev(a), b)
     u = torch.full((B, n, n), 0.5, dtype=torch.float64, device="cuda")
     tol = 1e-8
