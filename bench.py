@@ -73,6 +73,28 @@ def cpu_baseline(weights, a, b, f, iters_per_solve, sample_iters=2):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_finest_level_64x1023_f32.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2312_11093_amd", "csrc", f)
+                  for f in ("kernels_conv16.hip", "kernels_stencil.hip")]
+
+
+def measured_traffic_ratio(kind):
+    """HBM traffic / algorithmic bytes of a finest-level kernel from the committed rocprofv3
+    --pmc summary, or None if the summary is missing or the kernel sources changed since."""
+    import hashlib
+    try:
+        line = [ln for ln in open(TRAFFIC_FILE) if ln.startswith("traffic_json:")][0]
+        rec = json.loads(line.split(":", 1)[1])
+        h = hashlib.sha1()
+        for f in KERNEL_SOURCES:
+            h.update(open(f, "rb").read())
+        if h.hexdigest() != rec["source_sha1"]:
+            return None
+        return rec["ratio"].get(kind)
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+
+
 def roofline_of(stats):
     """Per-kind time shares and the roofline of the (kind, level) entry with the most time.
     A kernel whose algorithmic intensity (flops / HBM bytes) is above the fp32 ridge point
@@ -87,15 +109,22 @@ def roofline_of(stats):
     intensity = top["flops_per_launch"] / max(top["bytes_per_launch"], 1.0)
     ridge = FP32_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
     what = f"{top['kind']} (level {top['level']}, {top['launches']} launches, {avg_ms:.3f} ms avg)"
+    ratio = measured_traffic_ratio(top["kind"]) if top["level"] == 0 else None
+    traffic = round(ratio * top["bytes_per_launch"]) if ratio is not None else None
+    traffic_note = ("HBM bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE of the full-size launch, "
+                    "calibrated on a 1 GiB streaming kernel, as a ratio to the algorithmic bytes "
+                    "(profiles/pmc_finest_level_64x1023_f32.md)") if traffic is not None else None
     if intensity > ridge:
         roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": FP32_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": round(tfs / FP32_PEAK_TFS, 4), "traffic": None, "kernel": what,
+                "frac": round(tfs / FP32_PEAK_TFS, 4), "traffic": traffic, "kernel": what,
                 "flops_per_launch": top["flops_per_launch"], "bytes_per_launch": top["bytes_per_launch"],
+                "traffic_note": traffic_note,
                 "intensity_flop_per_byte": round(intensity, 2), "hbm_gbs": round(gbs, 1)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": what,
-                "bytes_per_launch": top["bytes_per_launch"], "intensity_flop_per_byte": round(intensity, 2)}
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": what,
+                "bytes_per_launch": top["bytes_per_launch"], "traffic_note": traffic_note,
+                "intensity_flop_per_byte": round(intensity, 2)}
     total = sum(by_kind.values())
     share = {k: round(v / total, 4) for k, v in sorted(by_kind.items(), key=lambda kv: -kv[1])}
     per_level0 = {s_["kind"]: {"ms": round(s_["ms_total"] / s_["launches"], 4),
