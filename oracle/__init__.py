@@ -13,6 +13,8 @@ Modules:
   solve     -- stationary iteration with relative-residual stop (Eq. (1),
                Sec. 4.1) and the residual loss (Eq. (19)).
   adjoint   -- reverse mode of the unrolled iteration and of the setup network.
+  gmg       -- the geometric multigrid baseline (Sec. 2.3, Alg. 1 as a V-cycle; Sec. 4.1
+               GMG settings).
 
 Parity pinning: every function here is checked by the "not gpu" tests against
 closed forms, library routines (scipy.signal, scipy.sparse, numpy.linalg),
@@ -21,4 +23,4 @@ invariants (linearity, adjoint identities) or central finite differences.
 The learned setup network with general weights has no closed form; it is pinned
 only through special cases (zero, diagonal and bias-only layers).
 """
-from . import operator, network, solve, adjoint  # noqa: F401
+from . import operator, network, solve, adjoint, gmg  # noqa: F401

@@ -56,31 +56,37 @@ class Solver:
         return u
 
     def solve(self, f, tol: float, maxit: int, u0=None):
-        """Tolerance-driven solve.  Returns (u, status, iters, relres, history).
+        """Tolerance-driven solve; see ``stationary``."""
+        return stationary(self, f, tol, maxit, u0)
 
-        At iterate k: r_k = f - A u_k, rho_k = ||r_k|| / ||f||; stop with OK if
-        rho_k <= tol (iters = k), with NOT_CONVERGED if k == maxit, with DIVERGED if
-        rho_k is not finite or exceeds 1e10; otherwise apply one more V-cycle.
-        A zero right-hand side returns u = 0, iters = 0, OK."""
-        f = np.asarray(f, dtype=np.float64)
-        nf = math.sqrt(float(np.sum(f * f)))
-        if nf == 0.0:
-            return np.zeros_like(f), OK, 0, 0.0, [0.0]
-        u = np.zeros_like(f) if u0 is None else np.asarray(u0, dtype=np.float64).copy()
-        hist = []
-        k = 0
-        while True:
-            r = self.residual(f, u)
-            rho = math.sqrt(float(np.sum(r * r))) / nf
-            hist.append(rho)
-            if rho <= tol:
-                return u, OK, k, rho, hist
-            if k == maxit:
-                return u, NOT_CONVERGED, k, rho, hist
-            if not math.isfinite(rho) or rho > DIVERGENCE_LIMIT:
-                return u, DIVERGED, k, rho, hist
-            u = u + self.correction(r)
-            k += 1
+
+def stationary(it, f, tol: float, maxit: int, u0=None):
+    """Tolerance-driven stationary iteration u <- u + it.correction(f - A u) for any object
+    with ``residual(f, u)`` and ``correction(r)``.  Returns (u, status, iters, relres, history).
+
+    At iterate k: r_k = f - A u_k, rho_k = ||r_k|| / ||f||; stop with OK if rho_k <= tol
+    (iters = k), with NOT_CONVERGED if k == maxit, with DIVERGED if rho_k is not finite or
+    exceeds 1e10; otherwise apply one more correction.  A zero right-hand side returns u = 0,
+    iters = 0, OK."""
+    f = np.asarray(f, dtype=np.float64)
+    nf = math.sqrt(float(np.sum(f * f)))
+    if nf == 0.0:
+        return np.zeros_like(f), OK, 0, 0.0, [0.0]
+    u = np.zeros_like(f) if u0 is None else np.asarray(u0, dtype=np.float64).copy()
+    hist = []
+    k = 0
+    while True:
+        r = it.residual(f, u)
+        rho = math.sqrt(float(np.sum(r * r))) / nf
+        hist.append(rho)
+        if rho <= tol:
+            return u, OK, k, rho, hist
+        if k == maxit:
+            return u, NOT_CONVERGED, k, rho, hist
+        if not math.isfinite(rho) or rho > DIVERGENCE_LIMIT:
+            return u, DIVERGED, k, rho, hist
+        u = u + it.correction(r)
+        k += 1
 
 
 def relres(a, b, f, u) -> float:
