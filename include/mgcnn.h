@@ -58,6 +58,18 @@ enum {
 enum { MGCNN_F32 = 0, MGCNN_BF16 = 1 };
 /* Precision of u, of the residual arithmetic and of the stopping test. */
 enum { MGCNN_U_F32 = 0, MGCNN_U_F64 = 1 };
+/* Preconditioner B of the iteration (both outer methods). */
+enum {
+  MGCNN_PRECOND_NETWORK = 0,    /* the MGCNN solve network (Alg. 3) on the setup tensors (Alg. 2) */
+  MGCNN_PRECOND_GMG = 1         /* the geometric multigrid baseline of Sec. 2.3 / Sec. 4.1: a V-cycle
+                                   with the PDE rediscretised on every coarse grid (coefficient
+                                   injected: a_c[I][J] = a[2I+1][2J+1], h doubled), bilinear
+                                   prolongation, full-weighting restriction (P^T / 4), gmg_sweeps
+                                   weighted-Jacobi sweeps (weight gmg_omega) before and after the
+                                   coarse correction, exact solve on the coarsest grid.  B(r/D) is
+                                   the cycle applied to r.  No weights, no setup network; training
+                                   entry points return MGCNN_E_STATE. */
+};
 /* Outer method of mgcnn_solve. */
 enum {
   MGCNN_METHOD_STATIONARY = 0,  /* u += B((f - A u)/D), Sec. 2.2 Eq. (1) */
@@ -84,10 +96,18 @@ typedef struct {
                        iteration of Eq. (1) on v from zero, z = B(v/D) then z += B((v - A z)/D) */
   int gs_passes;    /* FGMRES only: classical Gram-Schmidt applied 2 (default) or 1 times per
                        Arnoldi step */
+  int precond;      /* MGCNN_PRECOND_NETWORK (default) or MGCNN_PRECOND_GMG */
+  int gmg_levels;   /* GMG only: levels of the cycle; 0 (default) = log2(n+1) - 3, at least 1
+                       (coarsest grid 15 x 15, as in Sec. 4.1); otherwise a value in
+                       [max(1, log2(n+1) - 3), log2(n+1)] (the coarsest grid, solved exactly, has
+                       at most 15 x 15 nodes), checked by mgcnn_setup (MGCNN_E_ARG) */
+  int gmg_sweeps;   /* GMG only: sweeps before and after the coarse correction, 1..4 (default 3) */
+  float gmg_omega;  /* GMG only: weighted-Jacobi weight, in (0, 2) (default 0.67) */
 } mgcnn_opts;
 
 /* Default options: 16 channels, f32 state (split-bf16 matrix arithmetic), f64 u, graphs off,
- * check every 4 iterations, stationary method, FGMRES restart 30. */
+ * check every 4 iterations, stationary method, FGMRES restart 30, network preconditioner
+ * (GMG settings: default levels, 3 sweeps, weight 0.67). */
 void mgcnn_default_opts(mgcnn_opts *opts);
 
 /* Number of weights for `channels` hidden channels: 81 C^2 + 58 C. */
@@ -107,7 +127,9 @@ int mgcnn_set_stream(mgcnn_ctx *ctx, void *hip_stream);
 
 /* Setup phase (Sec. 3.2, Alg. 2) for `batch` problems of side n: a [batch][n][n] device
  * (a > 0), b [batch][2] host.  The library copies a and b; `a` need not outlive the call.
- * Computes and keeps the per-level setup tensors. */
+ * Computes and keeps the per-level setup tensors.  With MGCNN_PRECOND_GMG it builds the
+ * multigrid hierarchy instead: the injected coefficient of every coarse level and the f64
+ * inverse of the coarsest operator (8 N^2 bytes per problem, N = coarsest nodes <= 225). */
 int mgcnn_setup(mgcnn_ctx *ctx, const float *a, const float *b_host, int n, int batch);
 
 /* Tolerance-driven solve (Sec. 2.2, Eq. (1); stop on the relative residual as in Sec. 4.1).
@@ -163,7 +185,8 @@ int mgcnn_residual(mgcnn_ctx *ctx, const float *f, const void *u, float *r);
  * [batch].  Blocks the host. */
 int mgcnn_residual_norms(mgcnn_ctx *ctx, const float *f, const void *u, double *relres_host);
 
-/* Copy the level-l setup tensor (l = 1..L) into `out` [batch][n_l][n_l][16] float32 device. */
+/* Copy the level-l setup tensor (l = 1..L) into `out` [batch][n_l][n_l][16] float32 device
+ * (network preconditioner only). */
 int mgcnn_get_setup_tensor(mgcnn_ctx *ctx, int level, float *out);
 
 /* Per-launch profiling of the solve loop.  Between mgcnn_profile_begin and mgcnn_profile_end
@@ -181,7 +204,10 @@ enum {
      vectors the launch reads */
   MGCNN_K_KRYLOV_APPLY_A = 10, MGCNN_K_KRYLOV_DOTS = 11, MGCNN_K_KRYLOV_ORTH = 12,
   MGCNN_K_KRYLOV_SCALE = 13, MGCNN_K_KRYLOV_COMBINE = 14, MGCNN_K_KRYLOV_RESIDUAL = 15,
-  MGCNN_K_SCALE_BY_DIAG = 16, MGCNN_K_ZERO = 17
+  MGCNN_K_SCALE_BY_DIAG = 16, MGCNN_K_ZERO = 17,
+  /* GMG preconditioner: pre-sweeps + residual + restriction of one level; prolongation +
+     post-sweeps of one level; exact solve on the coarsest grid */
+  MGCNN_K_GMG_DOWN = 18, MGCNN_K_GMG_UP = 19, MGCNN_K_GMG_COARSE = 20
 };
 typedef struct {
   int kind;                /* MGCNN_K_* */

@@ -1,0 +1,459 @@
+// Geometric multigrid baseline on CDNA4 (gfx950): the V-cycle of Sec. 2.3 (Alg. 1 applied
+// recursively) with the settings of Sec. 4.1: the PDE rediscretised on every coarse grid
+// (coefficient injected to the coarse nodes, h doubled), bilinear prolongation P, full-weighting
+// restriction R = P^T / 4, weighted-Jacobi sweeps before and after the coarse correction, and an
+// exact solve on the coarsest grid (at most 15 x 15).
+//
+// Every level is HBM-bound scalar work (no contraction), so each level is two fused kernels
+// with temporal blocking in LDS:
+//   down: all pre-sweeps from zero, the residual and its full-weighting restriction, per
+//         32 x 32 output tile -- a and the right-hand side are read once, e and the coarse
+//         right-hand side written once;
+//   up:   prolong-add of the coarse correction and all post-sweeps, writing the level's final
+//         correction (on the finest level straight into u or z).
+// The halo of a tile grows by one node per sweep; the sweeps are recomputed on the overlap
+// instead of exchanged.  The stencil of every node (the four neighbour weights of D^-1 A and
+// D) is formed once per kernel in registers from a staged in LDS.
+//
+// Layouts: scalar fields [B][m][m] (x fastest), problem index from the compact list.
+#include <algorithm>
+
+#include "mgcnn_internal.h"
+#include "mgcnn_device.h"
+#include "mgcnn_gmg.h"
+
+namespace mg {
+
+constexpr int GT = 32;          // output tile side (fine nodes); 16 x 16 coarse nodes
+
+__device__ __forceinline__ float harmf(float p, float q) { return (2.f * p * q) / (p + q); }
+
+// Stencil of node (i, j) of an m x m grid from the coefficient staged in LDS around it (la at
+// the node; +-1 and +-P its neighbours).  q = rhs / D (or rhs itself when already scaled).
+struct Node {
+  float D, wW, wE, wS, wN, q;
+};
+__device__ __forceinline__ Node make_node(const float* la, int c, int P, int i, int j, int m,
+                                          float ih, float ih2, float bxp, float bxm, float byp,
+                                          float bym, float rhs, bool scaled) {
+  Node s;
+  const float ac = la[c];
+  const float aE = (j + 1 < m) ? harmf(ac, la[c + 1]) : ac;
+  const float aW = (j > 0) ? harmf(ac, la[c - 1]) : ac;
+  const float aN = (i + 1 < m) ? harmf(ac, la[c + P]) : ac;
+  const float aS = (i > 0) ? harmf(ac, la[c - P]) : ac;
+  s.D = (aE + aW + aN + aS) * ih2 + (bxp - bxm + byp - bym) * ih;
+  const float iD = 1.f / s.D;
+  s.wW = (j > 0) ? (aW * ih2 + bxp * ih) * iD : 0.f;
+  s.wE = (j + 1 < m) ? (aE * ih2 - bxm * ih) * iD : 0.f;
+  s.wS = (i > 0) ? (aS * ih2 + byp * ih) * iD : 0.f;
+  s.wN = (i + 1 < m) ? (aN * ih2 - bym * ih) * iD : 0.f;
+  s.q = scaled ? rhs : rhs * iD;
+  return s;
+}
+
+// Tile geometry: the e-region of side RS around the tile, padded by one ring (P = RS + 2) that
+// holds the coefficient halo in `la` and zeros in the e buffers.
+template <int RS>
+struct Geo {
+  static constexpr int P = RS + 2;
+  static constexpr int PTS = (RS * RS + 255) / 256;   // region nodes per thread
+};
+
+// ------------------------------------------------------------------------------------------
+// down: e = S^NU(0; r) on the tile; rc = R (r - A e) on the 16 x 16 coarse nodes of the tile.
+// ------------------------------------------------------------------------------------------
+template <int NU>
+__global__ __launch_bounds__(256) void gmg_down_kernel(const float* __restrict__ a,
+                                                       const float* __restrict__ bvec,
+                                                       const float* __restrict__ rhs, int scaled,
+                                                       float omega, float* __restrict__ e_out,
+                                                       float* __restrict__ rc_out, int m,
+                                                       int tiles_x, int tiles_per_prob,
+                                                       const int* __restrict__ active) {
+  constexpr int RS = GT + 1 + 2 * NU;      // region: tile rows y0 - NU .. y0 + GT + NU
+  using G = Geo<RS>;
+  constexpr int P = G::P;
+  __shared__ float la[P * P];
+  __shared__ float le[2][P * P];
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;
+  const int y0 = (tile / tiles_x) * GT, x0 = (tile % tiles_x) * GT;
+  const int oy = y0 - NU, ox = x0 - NU;    // grid coordinates of region node (0, 0)
+  const size_t base = (size_t)b * m * m;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < P * P; idx += 256) {
+    const int gi = oy - 1 + idx / P, gj = ox - 1 + idx % P;
+    const bool in = gi >= 0 && gi < m && gj >= 0 && gj < m;
+    la[idx] = in ? a[base + (size_t)gi * m + gj] : 0.f;
+    le[0][idx] = 0.f;
+    le[1][idx] = 0.f;
+  }
+  const float ih = (float)(m + 1), ih2 = ih * ih;
+  const float bx = bvec[2 * b], by = bvec[2 * b + 1];
+  const float bxp = bx > 0.f ? bx : 0.f, bxm = bx < 0.f ? bx : 0.f;
+  const float byp = by > 0.f ? by : 0.f, bym = by < 0.f ? by : 0.f;
+  __syncthreads();
+  Node nd[G::PTS];
+  float ev[G::PTS];
+#pragma unroll
+  for (int k = 0; k < G::PTS; ++k) {
+    const int p = tid + 256 * k;
+    const int ry = p / RS, rx = p % RS;
+    const int i = oy + ry, j = ox + rx;
+    const bool in = p < RS * RS && i >= 0 && i < m && j >= 0 && j < m;
+    if (in) {
+      const int c = (ry + 1) * P + rx + 1;
+      nd[k] = make_node(la, c, P, i, j, m, ih, ih2, bxp, bxm, byp, bym,
+                        rhs[base + (size_t)i * m + j], scaled != 0);
+      ev[k] = omega * nd[k].q;                       // first sweep from zero
+      le[0][c] = ev[k];
+    } else {
+      nd[k] = Node{1.f, 0.f, 0.f, 0.f, 0.f, 0.f};    // outside the grid: e stays 0
+      ev[k] = 0.f;
+    }
+  }
+  __syncthreads();
+  const float om1 = 1.f - omega;
+#pragma unroll
+  for (int s = 1; s < NU; ++s) {
+    const float* cur = le[(s - 1) & 1];
+    float* nxt = le[s & 1];
+#pragma unroll
+    for (int k = 0; k < G::PTS; ++k) {
+      const int p = tid + 256 * k;
+      if (p < RS * RS) {
+        const int c = (p / RS + 1) * P + p % RS + 1;
+        const Node& q = nd[k];
+        const float v = om1 * ev[k] +
+                        omega * (q.q + q.wW * cur[c - 1] + q.wE * cur[c + 1] + q.wS * cur[c - P] +
+                                 q.wN * cur[c + P]);
+        ev[k] = v;
+        nxt[c] = v;
+      }
+    }
+    __syncthreads();
+  }
+  // residual r - A e = D (q - e + sum w e_nb) on the restriction footprint (region rows and
+  // columns NU .. NU + GT), into the free buffer
+  {
+    const float* cur = le[(NU - 1) & 1];
+    float* res = le[NU & 1];
+#pragma unroll
+    for (int k = 0; k < G::PTS; ++k) {
+      const int p = tid + 256 * k;
+      const int ry = p / RS, rx = p % RS;
+      if (p < RS * RS && ry >= NU && ry <= NU + GT && rx >= NU && rx <= NU + GT) {
+        const int c = (ry + 1) * P + rx + 1;
+        const Node& q = nd[k];
+        res[c] = q.D * (q.q - ev[k] + q.wW * cur[c - 1] + q.wE * cur[c + 1] + q.wS * cur[c - P] +
+                        q.wN * cur[c + P]);
+      }
+    }
+  }
+  // final e of the tile's own nodes
+#pragma unroll
+  for (int k = 0; k < G::PTS; ++k) {
+    const int p = tid + 256 * k;
+    const int ry = p / RS, rx = p % RS;
+    const int i = oy + ry, j = ox + rx;
+    if (p < RS * RS && ry >= NU && ry < NU + GT && rx >= NU && rx < NU + GT && i < m && j < m)
+      e_out[base + (size_t)i * m + j] = ev[k];
+  }
+  __syncthreads();
+  // full weighting onto the coarse nodes (I, J) = (y0/2 + tid/16, x0/2 + tid%16)
+  const int mc = (m - 1) / 2;
+  const int I = y0 / 2 + tid / 16, J = x0 / 2 + tid % 16;
+  if (I < mc && J < mc) {
+    const float* res = le[NU & 1];
+    const int c = (2 * I + 1 - oy + 1) * P + (2 * J + 1 - ox + 1);
+    const float v = 4.f * res[c] + 2.f * (res[c - 1] + res[c + 1] + res[c - P] + res[c + P]) +
+                    (res[c - P - 1] + res[c - P + 1] + res[c + P - 1] + res[c + P + 1]);
+    rc_out[(size_t)b * mc * mc + (size_t)I * mc + J] = v * 0.0625f;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// up: e = S^NU(e_pre + P ec; r) on the tile, written per `mode` (f32 / f64, store / add).
+// ------------------------------------------------------------------------------------------
+template <int NU>
+__global__ __launch_bounds__(256) void gmg_up_kernel(const float* __restrict__ a,
+                                                     const float* __restrict__ bvec,
+                                                     const float* __restrict__ rhs, int scaled,
+                                                     float omega, const float* __restrict__ e_pre,
+                                                     const float* __restrict__ ec, void* out,
+                                                     int mode, const int* __restrict__ flags,
+                                                     int m, int tiles_x, int tiles_per_prob,
+                                                     const int* __restrict__ active) {
+  constexpr int RS = GT + 2 * NU;          // region: tile rows y0 - NU .. y0 + GT + NU - 1
+  using G = Geo<RS>;
+  constexpr int P = G::P;
+  constexpr int CS = GT / 2 + NU + 3;      // side of the staged coarse patch
+  __shared__ float la[P * P];
+  __shared__ float le[2][P * P];
+  __shared__ float lc[CS * CS];
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;
+  const int y0 = (tile / tiles_x) * GT, x0 = (tile % tiles_x) * GT;
+  const int oy = y0 - NU, ox = x0 - NU;
+  const size_t base = (size_t)b * m * m;
+  const int mc = (m - 1) / 2;
+  const size_t cbase = (size_t)b * mc * mc;
+  const int cy = (oy - 1) >> 1, cx = (ox - 1) >> 1;    // coarse patch origin (may be -1)
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < P * P; idx += 256) {
+    const int gi = oy - 1 + idx / P, gj = ox - 1 + idx % P;
+    const bool in = gi >= 0 && gi < m && gj >= 0 && gj < m;
+    la[idx] = in ? a[base + (size_t)gi * m + gj] : 0.f;
+    le[0][idx] = 0.f;
+    le[1][idx] = 0.f;
+  }
+  for (int idx = tid; idx < CS * CS; idx += 256) {
+    const int I = cy + idx / CS, J = cx + idx % CS;
+    lc[idx] = (I >= 0 && I < mc && J >= 0 && J < mc) ? ec[cbase + (size_t)I * mc + J] : 0.f;
+  }
+  const float ih = (float)(m + 1), ih2 = ih * ih;
+  const float bx = bvec[2 * b], by = bvec[2 * b + 1];
+  const float bxp = bx > 0.f ? bx : 0.f, bxm = bx < 0.f ? bx : 0.f;
+  const float byp = by > 0.f ? by : 0.f, bym = by < 0.f ? by : 0.f;
+  __syncthreads();
+  Node nd[G::PTS];
+  float ev[G::PTS];
+#pragma unroll
+  for (int k = 0; k < G::PTS; ++k) {
+    const int p = tid + 256 * k;
+    const int ry = p / RS, rx = p % RS;
+    const int i = oy + ry, j = ox + rx;
+    const bool in = p < RS * RS && i >= 0 && i < m && j >= 0 && j < m;
+    if (in) {
+      const int c = (ry + 1) * P + rx + 1;
+      const size_t g = base + (size_t)i * m + j;
+      nd[k] = make_node(la, c, P, i, j, m, ih, ih2, bxp, bxm, byp, bym, rhs[g], scaled != 0);
+      // bilinear interpolation: fine i lies between coarse rows (i-1)>>1 and i>>1 (the same
+      // row when i is odd); the four-term average gives weights 1, 1/2 and 1/4
+      const int i0 = ((i - 1) >> 1) - cy, i1 = (i >> 1) - cy;
+      const int j0 = ((j - 1) >> 1) - cx, j1 = (j >> 1) - cx;
+      const float pe = 0.25f * ((lc[i0 * CS + j0] + lc[i0 * CS + j1]) +
+                                (lc[i1 * CS + j0] + lc[i1 * CS + j1]));
+      ev[k] = e_pre[g] + pe;
+      le[0][c] = ev[k];
+    } else {
+      nd[k] = Node{1.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      ev[k] = 0.f;
+    }
+  }
+  __syncthreads();
+  const float om1 = 1.f - omega;
+#pragma unroll
+  for (int s = 0; s < NU; ++s) {
+    const float* cur = le[s & 1];
+    float* nxt = le[(s + 1) & 1];
+#pragma unroll
+    for (int k = 0; k < G::PTS; ++k) {
+      const int p = tid + 256 * k;
+      if (p < RS * RS) {
+        const int c = (p / RS + 1) * P + p % RS + 1;
+        const Node& q = nd[k];
+        const float v = om1 * ev[k] +
+                        omega * (q.q + q.wW * cur[c - 1] + q.wE * cur[c + 1] + q.wS * cur[c - P] +
+                                 q.wN * cur[c + P]);
+        ev[k] = v;
+        if (s + 1 < NU) nxt[c] = v;
+      }
+    }
+    if (s + 1 < NU) __syncthreads();
+  }
+  if (flags != nullptr && flags[b] == 0) return;
+#pragma unroll
+  for (int k = 0; k < G::PTS; ++k) {
+    const int p = tid + 256 * k;
+    const int ry = p / RS, rx = p % RS;
+    const int i = oy + ry, j = ox + rx;
+    if (p < RS * RS && ry >= NU && ry < NU + GT && rx >= NU && rx < NU + GT && i < m && j < m) {
+      const size_t g = base + (size_t)i * m + j;
+      switch (mode) {
+        case GMG_OUT_F32: static_cast<float*>(out)[g] = ev[k]; break;
+        case GMG_OUT_F32_ADD: static_cast<float*>(out)[g] += ev[k]; break;
+        case GMG_OUT_F64: static_cast<double*>(out)[g] = (double)ev[k]; break;
+        default: static_cast<double*>(out)[g] += (double)ev[k]; break;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// coarsest grid: exact solve with the inverse formed at setup (f64).
+// ------------------------------------------------------------------------------------------
+// Matrix of the rediscretised operator on an mc x mc grid (row index i*mc + j), assembled
+// transposed (column-major A, i.e. M[q][p] = A[p][q]) and inverted in place by Gauss-Jordan
+// elimination without pivoting (A is diagonally dominant: weakly in the interior, strictly next
+// to the boundary), one workgroup per problem.  The result M = (A^T)^-1 = (A^-1)^T is what the
+// apply kernel wants: for each column k, the threads read consecutive entries.
+__global__ __launch_bounds__(256) void gmg_coarse_inverse_kernel(const float* __restrict__ a,
+                                                                 const float* __restrict__ bvec,
+                                                                 double* __restrict__ inv, int mc) {
+  const int b = blockIdx.x;
+  const int N = mc * mc;
+  double* M = inv + (size_t)b * N * N;
+  const float* A = a + (size_t)b * N;
+  const int tid = threadIdx.x;
+  for (size_t idx = tid; idx < (size_t)N * N; idx += 256) M[idx] = 0.0;
+  __syncthreads();
+  const double ih = (double)(mc + 1), ih2 = ih * ih;
+  const double bx = bvec[2 * b], by = bvec[2 * b + 1];
+  const double bxp = bx > 0 ? bx : 0, bxm = bx < 0 ? bx : 0;
+  const double byp = by > 0 ? by : 0, bym = by < 0 ? by : 0;
+  auto hm = [](double p, double q) { return 2.0 * p * q / (p + q); };
+  for (int p = tid; p < N; p += 256) {
+    const int i = p / mc, j = p % mc;
+    const double ac = A[p];
+    const double aE = (j + 1 < mc) ? hm(ac, A[p + 1]) : ac;
+    const double aW = (j > 0) ? hm(ac, A[p - 1]) : ac;
+    const double aN = (i + 1 < mc) ? hm(ac, A[p + mc]) : ac;
+    const double aS = (i > 0) ? hm(ac, A[p - mc]) : ac;
+    // row p of A stored as column p of M
+    M[(size_t)p * N + p] = (aE + aW + aN + aS) * ih2 + (bxp - bxm + byp - bym) * ih;
+    if (j + 1 < mc) M[(size_t)(p + 1) * N + p] = -aE * ih2 + bxm * ih;
+    if (j > 0) M[(size_t)(p - 1) * N + p] = -aW * ih2 - bxp * ih;
+    if (i + 1 < mc) M[(size_t)(p + mc) * N + p] = -aN * ih2 + bym * ih;
+    if (i > 0) M[(size_t)(p - mc) * N + p] = -aS * ih2 - byp * ih;
+  }
+  __syncthreads();
+  __shared__ double fcol[GMG_MAX_COARSE];
+  __shared__ double piv;
+  for (int k = 0; k < N; ++k) {
+    if (tid == 0) piv = 1.0 / M[(size_t)k * N + k];
+    for (int i = tid; i < N; i += 256) fcol[i] = M[(size_t)i * N + k];
+    __syncthreads();
+    const double pk = piv;
+    // pivot row: M[k][:] *= p with M[k][k] = p
+    for (int j = tid; j < N; j += 256) {
+      const double v = (j == k) ? 1.0 : M[(size_t)k * N + j];
+      M[(size_t)k * N + j] = v * pk;
+    }
+    __syncthreads();
+    // other rows: M[i][:] -= f_i M[k][:], with M[i][k] starting from 0 (thread j owns column j)
+    if (tid < N) {
+      const int j = tid;
+      const double mkj = M[(size_t)k * N + j];
+      for (int i = 0; i < N; ++i) {
+        if (i == k) continue;
+        double* mij = M + (size_t)i * N + j;
+        const double base = (j == k) ? 0.0 : *mij;
+        *mij = base - fcol[i] * mkj;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// e = A^-1 r on the coarsest grid, one workgroup per problem.  `scaled`: r is given as r / D
+// (only when the coarsest grid is the finest one).
+__global__ __launch_bounds__(256) void gmg_coarse_solve_kernel(const double* __restrict__ inv,
+                                                               const float* __restrict__ a,
+                                                               const float* __restrict__ bvec,
+                                                               const float* __restrict__ rhs,
+                                                               int scaled, void* out, int mode,
+                                                               const int* __restrict__ flags,
+                                                               int mc, const int* __restrict__ active) {
+  const int b = active != nullptr ? active[blockIdx.x] : blockIdx.x;
+  const int N = mc * mc;
+  const int tid = threadIdx.x;
+  __shared__ double lr[GMG_MAX_COARSE];
+  const size_t base = (size_t)b * N;
+  if (tid < N) {
+    double r = rhs[base + tid];
+    if (scaled) {
+      const float* A = a + base;
+      const int i = tid / mc, j = tid % mc;
+      const double ih = (double)(mc + 1), ih2 = ih * ih;
+      const double ac = A[tid];
+      auto hm = [](double p, double q) { return 2.0 * p * q / (p + q); };
+      const double aE = (j + 1 < mc) ? hm(ac, A[tid + 1]) : ac;
+      const double aW = (j > 0) ? hm(ac, A[tid - 1]) : ac;
+      const double aN = (i + 1 < mc) ? hm(ac, A[tid + mc]) : ac;
+      const double aS = (i > 0) ? hm(ac, A[tid - mc]) : ac;
+      const double bx = bvec[2 * b], by = bvec[2 * b + 1];
+      r *= (aE + aW + aN + aS) * ih2 + (fabs(bx) + fabs(by)) * ih;
+    }
+    lr[tid] = r;
+  }
+  __syncthreads();
+  if (tid >= N) return;
+  const double* M = inv + (size_t)b * N * N;
+  double acc = 0.0;
+  for (int k = 0; k < N; ++k) acc += M[(size_t)k * N + tid] * lr[k];
+  if (flags != nullptr && flags[b] == 0) return;
+  switch (mode) {
+    case GMG_OUT_F32: static_cast<float*>(out)[base + tid] = (float)acc; break;
+    case GMG_OUT_F32_ADD: static_cast<float*>(out)[base + tid] += (float)acc; break;
+    case GMG_OUT_F64: static_cast<double*>(out)[base + tid] = acc; break;
+    default: static_cast<double*>(out)[base + tid] += acc; break;
+  }
+}
+
+// coefficient on the next coarser grid: a_c[I][J] = a[2I+1][2J+1]
+__global__ __launch_bounds__(256) void gmg_inject_kernel(const float* __restrict__ a,
+                                                         float* __restrict__ ac, int m, int B) {
+  const int mc = (m - 1) / 2;
+  const size_t total = (size_t)B * mc * mc;
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * 256) {
+    const size_t b = idx / ((size_t)mc * mc);
+    const int r = (int)(idx % ((size_t)mc * mc));
+    const int I = r / mc, J = r % mc;
+    ac[idx] = a[b * m * m + (size_t)(2 * I + 1) * m + 2 * J + 1];
+  }
+}
+
+// ---- launchers ---------------------------------------------------------------------------
+static inline int tiles_1d(int m) { return (m + GT - 1) / GT; }
+
+void launch_gmg_down(int nu, const float* a, const float* b, const float* rhs, bool scaled,
+                     float omega, float* e, float* rc, int m, int B, const int* active,
+                     hipStream_t st) {
+  const int tx = tiles_1d(m), tp = tx * tx;
+  const dim3 grid(tp * B), block(256);
+  switch (nu) {
+    case 1: hipLaunchKernelGGL(gmg_down_kernel<1>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active); break;
+    case 2: hipLaunchKernelGGL(gmg_down_kernel<2>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active); break;
+    case 3: hipLaunchKernelGGL(gmg_down_kernel<3>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active); break;
+    default: hipLaunchKernelGGL(gmg_down_kernel<4>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active); break;
+  }
+}
+
+void launch_gmg_up(int nu, const float* a, const float* b, const float* rhs, bool scaled,
+                   float omega, const float* e_pre, const float* ec, void* out, int mode,
+                   const int* flags, int m, int B, const int* active, hipStream_t st) {
+  const int tx = tiles_1d(m), tp = tx * tx;
+  const dim3 grid(tp * B), block(256);
+  switch (nu) {
+    case 1: hipLaunchKernelGGL(gmg_up_kernel<1>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active); break;
+    case 2: hipLaunchKernelGGL(gmg_up_kernel<2>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active); break;
+    case 3: hipLaunchKernelGGL(gmg_up_kernel<3>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active); break;
+    default: hipLaunchKernelGGL(gmg_up_kernel<4>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active); break;
+  }
+}
+
+void launch_gmg_coarse_inverse(const float* a, const float* b, double* inv, int mc, int B,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(gmg_coarse_inverse_kernel, dim3(B), dim3(256), 0, st, a, b, inv, mc);
+}
+
+void launch_gmg_coarse_solve(const double* inv, const float* a, const float* b, const float* rhs,
+                             bool scaled, void* out, int mode, const int* flags, int mc, int B,
+                             const int* active, hipStream_t st) {
+  hipLaunchKernelGGL(gmg_coarse_solve_kernel, dim3(B), dim3(256), 0, st, inv, a, b, rhs,
+                     (int)scaled, out, mode, flags, mc, active);
+}
+
+void launch_gmg_inject(const float* a, float* ac, int m, int B, hipStream_t st) {
+  const int mc = (m - 1) / 2;
+  const size_t total = (size_t)B * mc * mc;
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(gmg_inject_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, a, ac, m, B);
+}
+
+}  // namespace mg

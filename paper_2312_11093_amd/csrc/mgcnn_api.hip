@@ -13,6 +13,7 @@
 #include "../../include/mgcnn.h"
 #include "mgcnn_internal.h"
 #include "mgcnn_ctx.h"
+#include "mgcnn_gmg.h"
 
 using namespace mg;
 
@@ -110,6 +111,7 @@ void free_problem(mgcnn_ctx* c) {
   for (auto p : c->xin) fr(p);
   for (auto p : c->xdn) fr(p);
   c->s.clear(); c->xin.clear(); c->xdn.clear();
+  gmg_free(c);
   c->d_a = c->d_b = c->d_rt = nullptr;
   c->d_partial = c->d_nf2 = c->d_relres = nullptr;
   c->d_active = c->d_plist = c->d_status = c->d_iters = nullptr;
@@ -148,11 +150,15 @@ int ensure_problem(mgcnn_ctx* c, int n, int B) {
   if ((r = alloc(c, (void**)&c->d_iters, (size_t)B * 4))) return r;
   if ((r = alloc(c, (void**)&c->d_relres, (size_t)B * 8))) return r;
   c->s.assign(L, nullptr); c->xin.assign(L, nullptr); c->xdn.assign(L, nullptr);
+  if (c->gmg_on()) {
+    if ((r = gmg_alloc(c, n, B))) return r;
+  } else {
   for (int l = 0; l < L; ++l) {
     const size_t bytes = (size_t)c->nl[l] * c->nl[l] * B * C * c->state_bytes();
     if ((r = alloc(c, &c->s[l], (size_t)c->nl[l] * c->nl[l] * B * C * c->s_bytes()))) return r;
     if ((r = alloc(c, &c->xin[l], bytes))) return r;
     if ((r = alloc(c, &c->xdn[l], bytes))) return r;
+  }
   }
   c->alloc_n = n;
   c->alloc_B = B;
@@ -203,6 +209,7 @@ int run_chunk(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int 
 // stored into u (u = B(rt)) when !accumulate.
 int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool accumulate,
            const int* flags) {
+  if (c->gmg_on()) return gmg_cycle(c, u, u_f64, active, count, accumulate, flags);
   const StateType st = c->st();
   const int L = c->L, B = count;
   hipStream_t s = c->stream;
@@ -294,6 +301,10 @@ void mgcnn_default_opts(mgcnn_opts* o) {
   o->s_bf16 = 0;
   o->inner_steps = 1;
   o->gs_passes = 2;
+  o->precond = MGCNN_PRECOND_NETWORK;
+  o->gmg_levels = 0;
+  o->gmg_sweeps = 3;
+  o->gmg_omega = 0.67f;
 }
 
 size_t mgcnn_num_weights(int channels) {
@@ -317,6 +328,9 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.inner_steps < 1 || o.inner_steps > 16) return MGCNN_E_ARG;
   if (o.gs_passes != 1 && o.gs_passes != 2) return MGCNN_E_ARG;
   if (o.method == MGCNN_METHOD_FGMRES && (o.restart < 1 || o.restart > 63)) return MGCNN_E_ARG;
+  if (o.precond != MGCNN_PRECOND_NETWORK && o.precond != MGCNN_PRECOND_GMG) return MGCNN_E_ARG;
+  if (o.gmg_levels < 0 || o.gmg_sweeps < 1 || o.gmg_sweeps > GMG_MAX_SWEEPS) return MGCNN_E_ARG;
+  if (!(o.gmg_omega > 0.f && o.gmg_omega < 2.f)) return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
   if (!c) return MGCNN_E_NOMEM;
   c->opts = o;
@@ -354,6 +368,8 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
   if (B < 1) return fail(c, MGCNN_E_SIZE, "setup: batch must be >= 1");
   for (int i = 0; i < 2 * B; ++i)
     if (!std::isfinite(b_host[i])) return fail(c, MGCNN_E_ARG, "setup: non-finite velocity");
+  if (c->gmg_on() && gmg_levels_for(c, n) == 0)
+    return fail(c, MGCNN_E_ARG, "setup: gmg_levels out of range for this n");
   c->ready = false;
   int r = ensure_problem(c, n, B);
   if (r) return r;
@@ -363,6 +379,12 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
   const size_t nn = (size_t)n * n * B;
   HIP_TRY(c, hipMemcpyAsync(c->d_a, a, nn * 4, hipMemcpyDeviceToDevice, s));
   HIP_TRY(c, hipMemcpyAsync(c->d_b, b_host, (size_t)B * 2 * 4, hipMemcpyHostToDevice, s));
+  if (c->gmg_on()) {
+    if ((r = gmg_setup(c))) return r;
+    HIP_TRY(c, hipStreamSynchronize(s));   // b_host is read by the asynchronous copy above
+    c->ready = true;
+    return MGCNN_OK;
+  }
   // setup temporaries (f32): features, coefficient tensor (current, next), two ping-pong
   float *F = nullptr, *cc = nullptr, *cn = nullptr, *za = nullptr, *zb = nullptr;
   const size_t t16 = nn * C * 4;
@@ -479,6 +501,8 @@ int mgcnn_forward(mgcnn_ctx* c, const float* f, void* u, int K, int record) {
   if (!c) return MGCNN_E_ARG;
   if (!c->ready) return fail(c, MGCNN_E_STATE, "forward: call mgcnn_setup first");
   if (!f || !u || K < 0) return fail(c, MGCNN_E_ARG, "forward: bad argument");
+  if (record && c->gmg_on())
+    return fail(c, MGCNN_E_STATE, "forward: recording needs the network preconditioner");
   if (record) return forward_record(c, f, (float*)u, K);
   for (int k = 0; k < K; ++k) {
     {
@@ -524,6 +548,7 @@ int mgcnn_residual_norms(mgcnn_ctx* c, const float* f, const void* u, double* re
 int mgcnn_get_setup_tensor(mgcnn_ctx* c, int level, float* out) {
   if (!c) return MGCNN_E_ARG;
   if (!c->ready) return fail(c, MGCNN_E_STATE, "get_setup_tensor: no setup");
+  if (c->gmg_on()) return fail(c, MGCNN_E_STATE, "get_setup_tensor: no setup tensors with GMG");
   if (level < 1 || level > c->L || !out) return fail(c, MGCNN_E_ARG, "get_setup_tensor: bad level");
   const int m = c->nl[level - 1];
   const size_t cnt = (size_t)m * m * c->B * C;

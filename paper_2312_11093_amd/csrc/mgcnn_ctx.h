@@ -68,6 +68,17 @@ struct mgcnn_ctx {
     int* cyc = nullptr;       // problems live in the current restart cycle
   } kr;
 
+  // geometric multigrid preconditioner (opts.precond == MGCNN_PRECOND_GMG), per level l
+  struct Gmg {
+    int levels = 0;
+    std::vector<int> nl;                       // side of level l
+    std::vector<float*> a;                     // injected coefficient (l >= 1; level 0 is d_a)
+    std::vector<float*> rhs;                   // restricted residual (l >= 1; level 0 is d_rt)
+    std::vector<float*> pre;                   // correction after the pre-sweeps (l < levels-1)
+    std::vector<float*> cor;                   // final correction (l >= 1)
+    double* inv = nullptr;                     // [B][N][N] inverse of the coarsest operator^T
+  } gmg;
+
   // training: recorded forward (checkpoints of u_0..u_{K-1}) and reverse-pass workspace
   struct Train {
     int alloc_n = 0, alloc_B = 0, alloc_K = 0;
@@ -95,6 +106,7 @@ struct mgcnn_ctx {
     return opts.f32_split ? mg::ST_F32X : mg::ST_F32;
   }
   bool u64() const { return opts.u_dtype == MGCNN_U_F64; }
+  bool gmg_on() const { return opts.precond == MGCNN_PRECOND_GMG; }
   const float* W(size_t o) const { return d_w + o; }
 };
 

@@ -310,6 +310,7 @@ int mgcnn_loss(mgcnn_ctx* c, const float* f, const float* u, double* loss_host, 
 int mgcnn_backward(mgcnn_ctx* c, const float* dL_du, float* dL_dweights, float* dL_df) {
   if (!c) return MGCNN_E_ARG;
   if (!c->ready) return fail(c, MGCNN_E_STATE, "backward: call mgcnn_setup first");
+  if (c->gmg_on()) return fail(c, MGCNN_E_STATE, "backward: no weights with the GMG preconditioner");
   auto& T = c->tr;
   if (T.K <= 0 || T.f == nullptr || T.alloc_n != c->n || T.alloc_B != c->B)
     return fail(c, MGCNN_E_NORECORD, "backward: no recorded forward for this problem set");

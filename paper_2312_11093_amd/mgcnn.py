@@ -30,7 +30,9 @@ class mgcnn_opts(ctypes.Structure):
     _fields_ = [("channels", ctypes.c_int), ("state_dtype", ctypes.c_int), ("u_dtype", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("method", ctypes.c_int), ("restart", ctypes.c_int), ("f32_split", ctypes.c_int),
-                ("s_bf16", ctypes.c_int), ("inner_steps", ctypes.c_int), ("gs_passes", ctypes.c_int)]
+                ("s_bf16", ctypes.c_int), ("inner_steps", ctypes.c_int), ("gs_passes", ctypes.c_int),
+                ("precond", ctypes.c_int), ("gmg_levels", ctypes.c_int), ("gmg_sweeps", ctypes.c_int),
+                ("gmg_omega", ctypes.c_float)]
 
 
 class mgcnn_kernel_stat(ctypes.Structure):
@@ -42,7 +44,9 @@ class mgcnn_kernel_stat(ctypes.Structure):
 KERNEL_KINDS = {0: "residual", 1: "finalize", 2: "conv_in", 3: "smooth_down", 4: "restrict",
                 5: "smooth_up", 6: "prolong", 7: "out_update", 8: "smooth_in", 9: "smooth_out",
                 10: "krylov_apply_A", 11: "krylov_dots", 12: "krylov_orth", 13: "krylov_scale",
-                14: "krylov_combine", 15: "krylov_residual", 16: "scale_by_diag", 17: "zero"}
+                14: "krylov_combine", 15: "krylov_residual", 16: "scale_by_diag", 17: "zero",
+                18: "gmg_down", 19: "gmg_up", 20: "gmg_coarse"}
+PRECONDS = {"network": 0, "gmg": 1}
 
 EXPORTS = {
     # name: (restype, argtypes)
@@ -122,13 +126,36 @@ def _check_dev(t, dtype, name):
         raise ValueError(f"{name} must be contiguous")
 
 
+def _set_gmg(o, precond, levels, sweeps, omega):
+    o.precond = PRECONDS[precond]
+    o.gmg_levels = int(levels)
+    o.gmg_sweeps = int(sweeps)
+    o.gmg_omega = float(omega)
+
+
+def _weights_ptr(owner, weights, count):
+    """Host pointer to the flat float32 weights (kept alive on `owner`), or None (all zero;
+    allowed for the GMG preconditioner, which has no weights)."""
+    if weights is None:
+        owner._w = None
+        return None
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+    if w.size != count:
+        raise ValueError(f"expected {count} weights, got {w.size}")
+    owner._w = w
+    return w.ctypes.data
+
+
 class Solver:
     """One library context (weights + workspace for one problem set)."""
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", use_graph: bool = False,
                  check_every: int = 4, stream=None, method: str = "stationary", restart: int = 30,
                  f32_split: bool = True, s_bf16: bool = False, inner_steps: int = 1,
-                 gs_passes: int = 2):
+                 gs_passes: int = 2, precond: str = "network", gmg_levels: int = 0,
+                 gmg_sweeps: int = 3, gmg_omega: float = 0.67):
+        """weights: the flat network weights, or None with precond="gmg" (the geometric
+        multigrid baseline has none)."""
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -144,14 +171,13 @@ class Solver:
         o.s_bf16 = int(bool(s_bf16))
         o.inner_steps = int(inner_steps)
         o.gs_passes = int(gs_passes)
+        _set_gmg(o, precond, gmg_levels, gmg_sweeps, gmg_omega)
         self.opts = o
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
-        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
-        if w.size != self._L.mgcnn_num_weights(16):
-            raise ValueError(f"expected {self._L.mgcnn_num_weights(16)} weights, got {w.size}")
+        wp = _weights_ptr(self, weights, self._L.mgcnn_num_weights(16))
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
-        st = self._L.mgcnn_create(ctypes.byref(h), ctypes.byref(o), w.ctypes.data, ctypes.c_void_p(self._stream.cuda_stream))
+        st = self._L.mgcnn_create(ctypes.byref(h), ctypes.byref(o), wp, ctypes.c_void_p(self._stream.cuda_stream))
         if st != OK:
             raise MGCNNError(st, self._L.mgcnn_status_string(st).decode())
         self._h = h
@@ -294,7 +320,8 @@ class GroupSolver:
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", method: str = "stationary",
                  restart: int = 30, check_every: int = 4, f32_split: bool = True, s_bf16: bool = False,
-                 inner_steps: int = 1, gs_passes: int = 2, stream=None):
+                 inner_steps: int = 1, gs_passes: int = 2, stream=None, precond: str = "network",
+                 gmg_levels: int = 0, gmg_sweeps: int = 3, gmg_omega: float = 0.67):
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -308,11 +335,12 @@ class GroupSolver:
         o.s_bf16 = int(bool(s_bf16))
         o.inner_steps = int(inner_steps)
         o.gs_passes = int(gs_passes)
+        _set_gmg(o, precond, gmg_levels, gmg_sweeps, gmg_omega)
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
-        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        wp = _weights_ptr(self, weights, self._L.mgcnn_num_weights(16))
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
-        st = self._L.mgcnn_group_create(ctypes.byref(h), ctypes.byref(o), w.ctypes.data,
+        st = self._L.mgcnn_group_create(ctypes.byref(h), ctypes.byref(o), wp,
                                         ctypes.c_void_p(self._stream.cuda_stream))
         if st != OK:
             raise MGCNNError(st, self._L.mgcnn_status_string(st).decode())
