@@ -26,7 +26,9 @@ namespace mg {
 
 constexpr int GT = 32;          // output tile side (fine nodes); 16 x 16 coarse nodes
 
-__device__ __forceinline__ float harmf(float p, float q) { return (2.f * p * q) / (p + q); }
+// v_rcp_f32 (1 ulp): the preconditioner's stencil needs no correctly rounded division
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float harmf(float p, float q) { return (2.f * p * q) * rcpf(p + q); }
 
 // Stencil of node (i, j) of an m x m grid from the coefficient staged in LDS around it (la at
 // the node; +-1 and +-P its neighbours).  q = rhs / D (or rhs itself when already scaled).
@@ -43,13 +45,24 @@ __device__ __forceinline__ Node make_node(const float* la, int c, int P, int i, 
   const float aN = (i + 1 < m) ? harmf(ac, la[c + P]) : ac;
   const float aS = (i > 0) ? harmf(ac, la[c - P]) : ac;
   s.D = (aE + aW + aN + aS) * ih2 + (bxp - bxm + byp - bym) * ih;
-  const float iD = 1.f / s.D;
+  const float iD = rcpf(s.D);
   s.wW = (j > 0) ? (aW * ih2 + bxp * ih) * iD : 0.f;
   s.wE = (j + 1 < m) ? (aE * ih2 - bxm * ih) * iD : 0.f;
   s.wS = (i > 0) ? (aS * ih2 + byp * ih) * iD : 0.f;
   s.wN = (i + 1 < m) ? (aN * ih2 - bym * ih) * iD : 0.f;
   s.q = scaled ? rhs : rhs * iD;
   return s;
+}
+
+// Zero the padding ring of the two e buffers (every region node is written before it is read).
+template <int P>
+__device__ __forceinline__ void zero_ring(float* e0, float* e1, int tid) {
+  for (int t = tid; t < 4 * P; t += 256) {
+    const int side = t / P, r = t % P;
+    const int idx = side == 0 ? r : side == 1 ? (P - 1) * P + r : side == 2 ? r * P : r * P + P - 1;
+    e0[idx] = 0.f;
+    e1[idx] = 0.f;
+  }
 }
 
 // Tile geometry: the e-region of side RS around the tile, padded by one ring (P = RS + 2) that
@@ -83,13 +96,21 @@ __global__ __launch_bounds__(256) void gmg_down_kernel(const float* __restrict__
   const int oy = y0 - NU, ox = x0 - NU;    // grid coordinates of region node (0, 0)
   const size_t base = (size_t)b * m * m;
   const int tid = threadIdx.x;
+  // every global load of the tile is issued before the first barrier: the coefficient with its
+  // halo into LDS, the right-hand side of the tile's region nodes into registers
+  float rv[G::PTS];
+#pragma unroll
+  for (int k = 0; k < G::PTS; ++k) {
+    const int p = tid + 256 * k;
+    const int i = oy + p / RS, j = ox + p % RS;
+    rv[k] = (p < RS * RS && i >= 0 && i < m && j >= 0 && j < m) ? rhs[base + (size_t)i * m + j] : 0.f;
+  }
   for (int idx = tid; idx < P * P; idx += 256) {
     const int gi = oy - 1 + idx / P, gj = ox - 1 + idx % P;
     const bool in = gi >= 0 && gi < m && gj >= 0 && gj < m;
     la[idx] = in ? a[base + (size_t)gi * m + gj] : 0.f;
-    le[0][idx] = 0.f;
-    le[1][idx] = 0.f;
   }
+  zero_ring<P>(le[0], le[1], tid);
   const float ih = (float)(m + 1), ih2 = ih * ih;
   const float bx = bvec[2 * b], by = bvec[2 * b + 1];
   const float bxp = bx > 0.f ? bx : 0.f, bxm = bx < 0.f ? bx : 0.f;
@@ -103,16 +124,15 @@ __global__ __launch_bounds__(256) void gmg_down_kernel(const float* __restrict__
     const int ry = p / RS, rx = p % RS;
     const int i = oy + ry, j = ox + rx;
     const bool in = p < RS * RS && i >= 0 && i < m && j >= 0 && j < m;
+    const int c = (ry + 1) * P + rx + 1;
     if (in) {
-      const int c = (ry + 1) * P + rx + 1;
-      nd[k] = make_node(la, c, P, i, j, m, ih, ih2, bxp, bxm, byp, bym,
-                        rhs[base + (size_t)i * m + j], scaled != 0);
+      nd[k] = make_node(la, c, P, i, j, m, ih, ih2, bxp, bxm, byp, bym, rv[k], scaled != 0);
       ev[k] = omega * nd[k].q;                       // first sweep from zero
-      le[0][c] = ev[k];
     } else {
       nd[k] = Node{1.f, 0.f, 0.f, 0.f, 0.f, 0.f};    // outside the grid: e stays 0
       ev[k] = 0.f;
     }
+    if (p < RS * RS) le[0][c] = ev[k];
   }
   __syncthreads();
   const float om1 = 1.f - omega;
@@ -203,17 +223,28 @@ __global__ __launch_bounds__(256) void gmg_up_kernel(const float* __restrict__ a
   const size_t cbase = (size_t)b * mc * mc;
   const int cy = (oy - 1) >> 1, cx = (ox - 1) >> 1;    // coarse patch origin (may be -1)
   const int tid = threadIdx.x;
+  // global loads first: right-hand side and pre-smoothed e of the region nodes into registers,
+  // the coefficient with its halo and the coarse patch into LDS
+  float rv[G::PTS], pv[G::PTS];
+#pragma unroll
+  for (int k = 0; k < G::PTS; ++k) {
+    const int p = tid + 256 * k;
+    const int i = oy + p / RS, j = ox + p % RS;
+    const bool in = p < RS * RS && i >= 0 && i < m && j >= 0 && j < m;
+    const size_t g = base + (size_t)(in ? i : 0) * m + (in ? j : 0);
+    rv[k] = in ? rhs[g] : 0.f;
+    pv[k] = in ? e_pre[g] : 0.f;
+  }
   for (int idx = tid; idx < P * P; idx += 256) {
     const int gi = oy - 1 + idx / P, gj = ox - 1 + idx % P;
     const bool in = gi >= 0 && gi < m && gj >= 0 && gj < m;
     la[idx] = in ? a[base + (size_t)gi * m + gj] : 0.f;
-    le[0][idx] = 0.f;
-    le[1][idx] = 0.f;
   }
   for (int idx = tid; idx < CS * CS; idx += 256) {
     const int I = cy + idx / CS, J = cx + idx % CS;
     lc[idx] = (I >= 0 && I < mc && J >= 0 && J < mc) ? ec[cbase + (size_t)I * mc + J] : 0.f;
   }
+  zero_ring<P>(le[0], le[1], tid);
   const float ih = (float)(m + 1), ih2 = ih * ih;
   const float bx = bvec[2 * b], by = bvec[2 * b + 1];
   const float bxp = bx > 0.f ? bx : 0.f, bxm = bx < 0.f ? bx : 0.f;
@@ -227,22 +258,21 @@ __global__ __launch_bounds__(256) void gmg_up_kernel(const float* __restrict__ a
     const int ry = p / RS, rx = p % RS;
     const int i = oy + ry, j = ox + rx;
     const bool in = p < RS * RS && i >= 0 && i < m && j >= 0 && j < m;
+    const int c = (ry + 1) * P + rx + 1;
     if (in) {
-      const int c = (ry + 1) * P + rx + 1;
-      const size_t g = base + (size_t)i * m + j;
-      nd[k] = make_node(la, c, P, i, j, m, ih, ih2, bxp, bxm, byp, bym, rhs[g], scaled != 0);
+      nd[k] = make_node(la, c, P, i, j, m, ih, ih2, bxp, bxm, byp, bym, rv[k], scaled != 0);
       // bilinear interpolation: fine i lies between coarse rows (i-1)>>1 and i>>1 (the same
       // row when i is odd); the four-term average gives weights 1, 1/2 and 1/4
       const int i0 = ((i - 1) >> 1) - cy, i1 = (i >> 1) - cy;
       const int j0 = ((j - 1) >> 1) - cx, j1 = (j >> 1) - cx;
       const float pe = 0.25f * ((lc[i0 * CS + j0] + lc[i0 * CS + j1]) +
                                 (lc[i1 * CS + j0] + lc[i1 * CS + j1]));
-      ev[k] = e_pre[g] + pe;
-      le[0][c] = ev[k];
+      ev[k] = pv[k] + pe;
     } else {
       nd[k] = Node{1.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       ev[k] = 0.f;
     }
+    if (p < RS * RS) le[0][c] = ev[k];
   }
   __syncthreads();
   const float om1 = 1.f - omega;
