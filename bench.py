@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-gmg", action="store_true",
+                    help="skip the geometric multigrid baseline (same outer method, same batch)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -274,6 +276,46 @@ def main():
         Sp.close()
         print("[bench] plain FP32 unbatched done", file=sys.stderr, flush=True)
 
+    # the paper's comparison solver on the same GPU: geometric multigrid (rediscretised coarse
+    # operators, bilinear transfers, 3 + 3 weighted-Jacobi sweeps with weight 0.67, exact
+    # coarsest solve) as the preconditioner of the same outer method, same batch and tolerance
+    gmg = None
+    if not args.no_gmg:
+        Sg = Solver(None, precond="gmg", u="f64", check_every=args.check_every, method=args.method,
+                    restart=args.restart, gs_passes=args.gs_passes)
+
+        def gstep():
+            u.zero_()
+            Sg.setup(da, b)
+            return Sg.solve(df, u, args.tol, args.maxit)
+
+        gstep()
+        gt, git = [], None
+        for k in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, git, _, gps = gstep()
+            torch.cuda.synchronize()
+            gt.append(time.perf_counter() - t0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Sg.setup(da, b)
+        torch.cuda.synchronize()
+        gsetup = time.perf_counter() - t0
+        gms = 1000.0 * float(np.mean(gt))
+        gconv = bool((gps == 0).all())
+        gcheck = [osv.relres(a[p], b[p], f[p], u[p].cpu().numpy()) for p in (0, B - 1)]
+        gmg = {"value": round(B / (gms / 1000.0), 3) if gconv else 0.0, "unit": "solves/s",
+               "ms_per_step": round(gms, 3), "setup_ms": round(1000 * gsetup, 3),
+               "converged": gconv, "mean_iters": float(np.mean(git)), "max_iters": int(np.max(git)),
+               "oracle_relres_sampled": [float(x) for x in gcheck],
+               "settings": {"levels": Sg.gmg_levels, "sweeps": 3, "omega": 0.67,
+                            "coarsest": "exact solve", "coarse_coefficient": "injection"},
+               "what": "geometric multigrid V-cycle (Sec. 2.3 / Sec. 4.1 settings) as the "
+                       "preconditioner of the same outer method, same batch and tolerance"}
+        Sg.close()
+        print("[bench] GMG baseline done", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(weights, a[0], b[0], f[0], mean_iters)
@@ -298,6 +340,9 @@ def main():
         "plain_fp32_unbatched": plain,
         "speedup_vs_plain_fp32": (round(value / plain["value"], 3)
                                   if plain and plain["value"] > 0 and converged else None),
+        "gmg_baseline": gmg,
+        "mgcnn_over_gmg": (round(value / gmg["value"], 3)
+                           if gmg and gmg["value"] > 0 and converged else None),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

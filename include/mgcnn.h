@@ -185,6 +185,10 @@ int mgcnn_residual(mgcnn_ctx *ctx, const float *f, const void *u, float *r);
  * [batch].  Blocks the host. */
 int mgcnn_residual_norms(mgcnn_ctx *ctx, const float *f, const void *u, double *relres_host);
 
+/* Levels of the GMG cycle of the current problem set (MGCNN_PRECOND_GMG after mgcnn_setup);
+ * 0 otherwise. */
+int mgcnn_gmg_levels(const mgcnn_ctx *ctx);
+
 /* Copy the level-l setup tensor (l = 1..L) into `out` [batch][n_l][n_l][16] float32 device
  * (network preconditioner only). */
 int mgcnn_get_setup_tensor(mgcnn_ctx *ctx, int level, float *out);

@@ -589,6 +589,10 @@ int mgcnn_profile_end(mgcnn_ctx* c, mgcnn_kernel_stat* stats, int max_stats, int
 
 int mgcnn_levels(const mgcnn_ctx* c) { return (c && c->ready) ? c->L : 0; }
 
+int mgcnn_gmg_levels(const mgcnn_ctx* c) {
+  return (c && c->ready && c->gmg_on()) ? c->gmg.levels : 0;
+}
+
 const char* mgcnn_status_string(int s) {
   switch (s) {
     case MGCNN_OK: return "ok";

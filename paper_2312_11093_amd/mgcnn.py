@@ -52,6 +52,7 @@ EXPORTS = {
     # name: (restype, argtypes)
     "mgcnn_default_opts": (None, [ctypes.POINTER(mgcnn_opts)]),
     "mgcnn_num_weights": (ctypes.c_size_t, [ctypes.c_int]),
+    "mgcnn_gmg_levels": (ctypes.c_int, [ctypes.c_void_p]),
     "mgcnn_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(mgcnn_opts),
                                     ctypes.c_void_p, ctypes.c_void_p]),
     "mgcnn_set_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -312,6 +313,11 @@ class Solver:
     @property
     def levels(self) -> int:
         return self._L.mgcnn_levels(self._h)
+
+    @property
+    def gmg_levels(self) -> int:
+        """Levels of the GMG cycle of the current problem set (0 with the network)."""
+        return self._L.mgcnn_gmg_levels(self._h)
 
 
 class GroupSolver:

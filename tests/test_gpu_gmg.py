@@ -65,6 +65,7 @@ def test_cycle_matches_oracle(workload, n, B, levels, sweeps, omega, tol):
     z = S.apply(dev(r)).cpu().numpy()
     for p in range(B):
         G = ogmg.GMG(a[p], b[p], levels=levels, omega=np.float32(omega), sweeps=sweeps)
+        assert S.gmg_levels == G.levels
         ref = G.cycle(r[p])
         err = np.abs(z[p] - ref).max() / np.abs(ref).max()
         say("  problem", p, "levels", G.levels, "rel max err", err)
