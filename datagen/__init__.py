@@ -17,11 +17,12 @@ Grid convention: ``n`` interior points per side on the unit square,
 ``h = 1/(n+1)``, node ``(i, j)`` sits at ``x = (j+1) h``, ``y = (i+1) h``;
 arrays are ``[i][j]`` (row = y, column = x).
 
-The coefficient families stand in for the paper's coefficient sources (Sec. 4.1
-white noise; Sec. 4.3 image datasets and multi-level data, Alg. 4), which are
-not reproduced; they follow the workloads this implementation is measured on:
+The coefficient families follow the workloads this implementation is measured on:
 lognormal Gaussian random fields, random block partitions, checkerboards and
-circular inclusions.
+circular inclusions; plus the paper's own test problems (Sec. 4.1 "Problem
+settings"): white-noise coefficients mapped log-uniformly onto [1/Re, 1], velocity
+(sin 0.5, cos 0.5), right-hand side 1, for the non-divergence operator.  The
+paper's image datasets (Sec. 4.3) are not reproduced.
 """
 from __future__ import annotations
 
@@ -34,6 +35,7 @@ __all__ = [
     "rng_for", "grf", "blocks_lognormal", "checkerboard", "inclusions",
     "mixture", "velocity", "rhs", "mldata", "weight_shapes", "num_weights",
     "xavier_weights", "Problem", "make_batch", "WORKLOADS", "levels_for", "var_sizes", "VAR_SIZES",
+    "white_noise_coef",
 ]
 
 WEIGHT_STREAM = 0x5EED
@@ -143,11 +145,26 @@ def mldata(n: int, rng: np.random.Generator, levels: int = 4, init_size: int = 5
     return interp(d, n)
 
 
+def white_noise_coef(n: int, rng: np.random.Generator, Re: float) -> np.ndarray:
+    """The paper's test coefficients (Sec. 4.1 "Problem settings"): a white-noise tensor
+    (i.i.d. N(0, 1)) mapped linearly onto [0, log10 Re] as a power p, then coef = 10^-p, so
+    the mesh Reynolds number 1/coef spans [1, Re].  coef = mu / h is the diffusion
+    coefficient in units of the mesh size; the returned field is mu = coef * h, the
+    coefficient of the physically scaled operator, whose rows are the paper's (Eq. (8)) times
+    1/h."""
+    w = rng.standard_normal((n, n))
+    p = math.log10(Re) * (w - w.min()) / (w.max() - w.min())
+    return 10.0 ** (-p) / (n + 1)
+
+
 def velocity(rng: np.random.Generator, kind: str) -> np.ndarray:
     """Constant convection velocity b = (bx, by): ``"unit"`` gives (1, 1);
-    ``"random"`` gives |b| (cos t, sin t) with t ~ U(0, 2 pi), |b| ~ U(0, 10)."""
+    ``"random"`` gives |b| (cos t, sin t) with t ~ U(0, 2 pi), |b| ~ U(0, 10);
+    ``"paper"`` gives the unit vector (sin 0.5, cos 0.5) of Sec. 4.1."""
     if kind == "unit":
         return np.array([1.0, 1.0])
+    if kind == "paper":
+        return np.array([math.sin(0.5), math.cos(0.5)])
     theta = rng.uniform(0.0, 2.0 * math.pi)
     mag = rng.uniform(0.0, 10.0)
     return np.array([mag * math.cos(theta), mag * math.sin(theta)])
@@ -214,8 +231,10 @@ class Workload:
     coef: str          # "grf", "blocks", "mixture"
     grf_length: float
     grf_variance: float
-    vel: str           # "unit" | "random"
-    f_kind: str        # "uniform" | "normal"
+    vel: str           # "unit" | "random" | "paper"
+    f_kind: str        # "uniform" | "normal" | "ones"
+    re: float = 0.0    # "white" coefficients: the range limit Re of the mesh Reynolds number
+    form: str = "div"  # operator the workload is posed for: "div" or "nondiv"
 
 
 WORKLOADS = {
@@ -229,6 +248,11 @@ WORKLOADS = {
     "mixture127": Workload("mixture127", 4, "mixture", 0.1, 1.0, "random", "normal"),
     # uneven-size mixture (sizes 63..2047)
     "mixture_var": Workload("mixture_var", 5, "mixture", 0.1, 1.0, "random", "normal"),
+    # the paper's test problems (Sec. 4.1, Sec. 4.3): non-divergence operator, white-noise
+    # coefficients with mesh Reynolds number in [1, Re], v = (sin 0.5, cos 0.5), rhs = 1
+    "paper_re10": Workload("paper_re10", 6, "white", 0.0, 0.0, "paper", "ones", 10.0, "nondiv"),
+    "paper_re1e3": Workload("paper_re1e3", 7, "white", 0.0, 0.0, "paper", "ones", 1e3, "nondiv"),
+    "paper_re1e5": Workload("paper_re1e5", 8, "white", 0.0, 0.0, "paper", "ones", 1e5, "nondiv"),
 }
 
 
@@ -249,6 +273,8 @@ def make_problem(workload: str, n: int, index: int, seed: int = 0) -> Problem:
         a = blocks_lognormal(n, ra)
     elif w.coef == "mixture":
         a = mixture(n, ra)
+    elif w.coef == "white":
+        a = white_noise_coef(n, ra, w.re)
     else:
         raise ValueError(w.coef)
     b = velocity(rng_for(seed, w.wid, index, STREAM_B), w.vel)

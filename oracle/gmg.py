@@ -73,17 +73,18 @@ def restrict(r: np.ndarray) -> np.ndarray:
     return rc
 
 
-def jacobi(a, b, D, e, r, omega: float, sweeps: int) -> np.ndarray:
+def jacobi(a, b, D, e, r, omega: float, sweeps: int, form: str = "div") -> np.ndarray:
     """`sweeps` weighted-Jacobi steps on A e = r from e."""
     for _ in range(sweeps):
-        e = e + omega * (r - op.apply_A(a, b, e)) / D
+        e = e + omega * (r - op.apply_A(a, b, e, form)) / D
     return e
 
 
 class GMG:
     """Hierarchy of rediscretised operators for one problem (a, b) and its V-cycle."""
 
-    def __init__(self, a, b, levels: int | None = None, omega: float = OMEGA, sweeps: int = SWEEPS):
+    def __init__(self, a, b, levels: int | None = None, omega: float = OMEGA, sweeps: int = SWEEPS,
+                 form: str = "div"):
         a = np.asarray(a, dtype=np.float64)
         self.b = np.asarray(b, dtype=np.float64)
         self.n = a.shape[0]
@@ -96,19 +97,21 @@ class GMG:
         self.a = [a]
         for _ in range(self.levels - 1):
             self.a.append(inject(self.a[-1]))
-        self.D = [op.diagonal(al, self.b) for al in self.a]
+        self.form = form
+        self.D = [op.diagonal(al, self.b, form) for al in self.a]
 
     def A(self, l: int, e):
-        return op.apply_A(self.a[l], self.b, e)
+        return op.apply_A(self.a[l], self.b, e, self.form)
 
     def _cycle(self, l: int, r):
         a, D = self.a[l], self.D[l]
         if l + 1 == self.levels:
-            return spla.spsolve(op.assemble_A(a, self.b).tocsc(), r.ravel()).reshape(r.shape)
-        e = jacobi(a, self.b, D, np.zeros_like(r), r, self.omega, self.sweeps)
+            A = op.assemble_A(a, self.b, self.form).tocsc()
+            return spla.spsolve(A, r.ravel()).reshape(r.shape)
+        e = jacobi(a, self.b, D, np.zeros_like(r), r, self.omega, self.sweeps, self.form)
         rc = restrict(r - self.A(l, e))
         e = e + prolong(self._cycle(l + 1, rc))
-        return jacobi(a, self.b, D, e, r, self.omega, self.sweeps)
+        return jacobi(a, self.b, D, e, r, self.omega, self.sweeps, self.form)
 
     def cycle(self, r) -> np.ndarray:
         """One V-cycle: a correction e ~ A^{-1} r from a zero initial guess."""

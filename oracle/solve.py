@@ -27,19 +27,21 @@ DIVERGENCE_LIMIT = 1e10
 class Solver:
     """Setup once for one problem (a, b), then iterate (Sec. 3.1, network phases)."""
 
-    def __init__(self, weights: np.ndarray, a: np.ndarray, b, levels: int | None = None):
+    def __init__(self, weights: np.ndarray, a: np.ndarray, b, levels: int | None = None,
+                 form: str = "div"):
         self.C = net.channels_of(np.asarray(weights).size)
         self.P = net.unpack_weights(weights, self.C)
         self.a = np.asarray(a, dtype=np.float64)
         self.b = np.asarray(b, dtype=np.float64)
         self.n = self.a.shape[0]
         self.L = levels if levels is not None else net.num_levels(self.n)
-        self.D = op.diagonal(self.a, self.b)
-        self.F = op.features(self.a, self.b)
+        self.form = form
+        self.D = op.diagonal(self.a, self.b, form)
+        self.F = op.features(self.a, self.b, form)
         self.s = net.setup(self.P, self.F, self.L)
 
     def residual(self, f, u):
-        return np.asarray(f, dtype=np.float64) - op.apply_A(self.a, self.b, u)
+        return np.asarray(f, dtype=np.float64) - op.apply_A(self.a, self.b, u, self.form)
 
     def correction(self, r):
         return net.vcycle(self.P, self.s, r / self.D)
@@ -89,9 +91,9 @@ def stationary(it, f, tol: float, maxit: int, u0=None):
         k += 1
 
 
-def relres(a, b, f, u) -> float:
+def relres(a, b, f, u, form: str = "div") -> float:
     f = np.asarray(f, dtype=np.float64)
-    r = f - op.apply_A(np.asarray(a, dtype=np.float64), b, u)
+    r = f - op.apply_A(np.asarray(a, dtype=np.float64), b, u, form)
     return math.sqrt(float(np.sum(r * r))) / math.sqrt(float(np.sum(f * f)))
 
 
