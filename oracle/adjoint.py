@@ -126,20 +126,20 @@ def setup_backward(P, F, stape, g_s, dP):
     dP["W_sc"] += conv_same_dW(g_c[0], F)
 
 
-def loss_terms(a, b, f, u, N: int):
+def loss_terms(a, b, f, u, N: int, form: str = "div"):
     """Per-problem share of the loss and its partial derivatives:
     returns (||r||^2 / (N ||f||^2), dL/du, dL/df) with r = f - A u, where dL/df
     includes the dependence of the normalisation ||f||^2 on f."""
     f = np.asarray(f, dtype=np.float64)
-    r = f - op.apply_A(a, b, u)
+    r = f - op.apply_A(a, b, u, form)
     nf2 = float(np.sum(f * f))
     rr = float(np.sum(r * r))
-    dLdu = -2.0 * op.apply_AT(a, b, r) / (N * nf2)
+    dLdu = -2.0 * op.apply_AT(a, b, r, form) / (N * nf2)
     dLdf = 2.0 * r / (N * nf2) - 2.0 * rr * f / (N * nf2 * nf2)
     return rr / (N * nf2), dLdu, dLdf
 
 
-def unrolled_backward(P, a, b, f, K: int, lam, dP):
+def unrolled_backward(P, a, b, f, K: int, lam, dP, form: str = "div"):
     """Reverse of K iterations from u_0 = 0 given lam = dL/du_K.  Accumulates the
     weight gradient into dP and returns dL/df through the iteration."""
     a = np.asarray(a, dtype=np.float64)
@@ -147,13 +147,13 @@ def unrolled_backward(P, a, b, f, K: int, lam, dP):
     f = np.asarray(f, dtype=np.float64)
     n = a.shape[0]
     L = net.num_levels(n)
-    D = op.diagonal(a, b)
-    F = op.features(a, b)
+    D = op.diagonal(a, b, form)
+    F = op.features(a, b, form)
     s, stape = net.setup(P, F, L, keep=True)
     u = np.zeros((n, n))
     tapes = []
     for _ in range(K):
-        r = f - op.apply_A(a, b, u)
+        r = f - op.apply_A(a, b, u, form)
         corr, tape = net.vcycle(P, s, r / D, keep=True)
         tapes.append(tape)
         u = u + corr
@@ -165,12 +165,13 @@ def unrolled_backward(P, a, b, f, K: int, lam, dP):
             g_s_tot[l] += g_s[l]
         g_r = g_rt / D
         df += g_r
-        lam = lam - op.apply_AT(a, b, g_r)
+        lam = lam - op.apply_AT(a, b, g_r, form)
     setup_backward(P, F, stape, g_s_tot, dP)
     return df, u
 
 
-def loss_and_grad(weights, a_batch, b_batch, f_batch, K: int, want_df: bool = False):
+def loss_and_grad(weights, a_batch, b_batch, f_batch, K: int, want_df: bool = False,
+                  form: str = "div"):
     """Loss after K unrolled iterations from zero and its gradient with respect to
     the flat weight vector (and optionally to every f_i).  Returns
     (loss, grad_flat[, df_list])."""
@@ -185,14 +186,14 @@ def loss_and_grad(weights, a_batch, b_batch, f_batch, K: int, want_df: bool = Fa
         a = np.asarray(a_batch[i], dtype=np.float64)
         b = np.asarray(b_batch[i], dtype=np.float64)
         f = np.asarray(f_batch[i], dtype=np.float64)
-        s = net.setup(P, op.features(a, b), net.num_levels(a.shape[0]))
+        s = net.setup(P, op.features(a, b, form), net.num_levels(a.shape[0]))
         u = np.zeros_like(f)
-        D = op.diagonal(a, b)
+        D = op.diagonal(a, b, form)
         for _ in range(K):
-            u = u + net.vcycle(P, s, (f - op.apply_A(a, b, u)) / D)
-        li, dLdu, dLdf = loss_terms(a, b, f, u, N)
+            u = u + net.vcycle(P, s, (f - op.apply_A(a, b, u, form)) / D)
+        li, dLdu, dLdf = loss_terms(a, b, f, u, N, form)
         total += li
-        df_iter, _ = unrolled_backward(P, a, b, f, K, dLdu, dP)
+        df_iter, _ = unrolled_backward(P, a, b, f, K, dLdu, dP, form)
         dfs.append(dLdf + df_iter)
     grad = net.pack_weights(dP, C)
     if want_df:

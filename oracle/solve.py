@@ -97,12 +97,12 @@ def relres(a, b, f, u, form: str = "div") -> float:
     return math.sqrt(float(np.sum(r * r))) / math.sqrt(float(np.sum(f * f)))
 
 
-def loss(a_batch, b_batch, f_batch, u_batch) -> float:
+def loss(a_batch, b_batch, f_batch, u_batch, form: str = "div") -> float:
     """Mean over the batch of ||f_i - A_i u_i||^2 / ||f_i||^2."""
     N = len(f_batch)
     tot = 0.0
     for i in range(N):
         f = np.asarray(f_batch[i], dtype=np.float64)
-        r = f - op.apply_A(np.asarray(a_batch[i], dtype=np.float64), b_batch[i], u_batch[i])
+        r = f - op.apply_A(np.asarray(a_batch[i], dtype=np.float64), b_batch[i], u_batch[i], form)
         tot += float(np.sum(r * r)) / float(np.sum(f * f))
     return tot / N

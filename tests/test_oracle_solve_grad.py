@@ -147,6 +147,30 @@ def test_gradient_wrt_rhs():
         assert abs(dfs[0][i, j] - fd) <= 1e-6 * max(abs(fd), 1e-4)
 
 
+def test_gradient_nondiv_form():
+    """The reverse mode with the non-divergence operator (Eq. (7)): loss value and
+    directional central differences."""
+    C, n, K = 3, 7, 2
+    rng = np.random.default_rng(8)
+    w = datagen.xavier_weights(C, 5).astype(np.float64) * 0.5
+    batch = ([np.exp(rng.standard_normal((n, n)))], [np.array([0.4, 0.9])],
+             [rng.standard_normal((n, n))])
+    L0, g = adj.loss_and_grad(w, *batch, K, form="nondiv")
+
+    def loss(wv):
+        us = [sv.Solver(wv, a, b, form="nondiv").forward(f, K) for a, b, f in zip(*batch)]
+        return sv.loss(*batch, us, form="nondiv")
+
+    assert L0 == pytest.approx(loss(w), rel=1e-13)
+    assert L0 != pytest.approx(_loss(w, batch, K), rel=1e-6)     # the form matters here
+    h = 1e-3
+    for _ in range(6):
+        d = rng.standard_normal(w.size)
+        d /= np.linalg.norm(d)
+        fd = (loss(w + h * d) - loss(w - h * d)) / (2 * h)
+        assert abs(g @ d - fd) <= 1e-5 * max(abs(fd), 1e-6)
+
+
 def test_solve_network_adjoint_identity():
     """<B x, y> = <x, B^T y> for the reverse of one solve-network application."""
     C, n = 4, 15
