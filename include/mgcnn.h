@@ -15,10 +15,11 @@
  *   - Fields are row-major [batch][n][n] (index i*n + j, j along +x, i along +y), contiguous,
  *     16-byte aligned, in DEVICE memory owned by the caller.  `b` (the constant velocity of
  *     each problem, [batch][2] = (bx, by)) is in HOST memory.
- *   - Operator: divergence-form 5-point diffusion with harmonic-mean face coefficients (a
- *     boundary face uses the interior node's a) plus first-order upwind convection (Sec. 2.5,
- *     Eqs. (8)-(12)); physical scaling 1/h^2 and 1/h.  D = diag(A).  The network acts on the
- *     row-scaled residual (f - A u) / D.
+ *   - Operator: 5-point diffusion plus first-order upwind convection (Sec. 2.5, Eqs. (8)-(12)),
+ *     physical scaling 1/h^2 and 1/h; by default the divergence form with harmonic-mean face
+ *     coefficients (a boundary face uses the interior node's a), or the non-divergence form of
+ *     Eq. (7) (opts.op_form).  D = diag(A).  The network acts on the row-scaled residual
+ *     (f - A u) / D.
  *   - Weights: one flat float32 host vector of mgcnn_num_weights(16) = 21664 entries in the
  *     order: setup reChannel [16][4][3][3]; 4 x (setup ResNet conv [16][16][3][3], bias [16]);
  *     setup restriction [16][16][3][3]; solve reChannel-in [16][1][3][3]; down smoother, up
@@ -70,6 +71,14 @@ enum {
                                    the cycle applied to r.  No weights, no setup network; training
                                    entry points return MGCNN_E_STATE. */
 };
+/* Form of the operator A(a, b) (both: 5-point diffusion + first-order upwind convection, zero
+ * Dirichlet values, physical scaling 1/h^2 and 1/h). */
+enum {
+  MGCNN_OP_DIV = 0,     /* -div(a grad u) + b . grad u (Eq. (12)): the face coefficient between two
+                           nodes is the harmonic mean of their a (a boundary face: the node's a) */
+  MGCNN_OP_NONDIV = 1   /* -a (u_xx + u_yy) + b . grad u (Eq. (7), the form the paper computes
+                           with): every face of row (i, j) takes a[i][j] */
+};
 /* Outer method of mgcnn_solve. */
 enum {
   MGCNN_METHOD_STATIONARY = 0,  /* u += B((f - A u)/D), Sec. 2.2 Eq. (1) */
@@ -103,6 +112,7 @@ typedef struct {
                        at most 15 x 15 nodes), checked by mgcnn_setup (MGCNN_E_ARG) */
   int gmg_sweeps;   /* GMG only: sweeps before and after the coarse correction, 1..4 (default 3) */
   float gmg_omega;  /* GMG only: weighted-Jacobi weight, in (0, 2) (default 0.67) */
+  int op_form;      /* MGCNN_OP_DIV (default) or MGCNN_OP_NONDIV: the operator of every call */
 } mgcnn_opts;
 
 /* Default options: 16 channels, f32 state (split-bf16 matrix arithmetic), f64 u, graphs off,

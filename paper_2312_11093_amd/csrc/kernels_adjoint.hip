@@ -265,15 +265,17 @@ int launch_bias_grad(const float* g, const float* t, float* partial, size_t npx,
 template <typename R>
 __device__ __forceinline__ R harm2(R p, R q) { return (R(2) * p * q) / (p + q); }
 
-// Entries of row (i, j) of A (divergence form, harmonic faces, upwind convection).
+// Entries of row (i, j) of A (harmonic faces in the divergence form, the row's own node value
+// in the non-divergence form; upwind convection).
 struct Row { double C, E, W, N, S; };
-__device__ __forceinline__ Row row_of(const float* Ab, int n, int i, int j, double bx, double by) {
+__device__ __forceinline__ Row row_of(const float* Ab, int n, int i, int j, double bx, double by,
+                                      int form) {
   const size_t ij = (size_t)i * n + j;
   const double ac = Ab[ij];
-  const double aE = (j + 1 < n) ? harm2<double>(ac, Ab[ij + 1]) : ac;
-  const double aW = (j > 0) ? harm2<double>(ac, Ab[ij - 1]) : ac;
-  const double aN = (i + 1 < n) ? harm2<double>(ac, Ab[ij + n]) : ac;
-  const double aS = (i > 0) ? harm2<double>(ac, Ab[ij - n]) : ac;
+  const double aE = (j + 1 < n && !form) ? harm2<double>(ac, Ab[ij + 1]) : ac;
+  const double aW = (j > 0 && !form) ? harm2<double>(ac, Ab[ij - 1]) : ac;
+  const double aN = (i + 1 < n && !form) ? harm2<double>(ac, Ab[ij + n]) : ac;
+  const double aS = (i > 0 && !form) ? harm2<double>(ac, Ab[ij - n]) : ac;
   const double ih = (double)(n + 1), ih2 = ih * ih;
   const double bxp = bx > 0 ? bx : 0, bxm = bx < 0 ? bx : 0;
   const double byp = by > 0 ? by : 0, bym = by < 0 ? by : 0;
@@ -296,7 +298,8 @@ __global__ __launch_bounds__(256) void apply_AT_kernel(const float* __restrict__
                                                        const double* __restrict__ nf2, double alpha,
                                                        int div_by_diag, float* __restrict__ out,
                                                        float* __restrict__ df_acc, int n,
-                                                       int tiles_x, int tiles_per_prob, int N) {
+                                                       int tiles_x, int tiles_per_prob, int N,
+                                                       int form) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
@@ -309,12 +312,12 @@ __global__ __launch_bounds__(256) void apply_AT_kernel(const float* __restrict__
     const double x = V[(size_t)ii * n + jj];
     return div_by_diag ? x / r.C : x;
   };
-  const Row rc = row_of(Ab, n, i, j, bx, by);
+  const Row rc = row_of(Ab, n, i, j, bx, by, form);
   double s = rc.C * val(i, j, rc);
-  if (j > 0) { const Row r = row_of(Ab, n, i, j - 1, bx, by); s += r.E * val(i, j - 1, r); }
-  if (j + 1 < n) { const Row r = row_of(Ab, n, i, j + 1, bx, by); s += r.W * val(i, j + 1, r); }
-  if (i > 0) { const Row r = row_of(Ab, n, i - 1, j, bx, by); s += r.N * val(i - 1, j, r); }
-  if (i + 1 < n) { const Row r = row_of(Ab, n, i + 1, j, bx, by); s += r.S * val(i + 1, j, r); }
+  if (j > 0) { const Row r = row_of(Ab, n, i, j - 1, bx, by, form); s += r.E * val(i, j - 1, r); }
+  if (j + 1 < n) { const Row r = row_of(Ab, n, i, j + 1, bx, by, form); s += r.W * val(i, j + 1, r); }
+  if (i > 0) { const Row r = row_of(Ab, n, i - 1, j, bx, by, form); s += r.N * val(i - 1, j, r); }
+  if (i + 1 < n) { const Row r = row_of(Ab, n, i + 1, j, bx, by, form); s += r.S * val(i + 1, j, r); }
   double al = alpha;
   if (nf2 != nullptr) al = alpha / ((double)N * nf2[b]);
   const size_t c = (size_t)b * n * n + (size_t)i * n + j;
@@ -325,10 +328,10 @@ __global__ __launch_bounds__(256) void apply_AT_kernel(const float* __restrict__
 
 void launch_apply_AT(const float* a, const float* b, const float* v, const float* base,
                      const double* nf2, double alpha, bool div_by_diag, float* out, float* df_acc,
-                     int n, int B, hipStream_t st) {
+                     int n, int B, int form, hipStream_t st) {
   const int tx = (n + 63) / 64, ty = (n + 3) / 4;
   hipLaunchKernelGGL(apply_AT_kernel, dim3(tx * ty * B), dim3(256), 0, st, a, b, v, base, nf2, alpha,
-                     div_by_diag ? 1 : 0, out, df_acc, n, tx, tx * ty, B);
+                     div_by_diag ? 1 : 0, out, df_acc, n, tx, tx * ty, B, form);
 }
 
 // residual r = f - A u (u f32) into r, and per-problem partial sums of r^2
@@ -374,7 +377,8 @@ __global__ __launch_bounds__(256) void residual_plain_kernel(const float* __rest
                                                              const float* __restrict__ f,
                                                              const UT* __restrict__ u,
                                                              float* __restrict__ r, int n,
-                                                             int tiles_x, int tiles_per_prob) {
+                                                             int tiles_x, int tiles_per_prob,
+                                                             int form) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
@@ -382,7 +386,7 @@ __global__ __launch_bounds__(256) void residual_plain_kernel(const float* __rest
   if (i >= n || j >= n) return;
   const float* Ab = a + (size_t)b * n * n;
   const UT* U = u + (size_t)b * n * n;
-  const Row rw = row_of(Ab, n, i, j, bvec[2 * b], bvec[2 * b + 1]);
+  const Row rw = row_of(Ab, n, i, j, bvec[2 * b], bvec[2 * b + 1], form);
   const size_t ij = (size_t)i * n + j;
   double s = rw.C * (double)U[ij];
   if (j + 1 < n) s += rw.E * (double)U[ij + 1];
@@ -393,14 +397,14 @@ __global__ __launch_bounds__(256) void residual_plain_kernel(const float* __rest
 }
 
 void launch_residual_plain(const float* a, const float* b, const float* f, const void* u, bool u_f64,
-                           float* r, int n, int B, hipStream_t st) {
+                           float* r, int n, int B, int form, hipStream_t st) {
   const int tx = (n + 63) / 64, ty = (n + 3) / 4;
   if (u_f64)
     hipLaunchKernelGGL(residual_plain_kernel<double>, dim3(tx * ty * B), dim3(256), 0, st, a, b, f,
-                       (const double*)u, r, n, tx, tx * ty);
+                       (const double*)u, r, n, tx, tx * ty, form);
   else
     hipLaunchKernelGGL(residual_plain_kernel<float>, dim3(tx * ty * B), dim3(256), 0, st, a, b, f,
-                       (const float*)u, r, n, tx, tx * ty);
+                       (const float*)u, r, n, tx, tx * ty, form);
 }
 
 // elementwise y = x + z

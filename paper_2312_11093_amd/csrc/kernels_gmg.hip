@@ -31,19 +31,20 @@ __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ float harmf(float p, float q) { return (2.f * p * q) * rcpf(p + q); }
 
 // Stencil of node (i, j) of an m x m grid from the coefficient staged in LDS around it (la at
-// the node; +-1 and +-P its neighbours).  q = rhs / D (or rhs itself when already scaled).
+// the node; +-1 and +-P its neighbours; face coefficients per the operator form).  q = rhs / D
+// (or rhs itself when already scaled).
 struct Node {
   float D, wW, wE, wS, wN, q;
 };
 __device__ __forceinline__ Node make_node(const float* la, int c, int P, int i, int j, int m,
                                           float ih, float ih2, float bxp, float bxm, float byp,
-                                          float bym, float rhs, bool scaled) {
+                                          float bym, float rhs, bool scaled, int form) {
   Node s;
   const float ac = la[c];
-  const float aE = (j + 1 < m) ? harmf(ac, la[c + 1]) : ac;
-  const float aW = (j > 0) ? harmf(ac, la[c - 1]) : ac;
-  const float aN = (i + 1 < m) ? harmf(ac, la[c + P]) : ac;
-  const float aS = (i > 0) ? harmf(ac, la[c - P]) : ac;
+  const float aE = (j + 1 < m && !form) ? harmf(ac, la[c + 1]) : ac;
+  const float aW = (j > 0 && !form) ? harmf(ac, la[c - 1]) : ac;
+  const float aN = (i + 1 < m && !form) ? harmf(ac, la[c + P]) : ac;
+  const float aS = (i > 0 && !form) ? harmf(ac, la[c - P]) : ac;
   s.D = (aE + aW + aN + aS) * ih2 + (bxp - bxm + byp - bym) * ih;
   const float iD = rcpf(s.D);
   s.wW = (j > 0) ? (aW * ih2 + bxp * ih) * iD : 0.f;
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(256) void gmg_down_kernel(const float* __restrict__
                                                        float omega, float* __restrict__ e_out,
                                                        float* __restrict__ rc_out, int m,
                                                        int tiles_x, int tiles_per_prob,
-                                                       const int* __restrict__ active) {
+                                                       const int* __restrict__ active, int form) {
   constexpr int RS = GT + 1 + 2 * NU;      // region: tile rows y0 - NU .. y0 + GT + NU
   using G = Geo<RS>;
   constexpr int P = G::P;
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(256) void gmg_down_kernel(const float* __restrict__
     const bool in = p < RS * RS && i >= 0 && i < m && j >= 0 && j < m;
     const int c = (ry + 1) * P + rx + 1;
     if (in) {
-      nd[k] = make_node(la, c, P, i, j, m, ih, ih2, bxp, bxm, byp, bym, rv[k], scaled != 0);
+      nd[k] = make_node(la, c, P, i, j, m, ih, ih2, bxp, bxm, byp, bym, rv[k], scaled != 0, form);
       ev[k] = omega * nd[k].q;                       // first sweep from zero
     } else {
       nd[k] = Node{1.f, 0.f, 0.f, 0.f, 0.f, 0.f};    // outside the grid: e stays 0
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(256) void gmg_up_kernel(const float* __restrict__ a
                                                      const float* __restrict__ ec, void* out,
                                                      int mode, const int* __restrict__ flags,
                                                      int m, int tiles_x, int tiles_per_prob,
-                                                     const int* __restrict__ active) {
+                                                     const int* __restrict__ active, int form) {
   constexpr int RS = GT + 2 * NU;          // region: tile rows y0 - NU .. y0 + GT + NU - 1
   using G = Geo<RS>;
   constexpr int P = G::P;
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(256) void gmg_up_kernel(const float* __restrict__ a
     const bool in = p < RS * RS && i >= 0 && i < m && j >= 0 && j < m;
     const int c = (ry + 1) * P + rx + 1;
     if (in) {
-      nd[k] = make_node(la, c, P, i, j, m, ih, ih2, bxp, bxm, byp, bym, rv[k], scaled != 0);
+      nd[k] = make_node(la, c, P, i, j, m, ih, ih2, bxp, bxm, byp, bym, rv[k], scaled != 0, form);
       // bilinear interpolation: fine i lies between coarse rows (i-1)>>1 and i>>1 (the same
       // row when i is odd); the four-term average gives weights 1, 1/2 and 1/4
       const int i0 = ((i - 1) >> 1) - cy, i1 = (i >> 1) - cy;
@@ -323,7 +324,8 @@ __global__ __launch_bounds__(256) void gmg_up_kernel(const float* __restrict__ a
 // apply kernel wants: for each column k, the threads read consecutive entries.
 __global__ __launch_bounds__(256) void gmg_coarse_inverse_kernel(const float* __restrict__ a,
                                                                  const float* __restrict__ bvec,
-                                                                 double* __restrict__ inv, int mc) {
+                                                                 double* __restrict__ inv, int mc,
+                                                                 int form) {
   const int b = blockIdx.x;
   const int N = mc * mc;
   double* M = inv + (size_t)b * N * N;
@@ -339,10 +341,10 @@ __global__ __launch_bounds__(256) void gmg_coarse_inverse_kernel(const float* __
   for (int p = tid; p < N; p += 256) {
     const int i = p / mc, j = p % mc;
     const double ac = A[p];
-    const double aE = (j + 1 < mc) ? hm(ac, A[p + 1]) : ac;
-    const double aW = (j > 0) ? hm(ac, A[p - 1]) : ac;
-    const double aN = (i + 1 < mc) ? hm(ac, A[p + mc]) : ac;
-    const double aS = (i > 0) ? hm(ac, A[p - mc]) : ac;
+    const double aE = (j + 1 < mc && !form) ? hm(ac, A[p + 1]) : ac;
+    const double aW = (j > 0 && !form) ? hm(ac, A[p - 1]) : ac;
+    const double aN = (i + 1 < mc && !form) ? hm(ac, A[p + mc]) : ac;
+    const double aS = (i > 0 && !form) ? hm(ac, A[p - mc]) : ac;
     // row p of A stored as column p of M
     M[(size_t)p * N + p] = (aE + aW + aN + aS) * ih2 + (bxp - bxm + byp - bym) * ih;
     if (j + 1 < mc) M[(size_t)(p + 1) * N + p] = -aE * ih2 + bxm * ih;
@@ -387,7 +389,8 @@ __global__ __launch_bounds__(256) void gmg_coarse_solve_kernel(const double* __r
                                                                const float* __restrict__ rhs,
                                                                int scaled, void* out, int mode,
                                                                const int* __restrict__ flags,
-                                                               int mc, const int* __restrict__ active) {
+                                                               int mc, const int* __restrict__ active,
+                                                               int form) {
   const int b = active != nullptr ? active[blockIdx.x] : blockIdx.x;
   const int N = mc * mc;
   const int tid = threadIdx.x;
@@ -401,10 +404,10 @@ __global__ __launch_bounds__(256) void gmg_coarse_solve_kernel(const double* __r
       const double ih = (double)(mc + 1), ih2 = ih * ih;
       const double ac = A[tid];
       auto hm = [](double p, double q) { return 2.0 * p * q / (p + q); };
-      const double aE = (j + 1 < mc) ? hm(ac, A[tid + 1]) : ac;
-      const double aW = (j > 0) ? hm(ac, A[tid - 1]) : ac;
-      const double aN = (i + 1 < mc) ? hm(ac, A[tid + mc]) : ac;
-      const double aS = (i > 0) ? hm(ac, A[tid - mc]) : ac;
+      const double aE = (j + 1 < mc && !form) ? hm(ac, A[tid + 1]) : ac;
+      const double aW = (j > 0 && !form) ? hm(ac, A[tid - 1]) : ac;
+      const double aN = (i + 1 < mc && !form) ? hm(ac, A[tid + mc]) : ac;
+      const double aS = (i > 0 && !form) ? hm(ac, A[tid - mc]) : ac;
       const double bx = bvec[2 * b], by = bvec[2 * b + 1];
       r *= (aE + aW + aN + aS) * ih2 + (fabs(bx) + fabs(by)) * ih;
     }
@@ -442,41 +445,41 @@ __global__ __launch_bounds__(256) void gmg_inject_kernel(const float* __restrict
 static inline int tiles_1d(int m) { return (m + GT - 1) / GT; }
 
 void launch_gmg_down(int nu, const float* a, const float* b, const float* rhs, bool scaled,
-                     float omega, float* e, float* rc, int m, int B, const int* active,
+                     float omega, float* e, float* rc, int m, int B, const int* active, int form,
                      hipStream_t st) {
   const int tx = tiles_1d(m), tp = tx * tx;
   const dim3 grid(tp * B), block(256);
   switch (nu) {
-    case 1: hipLaunchKernelGGL(gmg_down_kernel<1>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active); break;
-    case 2: hipLaunchKernelGGL(gmg_down_kernel<2>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active); break;
-    case 3: hipLaunchKernelGGL(gmg_down_kernel<3>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active); break;
-    default: hipLaunchKernelGGL(gmg_down_kernel<4>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active); break;
+    case 1: hipLaunchKernelGGL(gmg_down_kernel<1>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active, form); break;
+    case 2: hipLaunchKernelGGL(gmg_down_kernel<2>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active, form); break;
+    case 3: hipLaunchKernelGGL(gmg_down_kernel<3>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active, form); break;
+    default: hipLaunchKernelGGL(gmg_down_kernel<4>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e, rc, m, tx, tp, active, form); break;
   }
 }
 
 void launch_gmg_up(int nu, const float* a, const float* b, const float* rhs, bool scaled,
                    float omega, const float* e_pre, const float* ec, void* out, int mode,
-                   const int* flags, int m, int B, const int* active, hipStream_t st) {
+                   const int* flags, int m, int B, const int* active, int form, hipStream_t st) {
   const int tx = tiles_1d(m), tp = tx * tx;
   const dim3 grid(tp * B), block(256);
   switch (nu) {
-    case 1: hipLaunchKernelGGL(gmg_up_kernel<1>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active); break;
-    case 2: hipLaunchKernelGGL(gmg_up_kernel<2>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active); break;
-    case 3: hipLaunchKernelGGL(gmg_up_kernel<3>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active); break;
-    default: hipLaunchKernelGGL(gmg_up_kernel<4>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active); break;
+    case 1: hipLaunchKernelGGL(gmg_up_kernel<1>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active, form); break;
+    case 2: hipLaunchKernelGGL(gmg_up_kernel<2>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active, form); break;
+    case 3: hipLaunchKernelGGL(gmg_up_kernel<3>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active, form); break;
+    default: hipLaunchKernelGGL(gmg_up_kernel<4>, grid, block, 0, st, a, b, rhs, (int)scaled, omega, e_pre, ec, out, mode, flags, m, tx, tp, active, form); break;
   }
 }
 
 void launch_gmg_coarse_inverse(const float* a, const float* b, double* inv, int mc, int B,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(gmg_coarse_inverse_kernel, dim3(B), dim3(256), 0, st, a, b, inv, mc);
+                               int form, hipStream_t st) {
+  hipLaunchKernelGGL(gmg_coarse_inverse_kernel, dim3(B), dim3(256), 0, st, a, b, inv, mc, form);
 }
 
 void launch_gmg_coarse_solve(const double* inv, const float* a, const float* b, const float* rhs,
                              bool scaled, void* out, int mode, const int* flags, int mc, int B,
-                             const int* active, hipStream_t st) {
+                             const int* active, int form, hipStream_t st) {
   hipLaunchKernelGGL(gmg_coarse_solve_kernel, dim3(B), dim3(256), 0, st, inv, a, b, rhs,
-                     (int)scaled, out, mode, flags, mc, active);
+                     (int)scaled, out, mode, flags, mc, active, form);
 }
 
 void launch_gmg_inject(const float* a, float* ac, int m, int B, hipStream_t st) {

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void kwalk_kernel(const float* __restrict__ a,
                                                     float* __restrict__ rt,
                                                     const double* __restrict__ sc, int n,
                                                     int tiles_x, int tiles_per_prob,
-                                                    const int* __restrict__ active) {
+                                                    const int* __restrict__ active, int form) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void kwalk_kernel(const float* __restrict__ a,
   const int dE = hasE ? 1 : 0, dW = hasW ? 1 : 0;          // clamped offsets: branch-free loads
   const XT* X = (MODE == KW_NORMALIZE) ? nullptr : x + base;
   double ac = A[i0 * n + j];
-  double aS = (i0 > 0) ? kharm(ac, (double)A[(i0 - 1) * n + j]) : ac;
+  double aS = (i0 > 0 && !form) ? kharm(ac, (double)A[(i0 - 1) * n + j]) : ac;
   double xc = 0.0, xs = 0.0;
   if constexpr (MODE != KW_NORMALIZE) {
     xc = X[i0 * n + j];
@@ -87,9 +87,9 @@ __global__ __launch_bounds__(256) void kwalk_kernel(const float* __restrict__ a,
     const bool hasN = i + 1 < n;
     const int dN = hasN ? n : 0;
     const double an = A[ij + dN];
-    const double aN = hasN ? kharm(ac, an) : ac;
-    const double aE = hasE ? kharm(ac, (double)A[ij + dE]) : ac;
-    const double aW = hasW ? kharm(ac, (double)A[ij - dW]) : ac;
+    const double aN = (hasN && !form) ? kharm(ac, an) : ac;
+    const double aE = (hasE && !form) ? kharm(ac, (double)A[ij + dE]) : ac;
+    const double aW = (hasW && !form) ? kharm(ac, (double)A[ij - dW]) : ac;
     const double sa = aE + aW + aN + aS;
     if constexpr (MODE == KW_NORMALIZE) {
       float* vp = y + (size_t)b * ystride + ij;
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void kwalk_kernel(const float* __restrict__ a,
         y[(size_t)b * ystride + ij] = (MODE == KW_RESIDUAL) ? (float)((double)f[base + ij] - Ax) : (float)Ax;
       xs = xc; xc = xn;
     }
-    ac = an; aS = aN;
+    ac = an; aS = form ? an : aN;   // next row's south face (own node value when form = 1)
   }
 }
 
@@ -119,42 +119,43 @@ static void kwalk_grid(int n, int B, dim3& grid, int& tx, int& tpp) {
 }
 
 void launch_apply_A(const float* a, const float* b, const float* x, float* y, size_t ystride, int n,
-                    int B, const int* active, hipStream_t st) {
+                    int B, const int* active, int form, hipStream_t st) {
   dim3 grid; int tx, tpp;
   kwalk_grid(n, B, grid, tx, tpp);
   hipLaunchKernelGGL((kwalk_kernel<float, KW_APPLY>), grid, dim3(256), 0, st, a, b, (const float*)nullptr,
-                     x, y, ystride, (float*)nullptr, (const double*)nullptr, n, tx, tpp, active);
+                     x, y, ystride, (float*)nullptr, (const double*)nullptr, n, tx, tpp, active, form);
 }
 
 void launch_krylov_residual(const float* a, const float* b, const float* f, const void* u, bool u_f64,
-                            float* r, size_t rstride, int n, int B, const int* active, hipStream_t st) {
+                            float* r, size_t rstride, int n, int B, const int* active, int form,
+                            hipStream_t st) {
   dim3 grid; int tx, tpp;
   kwalk_grid(n, B, grid, tx, tpp);
   if (u_f64)
     hipLaunchKernelGGL((kwalk_kernel<double, KW_RESIDUAL>), grid, dim3(256), 0, st, a, b, f,
                        (const double*)u, r, rstride, (float*)nullptr, (const double*)nullptr, n, tx, tpp,
-                       active);
+                       active, form);
   else
     hipLaunchKernelGGL((kwalk_kernel<float, KW_RESIDUAL>), grid, dim3(256), 0, st, a, b, f,
                        (const float*)u, r, rstride, (float*)nullptr, (const double*)nullptr, n, tx, tpp,
-                       active);
+                       active, form);
 }
 
 void launch_inner_residual(const float* a, const float* b, const float* v, const float* x, float* rt, int n,
-                           int B, const int* active, hipStream_t st) {
+                           int B, const int* active, int form, hipStream_t st) {
   dim3 grid; int tx, tpp;
   kwalk_grid(n, B, grid, tx, tpp);
   hipLaunchKernelGGL((kwalk_kernel<float, KW_INNER>), grid, dim3(256), 0, st, a, b, (const float*)nullptr,
-                     x, (float*)v, krylov_vpad(n), rt, (const double*)nullptr, n, tx, tpp, active);
+                     x, (float*)v, krylov_vpad(n), rt, (const double*)nullptr, n, tx, tpp, active, form);
 }
 
 void launch_normalize_diag(const float* a, const float* b, float* v, float* rt, const double* s, int n,
-                           int B, const int* active, hipStream_t st) {
+                           int B, const int* active, int form, hipStream_t st) {
   dim3 grid; int tx, tpp;
   kwalk_grid(n, B, grid, tx, tpp);
   hipLaunchKernelGGL((kwalk_kernel<float, KW_NORMALIZE>), grid, dim3(256), 0, st, a, b,
                      (const float*)nullptr, (const float*)nullptr, v, krylov_vpad(n), rt, s, n, tx, tpp,
-                     active);
+                     active, form);
 }
 
 // ---- Gram-Schmidt passes -----------------------------------------------------------------------

@@ -9,7 +9,8 @@
 namespace mg {
 
 // ------------------------------------------------------------------------------------------
-// Operator helpers (divergence form, harmonic face coefficients, first-order upwind).
+// Operator helpers (harmonic face coefficients in the divergence form, the row's own node
+// value in the non-divergence form; first-order upwind convection).
 // The discrete operator follows Sec. 2.5: 5-point diffusion (Eq. (8)) written for the
 // divergence form of Eq. (12), upwind convection split by the sign of the velocity
 // (Eqs. (9)-(11)); zero Dirichlet values outside the grid; a boundary face uses the
@@ -24,7 +25,7 @@ __device__ __forceinline__ R harm(R p, R q) { return (R(2) * p * q) / (p + q); }
 __global__ __launch_bounds__(256) void features_kernel(const float* __restrict__ a,
                                                        const float* __restrict__ bvec,
                                                        float* __restrict__ F, int n, int tiles_x,
-                                                       int tiles_per_prob) {
+                                                       int tiles_per_prob, int form) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
@@ -32,10 +33,10 @@ __global__ __launch_bounds__(256) void features_kernel(const float* __restrict__
   if (i >= n || j >= n) return;
   const float* A = a + (size_t)b * n * n;
   const double ac = A[(size_t)i * n + j];
-  const double aE = (j + 1 < n) ? harm<double>(ac, A[(size_t)i * n + j + 1]) : ac;
-  const double aW = (j > 0) ? harm<double>(ac, A[(size_t)i * n + j - 1]) : ac;
-  const double aN = (i + 1 < n) ? harm<double>(ac, A[(size_t)(i + 1) * n + j]) : ac;
-  const double aS = (i > 0) ? harm<double>(ac, A[(size_t)(i - 1) * n + j]) : ac;
+  const double aE = (j + 1 < n) ? (form ? ac : harm<double>(ac, A[(size_t)i * n + j + 1])) : ac;
+  const double aW = (j > 0) ? (form ? ac : harm<double>(ac, A[(size_t)i * n + j - 1])) : ac;
+  const double aN = (i + 1 < n) ? (form ? ac : harm<double>(ac, A[(size_t)(i + 1) * n + j])) : ac;
+  const double aS = (i > 0) ? (form ? ac : harm<double>(ac, A[(size_t)(i - 1) * n + j])) : ac;
   const double ih = (double)(n + 1), ih2 = ih * ih;
   const double bx = bvec[2 * b], by = bvec[2 * b + 1];
   const double bxp = bx > 0 ? bx : 0, bxm = bx < 0 ? bx : 0;
@@ -49,9 +50,10 @@ __global__ __launch_bounds__(256) void features_kernel(const float* __restrict__
   reinterpret_cast<float4*>(F)[((size_t)b * n + i) * n + j] = o;
 }
 
-void launch_features(const float* a, const float* b, float* F, int n, int B, hipStream_t st) {
+void launch_features(const float* a, const float* b, float* F, int n, int B, int form, hipStream_t st) {
   const int tx = (n + 63) / 64, ty = (n + 3) / 4;
-  hipLaunchKernelGGL(features_kernel, dim3(tx * ty * B), dim3(256), 0, st, a, b, F, n, tx, tx * ty);
+  hipLaunchKernelGGL(features_kernel, dim3(tx * ty * B), dim3(256), 0, st, a, b, F, n, tx, tx * ty,
+                     form);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__
                                                        float* __restrict__ rt,
                                                        double* __restrict__ partial, int n,
                                                        int tiles_x, int tiles_per_prob,
-                                                       const int* __restrict__ active) {
+                                                       const int* __restrict__ active, int form) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__
       R ac = (R)A[i0 * n + j];
       R uc = (R)U[i0 * n + j];
       R us = (i0 > 0) ? (R)U[(i0 - 1) * n + j] : R(0);
-      R aS = (i0 > 0) ? harm_fast<R>(ac, (R)A[(i0 - 1) * n + j]) : ac;
+      R aS = (i0 > 0 && !form) ? harm_fast<R>(ac, (R)A[(i0 - 1) * n + j]) : ac;
       const int dE = hasE ? 1 : 0, dW = hasW ? 1 : 0;       // clamped offsets: branch-free loads
 #pragma unroll 2
       for (int r = 0; r < RES_ROWS; ++r) {
@@ -121,9 +123,9 @@ __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__
         const R fv = (R)F[ij];
         const R an = an_raw;
         const R un = hasN ? un_raw : R(0);
-        const R aN = hasN ? harm_fast<R>(ac, an) : ac;
-        const R aE = hasE ? harm_fast<R>(ac, ae_raw) : ac;
-        const R aW = hasW ? harm_fast<R>(ac, aw_raw) : ac;
+        const R aN = (hasN && !form) ? harm_fast<R>(ac, an) : ac;
+        const R aE = (hasE && !form) ? harm_fast<R>(ac, ae_raw) : ac;
+        const R aW = (hasW && !form) ? harm_fast<R>(ac, aw_raw) : ac;
         const R uE = hasE ? ue_raw : R(0);
         const R uW = hasW ? uw_raw : R(0);
         const R sa = aE + aW + aN + aS;
@@ -135,7 +137,9 @@ __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__
           rt[base + ij] = (float)(rr * (R)__builtin_amdgcn_rcp((double)D));
         }
         r2 += (double)rr * (double)rr;
-        us = uc; uc = un; ac = an; aS = aN;
+        // the next row's south face: the same face in the divergence form, the next node's own
+        // value in the non-divergence form
+        us = uc; uc = un; ac = an; aS = form ? an : aN;
       }
     } else {
       (void)a; (void)bvec; (void)u; (void)rt;
@@ -152,18 +156,19 @@ __global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__
 }
 
 void launch_residual(const float* a, const float* b, const float* f, const void* u, bool u_f64,
-                     float* rt, double* partial, int n, int B, const int* active, hipStream_t st) {
+                     float* rt, double* partial, int n, int B, const int* active, int form,
+                     hipStream_t st) {
   const int tx = (n + 255) / 256, ty = (n + RES_ROWS - 1) / RES_ROWS;
   const dim3 grid(tx * ty * B), blk(256);
   if (u == nullptr) {
     hipLaunchKernelGGL((residual_kernel<double, double, false>), grid, blk, 0, st, a, b, f,
-                       (const double*)nullptr, rt, partial, n, tx, tx * ty, active);
+                       (const double*)nullptr, rt, partial, n, tx, tx * ty, active, form);
   } else if (u_f64) {
     hipLaunchKernelGGL((residual_kernel<double, double, true>), grid, blk, 0, st, a, b, f,
-                       (const double*)u, rt, partial, n, tx, tx * ty, active);
+                       (const double*)u, rt, partial, n, tx, tx * ty, active, form);
   } else {
     hipLaunchKernelGGL((residual_kernel<float, float, true>), grid, blk, 0, st, a, b, f,
-                       (const float*)u, rt, partial, n, tx, tx * ty, active);
+                       (const float*)u, rt, partial, n, tx, tx * ty, active, form);
   }
 }
 
@@ -459,7 +464,8 @@ __global__ __launch_bounds__(256) void scale_by_diag_kernel(const float* __restr
                                                             const float* __restrict__ bvec,
                                                             const float* __restrict__ r,
                                                             float* __restrict__ rt, int n,
-                                                            int tiles_x, int tiles_per_prob) {
+                                                            int tiles_x, int tiles_per_prob,
+                                                            int form) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int b = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
@@ -468,20 +474,20 @@ __global__ __launch_bounds__(256) void scale_by_diag_kernel(const float* __restr
   const float* A = a + (size_t)b * n * n;
   const size_t ij = (size_t)i * n + j;
   const double ac = A[ij];
-  const double aE = (j + 1 < n) ? harm<double>(ac, A[ij + 1]) : ac;
-  const double aW = (j > 0) ? harm<double>(ac, A[ij - 1]) : ac;
-  const double aN = (i + 1 < n) ? harm<double>(ac, A[ij + n]) : ac;
-  const double aS = (i > 0) ? harm<double>(ac, A[ij - n]) : ac;
+  const double aE = (j + 1 < n) ? (form ? ac : harm<double>(ac, A[ij + 1])) : ac;
+  const double aW = (j > 0) ? (form ? ac : harm<double>(ac, A[ij - 1])) : ac;
+  const double aN = (i + 1 < n) ? (form ? ac : harm<double>(ac, A[ij + n])) : ac;
+  const double aS = (i > 0) ? (form ? ac : harm<double>(ac, A[ij - n])) : ac;
   const double ih = (double)(n + 1);
   const double D = (aE + aW + aN + aS) * ih * ih + (fabs((double)bvec[2 * b]) + fabs((double)bvec[2 * b + 1])) * ih;
   rt[(size_t)b * n * n + ij] = (float)((double)r[(size_t)b * n * n + ij] / D);
 }
 
 void launch_scale_by_diag(const float* a, const float* b, const float* r, float* rt, int n, int B,
-                          hipStream_t st) {
+                          int form, hipStream_t st) {
   const int tx = (n + 63) / 64, ty = (n + 3) / 4;
   hipLaunchKernelGGL(scale_by_diag_kernel, dim3(tx * ty * B), dim3(256), 0, st, a, b, r, rt, n, tx,
-                     tx * ty);
+                     tx * ty, form);
 }
 
 }  // namespace mg

@@ -41,12 +41,12 @@ void launch_reduce_partials(const float* partial, int nblocks, int ne, float* ou
 int launch_bias_grad(const float* g, const float* t, float* partial, size_t npx, hipStream_t st);
 void launch_apply_AT(const float* a, const float* b, const float* v, const float* base,
                      const double* nf2, double alpha, bool div_by_diag, float* out, float* df_acc,
-                     int n, int B, hipStream_t st);
+                     int n, int B, int form, hipStream_t st);
 void launch_loss_finalize(const double* rr, const double* nf2, int B, double* loss, hipStream_t st);
 void launch_loss_df(const float* r, const float* f, const double* rr, const double* nf2, float* df,
                     int n, int B, hipStream_t st);
 void launch_residual_plain(const float* a, const float* b, const float* f, const void* u, bool u_f64,
-                           float* r, int n, int B, hipStream_t st);
+                           float* r, int n, int B, int form, hipStream_t st);
 void launch_add(const float* x, const float* z, float* y, size_t count, hipStream_t st);
 
 }  // namespace mg

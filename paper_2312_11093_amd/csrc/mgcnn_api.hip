@@ -41,7 +41,7 @@ WeightOffsets weight_offsets() {
 void launch_bf16_to_f32(const bf16_t* in, float* out, size_t count, hipStream_t st);
 void launch_zero_if_zero_rhs(void* u, bool u_f64, const double* nf2, int n, int B, hipStream_t st);
 void launch_scale_by_diag(const float* a, const float* b, const float* r, float* rt, int n, int B,
-                          hipStream_t st);
+                          int form, hipStream_t st);
 
 }  // namespace mg
 
@@ -271,7 +271,7 @@ int solve_step(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit) {
     const double nodes = (double)c->n * c->n * c->plist_count;
     Prof p(c, MGCNN_K_RESIDUAL, 0, nodes * (12.0 + (c->u64() ? 8 : 4)));
     launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->plist_count,
-                    c->d_plist, c->stream);
+                    c->d_plist, c->form(), c->stream);
   }
   {
     Prof p(c, MGCNN_K_FINALIZE, 0, (double)c->tiles * c->B * 8.0);
@@ -305,6 +305,7 @@ void mgcnn_default_opts(mgcnn_opts* o) {
   o->gmg_levels = 0;
   o->gmg_sweeps = 3;
   o->gmg_omega = 0.67f;
+  o->op_form = MGCNN_OP_DIV;
 }
 
 size_t mgcnn_num_weights(int channels) {
@@ -331,6 +332,7 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.precond != MGCNN_PRECOND_NETWORK && o.precond != MGCNN_PRECOND_GMG) return MGCNN_E_ARG;
   if (o.gmg_levels < 0 || o.gmg_sweeps < 1 || o.gmg_sweeps > GMG_MAX_SWEEPS) return MGCNN_E_ARG;
   if (!(o.gmg_omega > 0.f && o.gmg_omega < 2.f)) return MGCNN_E_ARG;
+  if (o.op_form != MGCNN_OP_DIV && o.op_form != MGCNN_OP_NONDIV) return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
   if (!c) return MGCNN_E_NOMEM;
   c->opts = o;
@@ -393,7 +395,7 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
   HIP_TRY(c, hipMallocAsync((void**)&cn, t16, s));
   HIP_TRY(c, hipMallocAsync((void**)&za, t16, s));
   HIP_TRY(c, hipMallocAsync((void**)&zb, t16, s));
-  launch_features(c->d_a, c->d_b, F, n, B, s);
+  launch_features(c->d_a, c->d_b, F, n, B, c->form(), s);
   launch_conv_in(4, F, c->W(c->off.setup_in), cc, ST_F32, n, B, nullptr, s);
   for (int l = 0; l < c->L; ++l) {
     const int m = c->nl[l];
@@ -447,7 +449,8 @@ int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, in
   hipStream_t s = c->stream;
   const int B = c->B;
   // ||f||^2 per problem
-  launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, c->n, B, nullptr, s);
+  launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, c->n, B, nullptr,
+                  c->form(), s);
   launch_sum_partials(c->d_partial, c->tiles, c->d_nf2, B, s);
   launch_solve_init(c->d_nf2, c->d_active, c->d_status, c->d_iters, c->d_relres, B, s);
   launch_zero_if_zero_rhs(u, c->u64(), c->d_nf2, c->n, B, s);
@@ -509,7 +512,7 @@ int mgcnn_forward(mgcnn_ctx* c, const float* f, void* u, int K, int record) {
       const double nodes = (double)c->n * c->n * c->B;
       Prof p(c, MGCNN_K_RESIDUAL, 0, nodes * (12.0 + (c->u64() ? 8 : 4)));
       launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->B, nullptr,
-                      c->stream);
+                      c->form(), c->stream);
     }
     int r = vcycle(c, u, c->u64(), nullptr, c->B);
     if (r) return r;
@@ -522,7 +525,7 @@ int mgcnn_apply(mgcnn_ctx* c, const float* r, float* z) {
   if (!c) return MGCNN_E_ARG;
   if (!c->ready) return fail(c, MGCNN_E_STATE, "apply: call mgcnn_setup first");
   if (!r || !z) return fail(c, MGCNN_E_ARG, "apply: null pointer");
-  launch_scale_by_diag(c->d_a, c->d_b, r, c->d_rt, c->n, c->B, c->stream);
+  launch_scale_by_diag(c->d_a, c->d_b, r, c->d_rt, c->n, c->B, c->form(), c->stream);
   return vcycle(c, z, false, nullptr, c->B, false);
 }
 
@@ -532,9 +535,11 @@ int mgcnn_residual_norms(mgcnn_ctx* c, const float* f, const void* u, double* re
   if (!f || !u || !relres_host) return fail(c, MGCNN_E_ARG, "residual: null pointer");
   hipStream_t s = c->stream;
   const int B = c->B;
-  launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, c->n, B, nullptr, s);
+  launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, c->n, B, nullptr,
+                  c->form(), s);
   launch_sum_partials(c->d_partial, c->tiles, c->d_nf2, B, s);
-  launch_residual(c->d_a, c->d_b, f, u, c->u64(), nullptr, c->d_partial, c->n, B, nullptr, s);
+  launch_residual(c->d_a, c->d_b, f, u, c->u64(), nullptr, c->d_partial, c->n, B, nullptr,
+                  c->form(), s);
   launch_sum_partials(c->d_partial, c->tiles, c->d_relres, B, s);
   LAUNCH_CHECK(c);
   std::vector<double> nf(B), rr(B);

@@ -107,6 +107,7 @@ struct mgcnn_ctx {
   }
   bool u64() const { return opts.u_dtype == MGCNN_U_F64; }
   bool gmg_on() const { return opts.precond == MGCNN_PRECOND_GMG; }
+  int form() const { return opts.op_form; }
   const float* W(size_t o) const { return d_w + o; }
 };
 

@@ -73,7 +73,7 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
   const int LD = KRYLOV_LD;
   const bool two_pass = c->opts.gs_passes != 1;
   // ||f||^2
-  launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, n, B, nullptr, s);
+  launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, n, B, nullptr, c->form(), s);
   launch_sum_partials(c->d_partial, c->tiles, c->d_nf2, B, s);
   launch_zero_if_zero_rhs(u, u64, c->d_nf2, n, B, s);
   std::vector<double> nf2(B);
@@ -112,7 +112,8 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
     if (nact == 0) break;
     {
       Prof p(c, MGCNN_K_KRYLOV_RESIDUAL, 0, nodes1 * nact * (12.0 + (u64 ? 8 : 4)));
-      launch_krylov_residual(c->d_a, c->d_b, f, u, u64, K.V, krylov_vpad(n), n, nact, K.act, s);
+      launch_krylov_residual(c->d_a, c->d_b, f, u, u64, K.V, krylov_vpad(n), n, nact, K.act,
+                             c->form(), s);
     }
     {
       Prof p(c, MGCNN_K_KRYLOV_DOTS, 0, nodes1 * nact * 4.0);
@@ -156,21 +157,21 @@ int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, i
       HIP_TRY(c, hipMemcpyAsync(K.s, sc.data(), (size_t)B * LD * 8, hipMemcpyHostToDevice, s));
       {
         Prof p(c, MGCNN_K_SCALE_BY_DIAG, 0, nodes * 16.0);
-        launch_normalize_diag(c->d_a, c->d_b, Vj, c->d_rt, K.s, n, nlive, K.act, s);
+        launch_normalize_diag(c->d_a, c->d_b, Vj, c->d_rt, K.s, n, nlive, K.act, c->form(), s);
       }
       if ((r = vcycle(c, Zj, false, K.act, nlive, false))) return r;
       // optional further stationary steps on v_j: z_j += B((v_j - A z_j) / D)
       for (int k = 1; k < c->opts.inner_steps; ++k) {
         {
           Prof p(c, MGCNN_K_KRYLOV_APPLY_A, 1, nodes * 16.0);
-          launch_inner_residual(c->d_a, c->d_b, Vj, Zj, c->d_rt, n, nlive, K.act, s);
+          launch_inner_residual(c->d_a, c->d_b, Vj, Zj, c->d_rt, n, nlive, K.act, c->form(), s);
         }
         if ((r = vcycle(c, Zj, false, K.act, nlive, true))) return r;
       }
       // w = A z_j
       {
         Prof p(c, MGCNN_K_KRYLOV_APPLY_A, 0, nodes * 12.0);
-        launch_apply_A(c->d_a, c->d_b, Zj, Vn, krylov_vpad(n), n, nlive, K.act, s);
+        launch_apply_A(c->d_a, c->d_b, Zj, Vn, krylov_vpad(n), n, nlive, K.act, c->form(), s);
       }
       // classical Gram-Schmidt applied twice, in three passes:
       //   h1 = V^T w ; w -= V h1 and h2 = V^T w ; w -= V h2 and |w|^2

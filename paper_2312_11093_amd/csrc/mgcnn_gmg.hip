@@ -57,7 +57,8 @@ int gmg_setup(mgcnn_ctx* c) {
   hipStream_t s = c->stream;
   for (int l = 1; l < L; ++l)
     launch_gmg_inject(l == 1 ? c->d_a : G.a[l - 1], G.a[l], G.nl[l - 1], B, s);
-  launch_gmg_coarse_inverse(L == 1 ? c->d_a : G.a[L - 1], c->d_b, G.inv, G.nl[L - 1], B, s);
+  launch_gmg_coarse_inverse(L == 1 ? c->d_a : G.a[L - 1], c->d_b, G.inv, G.nl[L - 1], B, c->form(),
+                            s);
   LAUNCH_CHECK(c);
   return MGCNN_OK;
 }
@@ -83,7 +84,8 @@ int gmg_cycle(mgcnn_ctx* c, void* u, bool u_f64, const int* list, int count, boo
   const double Nc = (double)mcL * mcL;
   auto coarse = [&](const float* rhs, bool scaled, void* out, int md, const int* fl, double outb) {
     Prof p(c, MGCNN_K_GMG_COARSE, L - 1, B * (Nc * Nc * 8.0 + Nc * (4.0 + outb)), B * Nc * Nc * 2.0);
-    launch_gmg_coarse_solve(G.inv, A(L - 1), c->d_b, rhs, scaled, out, md, fl, mcL, B, list, s);
+    launch_gmg_coarse_solve(G.inv, A(L - 1), c->d_b, rhs, scaled, out, md, fl, mcL, B, list,
+                            c->form(), s);
   };
   if (L == 1) {
     coarse(c->d_rt, true, u, mode, flags, ub);
@@ -94,7 +96,7 @@ int gmg_cycle(mgcnn_ctx* c, void* u, bool u_f64, const int* list, int count, boo
     Prof p(c, MGCNN_K_GMG_DOWN, l, nodes(l) * 12.0 + nodes(l + 1) * 4.0,
            nodes(l) * (12.0 * nu + 12.0 + 17.0 / 4.0));
     launch_gmg_down(nu, A(l), c->d_b, R(l), l == 0, omega, G.pre[l], G.rhs[l + 1], G.nl[l], B,
-                    list, s);
+                    list, c->form(), s);
   }
   coarse(G.rhs[L - 1], false, G.cor[L - 1], GMG_OUT_F32, nullptr, 4.0);
   for (int l = L - 2; l >= 0; --l) {
@@ -103,7 +105,7 @@ int gmg_cycle(mgcnn_ctx* c, void* u, bool u_f64, const int* list, int count, boo
            nodes(l) * (12.0 * nu + 4.0));
     launch_gmg_up(nu, A(l), c->d_b, R(l), fin, omega, G.pre[l], G.cor[l + 1],
                   fin ? u : (void*)G.cor[l], fin ? mode : GMG_OUT_F32, fin ? flags : nullptr,
-                  G.nl[l], B, list, s);
+                  G.nl[l], B, list, c->form(), s);
   }
   LAUNCH_CHECK(c);
   return MGCNN_OK;

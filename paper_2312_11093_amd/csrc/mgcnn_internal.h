@@ -33,8 +33,12 @@ typedef uint16_t bf16_t;
 // list of B problem indices (the launch covers exactly those problems; retired problems are
 // left out of the grid instead of being skipped by every workgroup).
 
+// Operator form (`form` argument of every launcher that evaluates A): the face coefficient
+// between a node and its neighbour is their harmonic mean (divergence form, Eq. (12)) or the
+// node's own value (non-divergence form of Eq. (7)); public values MGCNN_OP_DIV / MGCNN_OP_NONDIV.
+
 // Setup: stencil features F [B][n][n][4] (f32) from a [B][n][n] and b [B][2].
-void launch_features(const float* a, const float* b, float* F, int n, int B, hipStream_t st);
+void launch_features(const float* a, const float* b, float* F, int n, int B, int form, hipStream_t st);
 
 // Same-size 3x3 conv from CIN (1 or 4) channels to 16, zero padded.
 //   in  [B][n][n][CIN] f32, W [16][CIN][3][3] f32, out [B][n][n][16] (f32 or bf16).
@@ -70,7 +74,8 @@ void launch_out_update(StateType t, const void* x, const float* Wout, void* u, b
 // the stencil arithmetic is f32 (the partial sums stay f64).
 int residual_tiles(int n);
 void launch_residual(const float* a, const float* b, const float* f, const void* u, bool u_f64,
-                     float* rt, double* partial, int n, int B, const int* active, hipStream_t st);
+                     float* rt, double* partial, int n, int B, const int* active, int form,
+                     hipStream_t st);
 
 // Per-problem stop test (one workgroup per problem).  On entry iters[b] = k of the current
 // iterate.  Computes rho_k = sqrt(sum partial)/sqrt(nf2).  If nf2 is zero, rho = 0.

@@ -16,10 +16,11 @@ int krylov_blocks(int n);
 
 // y = A x ([B][n][n] in, per-problem stride ystride out), f64 stencil arithmetic
 void launch_apply_A(const float* a, const float* b, const float* x, float* y, size_t ystride, int n,
-                    int B, const int* active, hipStream_t st);
+                    int B, const int* active, int form, hipStream_t st);
 // r = f - A u (u f32 or f64, [B][n][n]); r with per-problem stride rstride
 void launch_krylov_residual(const float* a, const float* b, const float* f, const void* u, bool u_f64,
-                            float* r, size_t rstride, int n, int B, const int* active, hipStream_t st);
+                            float* r, size_t rstride, int n, int B, const int* active, int form,
+                            hipStream_t st);
 // One Gram-Schmidt pass over w and V_0..V_{cnt-1} (V_i at V + i * vstride), results in
 // out[b * KRYLOV_LD + slot]:
 //   mode 0: out[i] = <V_i, w> (i < cnt), out[cnt] = <w, w>
@@ -30,10 +31,10 @@ int launch_gs_pass(int mode, float* w, const float* V, size_t vstride, int cnt, 
                    const double* h, double* partial, double* out, const int* active, hipStream_t st);
 // rt = (v - A x) / D: v a basis vector (stride krylov_vpad(n)), x and rt [B][n][n]
 void launch_inner_residual(const float* a, const float* b, const float* v, const float* x, float* rt, int n,
-                           int B, const int* active, hipStream_t st);
+                           int B, const int* active, int form, hipStream_t st);
 // v *= s[b * KRYLOV_LD] in place (stride krylov_vpad(n)) and rt = v / D ([B][n][n])
 void launch_normalize_diag(const float* a, const float* b, float* v, float* rt, const double* s, int n,
-                           int B, const int* active, hipStream_t st);
+                           int B, const int* active, int form, hipStream_t st);
 // u_b += sum_{j<cnt} y[b * KRYLOV_LD + j] Z_j,b  (Z_j at Z + j * zstride, [B][n][n])
 void launch_combine(void* u, bool u_f64, const float* Z, size_t zstride, int cnt, int n, int B,
                     const double* y, const int* active, hipStream_t st);

@@ -79,7 +79,8 @@ int forward_record(mgcnn_ctx* c, const float* f, float* u, int K) {
   const size_t nn = (size_t)c->n * c->n * c->B;
   for (int k = 0; k < K; ++k) {
     HIP_TRY(c, hipMemcpyAsync(T.uk + (size_t)k * nn, u, nn * 4, hipMemcpyDeviceToDevice, c->stream));
-    launch_residual(c->d_a, c->d_b, f, u, false, c->d_rt, c->d_partial, c->n, c->B, nullptr, c->stream);
+    launch_residual(c->d_a, c->d_b, f, u, false, c->d_rt, c->d_partial, c->n, c->B, nullptr,
+                    c->form(), c->stream);
     if ((r = vcycle(c, u, false, nullptr, c->B))) return r;
   }
   T.K = K;
@@ -196,7 +197,7 @@ static void recompute_setup(mgcnn_ctx* c) {
   const int L = c->L, B = c->B, n = c->n;
   hipStream_t s = c->stream;
   const auto& o = c->off;
-  launch_features(c->d_a, c->d_b, T.F, n, B, s);
+  launch_features(c->d_a, c->d_b, T.F, n, B, c->form(), s);
   launch_dconv(conv_args(T.F, c->W(o.setup_in), T.c[0], n, n, 4, C, GM_SAME, EP_STORE, 0, 0), B, s);
   for (int l = 0; l < L; ++l) {
     const int m = c->nl[l];
@@ -274,7 +275,7 @@ int mgcnn_residual(mgcnn_ctx* c, const float* f, const void* u, float* r) {
   if (!c) return MGCNN_E_ARG;
   if (!c->ready) return fail(c, MGCNN_E_STATE, "residual: call mgcnn_setup first");
   if (!f || !u || !r) return fail(c, MGCNN_E_ARG, "residual: null pointer");
-  launch_residual_plain(c->d_a, c->d_b, f, u, c->u64(), r, c->n, c->B, c->stream);
+  launch_residual_plain(c->d_a, c->d_b, f, u, c->u64(), r, c->n, c->B, c->form(), c->stream);
   LAUNCH_CHECK(c);
   return MGCNN_OK;
 }
@@ -290,14 +291,15 @@ int mgcnn_loss(mgcnn_ctx* c, const float* f, const float* u, double* loss_host, 
   auto& T = c->tr;
   hipStream_t s = c->stream;
   const int B = c->B, n = c->n;
-  launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, n, B, nullptr, s);
+  launch_residual(c->d_a, c->d_b, f, nullptr, true, nullptr, c->d_partial, n, B, nullptr, c->form(), s);
   launch_sum_partials(c->d_partial, c->tiles, c->d_nf2, B, s);
-  launch_residual_plain(c->d_a, c->d_b, f, u, false, T.r, n, B, s);
+  launch_residual_plain(c->d_a, c->d_b, f, u, false, T.r, n, B, c->form(), s);
   // ||r||^2 per problem in f64 from the float32 residual
-  launch_residual(c->d_a, c->d_b, T.r, nullptr, true, nullptr, c->d_partial, n, B, nullptr, s);
+  launch_residual(c->d_a, c->d_b, T.r, nullptr, true, nullptr, c->d_partial, n, B, nullptr, c->form(), s);
   launch_sum_partials(c->d_partial, c->tiles, T.d_rr, B, s);
   launch_loss_finalize(T.d_rr, c->d_nf2, B, T.d_loss, s);
-  if (dloss_du) launch_apply_AT(c->d_a, c->d_b, T.r, nullptr, c->d_nf2, -2.0, false, dloss_du, nullptr, n, B, s);
+  if (dloss_du)
+    launch_apply_AT(c->d_a, c->d_b, T.r, nullptr, c->d_nf2, -2.0, false, dloss_du, nullptr, n, B, c->form(), s);
   if (dloss_df) launch_loss_df(T.r, f, T.d_rr, c->d_nf2, dloss_df, n, B, s);
   LAUNCH_CHECK(c);
   if (loss_host) {
@@ -325,11 +327,11 @@ int mgcnn_backward(mgcnn_ctx* c, const float* dL_du, float* dL_dweights, float* 
   float* lam_next = T.lam1;
   for (int k = T.K - 1; k >= 0; --k) {
     const float* uk = T.uk + (size_t)k * nn;
-    launch_residual(c->d_a, c->d_b, T.f, uk, false, c->d_rt, c->d_partial, n, B, nullptr, s);
+    launch_residual(c->d_a, c->d_b, T.f, uk, false, c->d_rt, c->d_partial, n, B, nullptr, c->form(), s);
     recompute_vcycle(c);
     vcycle_reverse(c, lam);
     // lam_k = lam_{k+1} - A^T (grt / D); dL/df += grt / D
-    launch_apply_AT(c->d_a, c->d_b, T.grt, lam, nullptr, -1.0, true, lam_next, dL_df, n, B, s);
+    launch_apply_AT(c->d_a, c->d_b, T.grt, lam, nullptr, -1.0, true, lam_next, dL_df, n, B, c->form(), s);
     std::swap(lam, lam_next);
   }
   recompute_setup(c);

@@ -32,7 +32,7 @@ class mgcnn_opts(ctypes.Structure):
                 ("method", ctypes.c_int), ("restart", ctypes.c_int), ("f32_split", ctypes.c_int),
                 ("s_bf16", ctypes.c_int), ("inner_steps", ctypes.c_int), ("gs_passes", ctypes.c_int),
                 ("precond", ctypes.c_int), ("gmg_levels", ctypes.c_int), ("gmg_sweeps", ctypes.c_int),
-                ("gmg_omega", ctypes.c_float)]
+                ("gmg_omega", ctypes.c_float), ("op_form", ctypes.c_int)]
 
 
 class mgcnn_kernel_stat(ctypes.Structure):
@@ -47,6 +47,7 @@ KERNEL_KINDS = {0: "residual", 1: "finalize", 2: "conv_in", 3: "smooth_down", 4:
                 14: "krylov_combine", 15: "krylov_residual", 16: "scale_by_diag", 17: "zero",
                 18: "gmg_down", 19: "gmg_up", 20: "gmg_coarse"}
 PRECONDS = {"network": 0, "gmg": 1}
+FORMS = {"div": 0, "nondiv": 1}
 
 EXPORTS = {
     # name: (restype, argtypes)
@@ -154,9 +155,10 @@ class Solver:
                  check_every: int = 4, stream=None, method: str = "stationary", restart: int = 30,
                  f32_split: bool = True, s_bf16: bool = False, inner_steps: int = 1,
                  gs_passes: int = 2, precond: str = "network", gmg_levels: int = 0,
-                 gmg_sweeps: int = 3, gmg_omega: float = 0.67):
+                 gmg_sweeps: int = 3, gmg_omega: float = 0.67, form: str = "div"):
         """weights: the flat network weights, or None with precond="gmg" (the geometric
-        multigrid baseline has none)."""
+        multigrid baseline has none).  form: "div" (divergence form, harmonic face
+        coefficients) or "nondiv" (the non-divergence form -a Lap(u) + b . grad u)."""
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -173,6 +175,7 @@ class Solver:
         o.inner_steps = int(inner_steps)
         o.gs_passes = int(gs_passes)
         _set_gmg(o, precond, gmg_levels, gmg_sweeps, gmg_omega)
+        o.op_form = FORMS[form]
         self.opts = o
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         wp = _weights_ptr(self, weights, self._L.mgcnn_num_weights(16))
@@ -327,7 +330,8 @@ class GroupSolver:
     def __init__(self, weights, state: str = "f32", u: str = "f64", method: str = "stationary",
                  restart: int = 30, check_every: int = 4, f32_split: bool = True, s_bf16: bool = False,
                  inner_steps: int = 1, gs_passes: int = 2, stream=None, precond: str = "network",
-                 gmg_levels: int = 0, gmg_sweeps: int = 3, gmg_omega: float = 0.67):
+                 gmg_levels: int = 0, gmg_sweeps: int = 3, gmg_omega: float = 0.67,
+                 form: str = "div"):
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -342,6 +346,7 @@ class GroupSolver:
         o.inner_steps = int(inner_steps)
         o.gs_passes = int(gs_passes)
         _set_gmg(o, precond, gmg_levels, gmg_sweeps, gmg_omega)
+        o.op_form = FORMS[form]
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         wp = _weights_ptr(self, weights, self._L.mgcnn_num_weights(16))
         self._stream = stream if stream is not None else torch.cuda.current_stream()

@@ -1,0 +1,177 @@
+"""GPU: the non-divergence operator of Eq. (7) (opts.op_form = MGCNN_OP_NONDIV) through the
+C-ABI against the FP64 oracle with form="nondiv", on the paper's own test problems
+(white-noise coefficients, v = (sin 0.5, cos 0.5), rhs = 1):
+
+* residual vector and norms, one network application, one GMG cycle, the stationary solves
+  (network with weighted-Jacobi weights and GMG: iteration counts and solutions), FGMRES with
+  the hand-set network, and the training gradient -- the same checks and tolerances as the
+  divergence-form tests;
+* GMG iteration counts on the paper's problems against the counts the paper prints for its
+  GMG (golden fixture, within 15 % at 127^2 and 255^2).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import adjoint as oadj
+from oracle import gmg as ogmg
+from oracle import network as onet
+from oracle import operator as oop
+from oracle import solve as osv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_11093_amd import Solver  # noqa: E402
+from paper_2312_11093_amd import mgcnn as M  # noqa: E402
+from paper_2312_11093_amd.handbuilt import vcycle_weights  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_gmg_iterations.json")
+WL = "paper_re1e3"
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype)
+
+
+def test_residual_and_norms():
+    n, B = 127, 2
+    say("nondiv residual", n, B)
+    a, b, f = datagen.make_batch(WL, n, B, seed=1)
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal((B, n, n))
+    S = Solver(None, precond="gmg", u="f64", form="nondiv")
+    S.setup(dev(a), b)
+    r = S.residual(dev(f), dev(u, torch.float64)).cpu().numpy()
+    rr = S.residual_norms(dev(f), dev(u, torch.float64))
+    for p in range(B):
+        exp = f[p] - oop.apply_A(a[p], b[p], u[p], "nondiv")
+        assert np.max(np.abs(r[p] - exp)) <= 2e-7 * np.max(np.abs(exp))
+        assert abs(rr[p] - osv.relres(a[p], b[p], f[p], u[p], "nondiv")) <= 1e-12 * rr[p]
+    S.close()
+
+
+@pytest.mark.parametrize("n", [31, 63])
+def test_network_application(n):
+    """z = B(r / D) with Xavier weights against the oracle network (f32 tolerance 1e-5)."""
+    B = 2
+    say("nondiv network apply", n)
+    a, b, _ = datagen.make_batch(WL, n, B, seed=3)
+    r = np.random.default_rng(4).standard_normal((B, n, n)).astype(np.float32)
+    w = datagen.xavier_weights(16, 0)
+    S = Solver(w, state="f32", u="f64", form="nondiv")
+    S.setup(dev(a), b)
+    z = S.apply(dev(r)).cpu().numpy()
+    for p in range(B):
+        ref = osv.Solver(w, a[p], b[p], form="nondiv").correction(r[p].astype(np.float64))
+        err = np.max(np.abs(z[p] - ref)) / np.max(np.abs(ref))
+        say("  problem", p, "rel err", err)
+        assert err <= 1e-5
+    S.close()
+
+
+def test_gmg_cycle_and_stationary_solve():
+    n, B = 127, 2
+    say("nondiv gmg", n, B)
+    a, b, f = datagen.make_batch(WL, n, B, seed=5)
+    r = np.random.default_rng(6).standard_normal((B, n, n)).astype(np.float32)
+    S = Solver(None, precond="gmg", u="f64", form="nondiv", check_every=1)
+    S.setup(dev(a), b)
+    z = S.apply(dev(r)).cpu().numpy()
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(f), u, 1e-8, 200)
+    say("  iters", list(it))
+    assert st == M.OK
+    for p in range(B):
+        G = ogmg.GMG(a[p], b[p], omega=np.float32(0.67), form="nondiv")
+        ref = G.cycle(r[p])
+        assert np.max(np.abs(z[p] - ref)) <= 2e-6 * np.max(np.abs(ref))
+        ou, ost, oit, _, _ = G.solve(f[p], 1e-8, 200)
+        assert abs(int(it[p]) - oit) <= 1, (p, it[p], oit)
+        up = u[p].cpu().numpy()
+        assert osv.relres(a[p], b[p], f[p], up, "nondiv") <= 1e-8 * (1 + 1e-6)
+        assert np.linalg.norm(up - ou) <= 1e-6 * np.linalg.norm(ou)
+    S.close()
+
+
+@pytest.mark.parametrize("n", [127, 255, 1023])
+def test_gmg_iterations_against_the_paper(n):
+    """The paper's GMG settings on the paper's problems (3 problems): mean iteration count
+    within 15 % of the printed one at 127^2 and 255^2; at 1023^2 reported only (printed: 45)."""
+    B = 3
+    want = json.load(open(GOLDEN))["gmg_iterations"][str(n)]
+    a, b, f = datagen.make_batch(WL, n, B, seed=7)
+    S = Solver(None, precond="gmg", u="f64", form="nondiv")
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(f), u, 1e-8, 500)
+    say("gmg on the paper's problems", n, "iters", list(it), "paper", want)
+    assert st == M.OK
+    for p in range(B):
+        assert osv.relres(a[p], b[p], f[p], u[p].cpu().numpy(), "nondiv") <= 1e-8 * (1 + 1e-6)
+    if n <= 255:
+        assert abs(float(np.mean(it)) - want) <= 0.15 * want
+    S.close()
+
+
+def test_network_fgmres_and_stationary_jacobi():
+    n, B = 255, 2
+    say("nondiv network solves", n)
+    a, b, f = datagen.make_batch(WL, n, B, seed=8)
+    S = Solver(vcycle_weights(), state="f32", u="f64", method="fgmres", restart=30, form="nondiv")
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(f), u, 1e-8, 3000)
+    say("  fgmres iters", list(it))
+    assert st == M.OK
+    for p in range(B):
+        assert osv.relres(a[p], b[p], f[p], u[p].cpu().numpy(), "nondiv") <= 1e-8 * (1 + 1e-6)
+    S.close()
+    # weighted Jacobi as network weights: the stationary iteration against the oracle's
+    n = 15
+    a, b, f = datagen.make_batch(WL, n, 1, seed=9)
+    C = 16
+    P = {k: np.zeros_like(v) for k, v in onet.unpack_weights(np.zeros(81 * C * C + 58 * C), C).items()}
+    P["W_in"][0, 0, 1, 1] = 1.0
+    P["W_out"][0, 0, 1, 1] = 0.8
+    w = onet.pack_weights(P, C).astype(np.float32)
+    S = Solver(w, state="f32", u="f64", check_every=1, form="nondiv")
+    S.setup(dev(a), b)
+    u = torch.zeros((1, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(f), u, 1e-6, 20000)
+    ou, ost, oit, _, _ = osv.Solver(w, a[0], b[0], form="nondiv").solve(f[0], 1e-6, 20000)
+    say("  jacobi iters", int(it[0]), oit)
+    assert st == M.OK and ost == osv.OK and abs(int(it[0]) - oit) <= 1
+    S.close()
+
+
+def test_training_gradient():
+    n, B, K = 15, 2, 2
+    say("nondiv gradient")
+    a, b, f = datagen.make_batch(WL, n, B, seed=10)
+    w = (datagen.xavier_weights(16, 1) * 0.5).astype(np.float32)
+    S = Solver(w, state="f32", u="f32", form="nondiv")
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
+    df = dev(f)                     # the recorded forward keeps this pointer until backward
+    S.forward(df, u, K, record=True)
+    du = torch.empty_like(u)
+    L = S.loss(df, u, du)
+    g = S.backward(du).cpu().numpy()
+    S.close()
+    L_ref, g_ref = oadj.loss_and_grad(w, list(a), list(b), list(f), K, form="nondiv")
+    say("  loss", L, L_ref)
+    assert abs(L - L_ref) <= 1e-5 * abs(L_ref)
+    assert np.linalg.norm(g - g_ref) <= 1e-4 * np.linalg.norm(g_ref)
