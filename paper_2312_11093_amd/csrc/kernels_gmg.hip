@@ -317,21 +317,28 @@ __global__ __launch_bounds__(256) void gmg_up_kernel(const float* __restrict__ a
 // ------------------------------------------------------------------------------------------
 // coarsest grid: exact solve with the inverse formed at setup (f64).
 // ------------------------------------------------------------------------------------------
-// Matrix of the rediscretised operator on an mc x mc grid (row index i*mc + j), assembled
-// transposed (column-major A, i.e. M[q][p] = A[p][q]) and inverted in place by Gauss-Jordan
-// elimination without pivoting (A is diagonally dominant: weakly in the interior, strictly next
-// to the boundary), one workgroup per problem.  The result M = (A^T)^-1 = (A^-1)^T is what the
-// apply kernel wants: for each column k, the threads read consecutive entries.
+// Inverse of the rediscretised operator on an mc x mc grid (row index i*mc + j), one
+// workgroup per problem.  A is an M-matrix with bandwidth mc (couplings at +-1 and +-mc), so an
+// LU factorisation without pivoting is stable and stays inside the band: the band (at most
+// 225 rows x 31 diagonals, f64) is assembled and factorised in LDS, then thread t solves
+// A x = e_t (forward then backward substitution, the last 16 values in a register window) and
+// writes x, column t of A^-1, as row t of inv.  So inv = (A^-1)^T, what the apply kernel wants:
+// for each k, the threads read consecutive entries.
+constexpr int GMG_BAND = GMG_MAX_COARSE_SIDE;            // largest bandwidth
+constexpr int GMG_BW = 2 * GMG_BAND + 1;                 // stored diagonals per row
+constexpr int GMG_WIN = 16;                              // register window >= GMG_BAND
+
 __global__ __launch_bounds__(256) void gmg_coarse_inverse_kernel(const float* __restrict__ a,
                                                                  const float* __restrict__ bvec,
                                                                  double* __restrict__ inv, int mc,
                                                                  int form) {
   const int b = blockIdx.x;
   const int N = mc * mc;
-  double* M = inv + (size_t)b * N * N;
-  const float* A = a + (size_t)b * N;
   const int tid = threadIdx.x;
-  for (size_t idx = tid; idx < (size_t)N * N; idx += 256) M[idx] = 0.0;
+  const float* A = a + (size_t)b * N;
+  __shared__ double band[GMG_MAX_COARSE * GMG_BW];       // band[p][q - p + GMG_BAND] = A[p][q]
+  auto at = [&](int p, int q) -> double& { return band[p * GMG_BW + (q - p + GMG_BAND)]; };
+  for (int idx = tid; idx < GMG_MAX_COARSE * GMG_BW; idx += 256) band[idx] = 0.0;
   __syncthreads();
   const double ih = (double)(mc + 1), ih2 = ih * ih;
   const double bx = bvec[2 * b], by = bvec[2 * b + 1];
@@ -345,39 +352,54 @@ __global__ __launch_bounds__(256) void gmg_coarse_inverse_kernel(const float* __
     const double aW = (j > 0 && !form) ? hm(ac, A[p - 1]) : ac;
     const double aN = (i + 1 < mc && !form) ? hm(ac, A[p + mc]) : ac;
     const double aS = (i > 0 && !form) ? hm(ac, A[p - mc]) : ac;
-    // row p of A stored as column p of M
-    M[(size_t)p * N + p] = (aE + aW + aN + aS) * ih2 + (bxp - bxm + byp - bym) * ih;
-    if (j + 1 < mc) M[(size_t)(p + 1) * N + p] = -aE * ih2 + bxm * ih;
-    if (j > 0) M[(size_t)(p - 1) * N + p] = -aW * ih2 - bxp * ih;
-    if (i + 1 < mc) M[(size_t)(p + mc) * N + p] = -aN * ih2 + bym * ih;
-    if (i > 0) M[(size_t)(p - mc) * N + p] = -aS * ih2 - byp * ih;
+    at(p, p) = (aE + aW + aN + aS) * ih2 + (bxp - bxm + byp - bym) * ih;
+    if (j + 1 < mc) at(p, p + 1) = -aE * ih2 + bxm * ih;
+    if (j > 0) at(p, p - 1) = -aW * ih2 - bxp * ih;
+    if (i + 1 < mc) at(p, p + mc) = -aN * ih2 + bym * ih;
+    if (i > 0) at(p, p - mc) = -aS * ih2 - byp * ih;
   }
   __syncthreads();
-  __shared__ double fcol[GMG_MAX_COARSE];
-  __shared__ double piv;
+  // Doolittle LU in the band: step k updates rows and columns k+1 .. k+mc (one entry per thread),
+  // then stores the multipliers of column k
+  const int W = mc;
   for (int k = 0; k < N; ++k) {
-    if (tid == 0) piv = 1.0 / M[(size_t)k * N + k];
-    for (int i = tid; i < N; i += 256) fcol[i] = M[(size_t)i * N + k];
-    __syncthreads();
-    const double pk = piv;
-    // pivot row: M[k][:] *= p with M[k][k] = p
-    for (int j = tid; j < N; j += 256) {
-      const double v = (j == k) ? 1.0 : M[(size_t)k * N + j];
-      M[(size_t)k * N + j] = v * pk;
+    if (tid < W * W) {
+      const int i = k + 1 + tid / W, j = k + 1 + tid % W;
+      if (i < N && j < N) at(i, j) -= at(i, k) / at(k, k) * at(k, j);
     }
     __syncthreads();
-    // other rows: M[i][:] -= f_i M[k][:], with M[i][k] starting from 0 (thread j owns column j)
-    if (tid < N) {
-      const int j = tid;
-      const double mkj = M[(size_t)k * N + j];
-      for (int i = 0; i < N; ++i) {
-        if (i == k) continue;
-        double* mij = M + (size_t)i * N + j;
-        const double base = (j == k) ? 0.0 : *mij;
-        *mij = base - fcol[i] * mkj;
-      }
-    }
+    if (tid < W && k + 1 + tid < N) at(k + 1 + tid, k) /= at(k, k);
     __syncthreads();
+  }
+  if (tid >= N) return;
+  double* X = inv + (size_t)b * N * N + (size_t)tid * N;
+  // forward: y = L^-1 e_t (unit lower); win[GMG_WIN - d] = y_{i-d}
+  double win[GMG_WIN];
+#pragma unroll
+  for (int d = 0; d < GMG_WIN; ++d) win[d] = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double y = (i == tid) ? 1.0 : 0.0;
+#pragma unroll
+    for (int d = 1; d <= GMG_BAND; ++d)
+      if (i - d >= 0) y -= band[i * GMG_BW + (GMG_BAND - d)] * win[GMG_WIN - d];
+#pragma unroll
+    for (int d = 0; d < GMG_WIN - 1; ++d) win[d] = win[d + 1];
+    win[GMG_WIN - 1] = y;
+    X[i] = y;
+  }
+  // backward: x = U^-1 y; win[GMG_WIN - d] = x_{i+d}
+#pragma unroll
+  for (int d = 0; d < GMG_WIN; ++d) win[d] = 0.0;
+  for (int i = N - 1; i >= 0; --i) {
+    double x = X[i];
+#pragma unroll
+    for (int d = 1; d <= GMG_BAND; ++d)
+      if (i + d < N) x -= band[i * GMG_BW + (GMG_BAND + d)] * win[GMG_WIN - d];
+    x /= band[i * GMG_BW + GMG_BAND];
+#pragma unroll
+    for (int d = 0; d < GMG_WIN - 1; ++d) win[d] = win[d + 1];
+    win[GMG_WIN - 1] = x;
+    X[i] = x;
   }
 }
 
