@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--deflate", type=int, default=8,
+                    help="FGMRES deflated restarts: directions kept across a restart (0 = plain)")
     ap.add_argument("--no-gmg", action="store_true",
                     help="skip the geometric multigrid baseline (same outer method, same batch)")
     args = ap.parse_args()
@@ -179,8 +181,9 @@ def main():
     def make(state, use_graph):
         return Solver(weights, state=state, u="f64", check_every=args.check_every,
                       use_graph=use_graph and args.method == "stationary", method=args.method,
-                      restart=args.restart, gs_passes=args.gs_passes)
+                      restart=args.restart, gs_passes=args.gs_passes, deflate=dfl)
 
+    dfl = args.deflate if args.method == "fgmres" else 0
     S = make(args.state, not args.no_graph)
 
     def step():
@@ -241,7 +244,7 @@ def main():
         P = min(args.plain_sample, B)
         # plain FP32: float32 matrix instructions, one problem per call, no graphs
         Sp = Solver(weights, state="f32", u="f64", check_every=1, method=args.method, restart=args.restart,
-                    gs_passes=args.gs_passes, f32_split=False)
+                    gs_passes=args.gs_passes, f32_split=False, deflate=dfl)
         up = torch.zeros((1, n, n), dtype=torch.float64, device="cuda")
         Sp.setup(da[0:1].contiguous(), b[0:1])
         Sp.solve(df[0:1].contiguous(), up, args.tol, min(args.maxit, 2 * args.restart))   # warm-up
@@ -282,7 +285,7 @@ def main():
     gmg = None
     if not args.no_gmg:
         Sg = Solver(None, precond="gmg", u="f64", check_every=args.check_every, method=args.method,
-                    restart=args.restart, gs_passes=args.gs_passes)
+                    restart=args.restart, gs_passes=args.gs_passes, deflate=dfl)
 
         def gstep():
             u.zero_()
@@ -331,6 +334,7 @@ def main():
                    "global_batch": B, "n": n, "method": args.method,
                    "restart": args.restart if args.method == "fgmres" else None,
                    "gs_passes": args.gs_passes if args.method == "fgmres" else None,
+                   "deflate": dfl if args.method == "fgmres" else None,
                    "state": args.state, "u": "f64", "weights": wsrc, "parallelism": "single GPU"},
         "converged": converged, "mean_iters": mean_iters, "max_iters": int(np.max(its[-1])),
         "ms_per_stationary_iteration": round(iter_ms, 3),

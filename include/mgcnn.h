@@ -113,6 +113,10 @@ typedef struct {
   int gmg_sweeps;   /* GMG only: sweeps before and after the coarse correction, 1..4 (default 3) */
   float gmg_omega;  /* GMG only: weighted-Jacobi weight, in (0, 2) (default 0.67) */
   int op_form;      /* MGCNN_OP_DIV (default) or MGCNN_OP_NONDIV: the operator of every call */
+  int deflate;      /* FGMRES only: 0 = plain restarts; k in 1..32 (and < restart) = deflated restarts:
+                       each restart keeps the k directions in which the preconditioned operator
+                       of the finished cycle is smallest (right singular vectors of its
+                       Hessenberg matrix) as the first k basis vectors of the next cycle */
 } mgcnn_opts;
 
 /* Default options: 16 channels, f32 state (split-bf16 matrix arithmetic), f64 u, graphs off,

@@ -349,6 +349,44 @@ int launch_gs_pass(int mode, float* w, const float* V, size_t vstride, int cnt, 
   return 0;
 }
 
+// In-place change of basis: each thread reads element e of all the problem's input vectors and
+// writes element e of the k outputs (so overwriting inputs 0..k-1 is safe).  Coefficients are
+// wave-uniform (scalar loads).
+constexpr int KB_MAX = KRYLOV_MAX_DEFLATE;
+__global__ __launch_bounds__(256) void basis_combine_kernel(float* __restrict__ X, size_t stride,
+                                                            size_t plen, int k,
+                                                            const double* __restrict__ C,
+                                                            size_t cstride, int blocks_per_prob,
+                                                            const int* __restrict__ active) {
+  const int slot = blockIdx.x / blocks_per_prob, blk = blockIdx.x % blocks_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;
+  const size_t e = (size_t)blk * 256 + threadIdx.x;
+  if (e >= plen) return;
+  const double* Cb = C + (size_t)b * cstride;
+  const int count = (int)Cb[cstride - 1];
+  float acc[KB_MAX];
+#pragma unroll
+  for (int i = 0; i < KB_MAX; ++i) acc[i] = 0.f;
+  float* Xb = X + (size_t)b * plen + e;
+  for (int j = 0; j < count; ++j) {
+    const float x = Xb[(size_t)j * stride];
+#pragma unroll
+    for (int i = 0; i < KB_MAX; ++i)
+      if (i < k) acc[i] = fmaf((float)Cb[(size_t)j * k + i], x, acc[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < KB_MAX; ++i)
+    if (i < k) Xb[(size_t)i * stride] = acc[i];
+}
+
+void launch_basis_combine(float* X, size_t stride, size_t plen, int cnt, int k, const double* C,
+                          size_t cstride, int B, const int* active, hipStream_t st) {
+  (void)cnt;
+  const int bpp = (int)((plen + 255) / 256);
+  hipLaunchKernelGGL(basis_combine_kernel, dim3(bpp * B), dim3(256), 0, st, X, stride, plen, k, C,
+                     cstride, bpp, active);
+}
+
 // u[b] += sum_{j<cnt} y[b][j] Z_j[b] for the listed problems (terms with y = 0 are skipped:
 // their Z_j may be stale)
 template <typename UT>

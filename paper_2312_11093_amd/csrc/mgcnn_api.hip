@@ -306,6 +306,7 @@ void mgcnn_default_opts(mgcnn_opts* o) {
   o->gmg_sweeps = 3;
   o->gmg_omega = 0.67f;
   o->op_form = MGCNN_OP_DIV;
+  o->deflate = 0;
 }
 
 size_t mgcnn_num_weights(int channels) {
@@ -333,6 +334,8 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.gmg_levels < 0 || o.gmg_sweeps < 1 || o.gmg_sweeps > GMG_MAX_SWEEPS) return MGCNN_E_ARG;
   if (!(o.gmg_omega > 0.f && o.gmg_omega < 2.f)) return MGCNN_E_ARG;
   if (o.op_form != MGCNN_OP_DIV && o.op_form != MGCNN_OP_NONDIV) return MGCNN_E_ARG;
+  if (o.deflate < 0 || o.deflate > 32) return MGCNN_E_ARG;
+  if (o.method == MGCNN_METHOD_FGMRES && o.deflate > 0 && o.deflate >= o.restart) return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
   if (!c) return MGCNN_E_NOMEM;
   c->opts = o;

@@ -66,6 +66,8 @@ struct mgcnn_ctx {
     double* s = nullptr;      // per-problem scale factors / combination coefficients
     int* act = nullptr;       // problems extending their basis
     int* cyc = nullptr;       // problems live in the current restart cycle
+    int* grp = nullptr;       // problems restarting with deflation vectors
+    double* coef = nullptr;   // deflation: basis combination coefficients (V, then Z)
   } kr;
 
   // geometric multigrid preconditioner (opts.precond == MGCNN_PRECOND_GMG), per level l

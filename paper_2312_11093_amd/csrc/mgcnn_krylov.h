@@ -8,6 +8,7 @@ namespace mg {
 
 constexpr int KRYLOV_MAX_BASIS = 64;   // maximum restart length + 1
 constexpr int KRYLOV_LD = 72;          // per-problem stride of the scalar arrays (basis + norm + pad)
+constexpr int KRYLOV_MAX_DEFLATE = 32; // deflation vectors kept across a restart
 
 // Arnoldi vectors are [B][krylov_vpad(n)] float32, zero padded; Gram-Schmidt passes run over
 // krylov_blocks(n) groups of elements per problem.
@@ -35,6 +36,11 @@ void launch_inner_residual(const float* a, const float* b, const float* v, const
 // v *= s[b * KRYLOV_LD] in place (stride krylov_vpad(n)) and rt = v / D ([B][n][n])
 void launch_normalize_diag(const float* a, const float* b, float* v, float* rt, const double* s, int n,
                            int B, const int* active, int form, hipStream_t st);
+// In place X_i,b = sum_{j < count_b} X_j,b C_b[j][i] for i < k (X_j at X + j * stride, problem b
+// at b * plen); C_b at C + b * cstride, row-major with row length k, count_b = C_b[cstride - 1];
+// count_b <= cnt.  Only the listed problems.
+void launch_basis_combine(float* X, size_t stride, size_t plen, int cnt, int k, const double* C,
+                          size_t cstride, int B, const int* active, hipStream_t st);
 // u_b += sum_{j<cnt} y[b * KRYLOV_LD + j] Z_j,b  (Z_j at Z + j * zstride, [B][n][n])
 void launch_combine(void* u, bool u_f64, const float* Z, size_t zstride, int cnt, int n, int B,
                     const double* y, const int* active, hipStream_t st);

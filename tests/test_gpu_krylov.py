@@ -141,3 +141,37 @@ def test_bf16_setup_tensors_option():
         assert osv.relres(a[p], b[p], f[p], u[p].cpu().numpy()) <= 1e-8 * (1 + 1e-6)
     S32.close()
     S16.close()
+
+
+@pytest.mark.parametrize("precond,n,B,restart,kd", [
+    ("network", 255, 3, 63, 16),
+    ("network", 127, 4, 30, 8),
+    ("gmg", 255, 3, 30, 8),
+])
+def test_fgmres_deflated_restarts(precond, n, B, restart, kd):
+    """opts.deflate: restarts keep the kd smallest singular directions of the cycle.  Every
+    problem still reaches the tolerance (the oracle re-checks; a zero right-hand side stays
+    zero), in fewer Arnoldi steps in total than plain restarts."""
+    say("fgmres deflated restarts", precond, n, B, restart, kd)
+    a, b, f = datagen.make_batch("blocks1023", n, B, seed=16)
+    f[B - 1] = 0.0
+    w = vcycle_weights() if precond == "network" else None
+    its = {}
+    for k in (0, kd):
+        S = Solver(w, precond=precond, state="f32", u="f64", method="fgmres", restart=restart,
+                   gs_passes=1, deflate=k)
+        S.setup(dev(a), b)
+        u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+        st, it, rr, ps = S.solve(dev(f), u, 1e-8, 4000)
+        say("  deflate", k, "iters", list(it))
+        assert st == M.OK and (ps == 0).all()
+        assert int(it[B - 1]) == 0 and (u[B - 1] == 0).all()
+        for p in range(B - 1):
+            rho = osv.relres(a[p], b[p], f[p], u[p].cpu().numpy())
+            assert rho <= 1e-8 * (1 + 1e-6), (k, p, rho)
+            assert abs(rho - rr[p]) <= 1e-3 * 1e-8 + 1e-6 * rho
+        its[k] = int(it.sum())
+        S.close()
+    assert its[kd] < its[0], its
+    with pytest.raises(M.MGCNNError):
+        Solver(w, precond=precond, method="fgmres", restart=8, deflate=8)
