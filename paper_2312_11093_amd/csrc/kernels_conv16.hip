@@ -378,22 +378,28 @@ __global__ __launch_bounds__(256) void conv16_restrict_kernel(
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int px = lane & 15, g = lane >> 4;
+  // tap-major over the wave's segments: independent accumulation chains (the staged tile is
+  // zero outside the grid, so every segment may be computed; only the stores are guarded)
+  f4v accs[K::TPW];
+#pragma unroll
+  for (int tt = 0; tt < K::TPW; ++tt) accs[tt] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int tt = 0; tt < K::TPW; ++tt) {
+        const int task = wave * K::TPW + tt;
+        const int orow = task / K::NSEG, jj = (task % K::NSEG) * 16 + px;
+        accs[tt] = fr.mma(p * 3 + q, &lds[((2 * orow + p) * K::ROW + rs_slot<K::HALF>(2 * jj + q)) * PS],
+                          accs[tt], PSTR);
+      }
 #pragma unroll
   for (int tt = 0; tt < K::TPW; ++tt) {
     const int task = wave * K::TPW + tt;
-    const int orow = task / K::NSEG, seg = task % K::NSEG;
-    const int gi = orow0 + orow;
-    if (gi >= mo || ocol0 + seg * 16 >= mo) continue;
-    f4v acc = {0.f, 0.f, 0.f, 0.f};
-    const int jj = seg * 16 + px;
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-        acc = fr.mma(p * 3 + q, &lds[((2 * orow + p) * K::ROW + rs_slot<K::HALF>(2 * jj + q)) * PS], acc,
-                     PSTR);
-    const int gj = ocol0 + jj;
-    if (gj < mo) st4(Yb, gi * mo + gj, g, make_float4(acc[0], acc[1], acc[2], acc[3]));
+    const int gi = orow0 + task / K::NSEG, gj = ocol0 + (task % K::NSEG) * 16 + px;
+    const f4v acc = accs[tt];
+    if (gi < mo && gj < mo) st4(Yb, gi * mo + gj, g, make_float4(acc[0], acc[1], acc[2], acc[3]));
   }
 }
 
@@ -489,8 +495,10 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
 // Finest level, down smoother with the reChannel-in conv folded in:
 //   x1 = W_in * rt  (1 -> 16, zero padding),  y = x1 + W_dn * (s . x1).
 // x1 is computed on the staged tile (one-pixel halo, zero outside the grid) from an LDS copy of
-// rt with a two-pixel halo, so x1 never travels through HBM; x1 at the output pixels is kept in
-// LDS for the skip term.
+// rt with a two-pixel halo, so x1 never travels through HBM.  The skip term x1 at the output
+// pixels is, with f32 state, three more 16x16x4 MFMAs per segment into the same accumulator
+// (W_in as a 16 x 12 matrix, taps 9..11 zero, against the nine rt values around each pixel);
+// with bf16 state it is the rounded stored x1, kept in LDS.
 // ------------------------------------------------------------------------------------------
 template <int ST, bool SBF = false>
 __global__ __launch_bounds__(256) void smooth_in_kernel(
@@ -505,7 +513,8 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
   constexpr int RPT = (RR * RC + 255) / 256;             // rt values per thread
   constexpr int PSTR = K::NPIX * PS;                     // LDS plane stride
   __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];  // z = s . x1
-  __shared__ __attribute__((aligned(16))) E lx[K::TH * K::TW * PS];  // x1 at the output pixels
+  constexpr bool SKIP_MMA = ST == ST_F32;                // skip term on the matrix cores
+  __shared__ __attribute__((aligned(16))) E lx[SKIP_MMA ? 4 : K::TH * K::TW * PS];  // x1 at the outputs
   __shared__ float lrt[RR * RC];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
@@ -581,7 +590,15 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
     } else {
       store16(&lds[pix * PS], z);
     }
-    if (lr >= 1 && lr <= K::TH && lc >= 1 && lc <= K::TW) store16(&lx[((lr - 1) * K::TW + lc - 1) * PS], x1);
+    if constexpr (!SKIP_MMA)
+      if (lr >= 1 && lr <= K::TH && lc >= 1 && lc <= K::TW) store16(&lx[((lr - 1) * K::TW + lc - 1) * PS], x1);
+  }
+  // A operand of the skip MFMAs: lane (px, g) holds W_in[channel px][tap 4 s + g] for instruction s
+  float wsk[3];
+#pragma unroll
+  for (int s3 = 0; s3 < 3; ++s3) {
+    const int tap = 4 * s3 + g;
+    wsk[s3] = (SKIP_MMA && tap < 9) ? Win[px * 9 + tap] : 0.f;
   }
   __syncthreads();
   // 3. implicit GEMM per 16-pixel segment, y = x1 + acc
@@ -592,6 +609,16 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
     const int gi = row0 + orow;
     if (gi >= m || col0 + seg * 16 >= m) continue;
     f4v acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (SKIP_MMA) {
+      // x1 at the output pixel: B[k = g][px] = rt at tap 4 s + g (zero for taps 9..11)
+#pragma unroll
+      for (int s3 = 0; s3 < 3; ++s3) {
+        const int tap = 4 * s3 + g;
+        const int tp = tap < 9 ? tap : 0;
+        const float rb = lrt[(orow + 1 + tp / 3) * RC + seg * 16 + px + 1 + tp % 3];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wsk[s3], tap < 9 ? rb : 0.f, acc, 0, 0, 0);
+      }
+    }
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
@@ -599,11 +626,13 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
         acc = fr.mma(p * 3 + q, &lds[((orow + p) * K::IC + seg * 16 + px + q) * PS], acc, PSTR);
     const int gj = col0 + seg * 16 + px;
     if (gj < m) {
-      const E* xp = &lx[(orow * K::TW + seg * 16 + px) * PS + 4 * g];
       float4 xo;
-      if constexpr (ST != ST_BF16) {
-        xo = *reinterpret_cast<const float4*>(xp);
+      if constexpr (SKIP_MMA) {
+        xo = make_float4(0.f, 0.f, 0.f, 0.f);
+      } else if constexpr (ST != ST_BF16) {
+        xo = *reinterpret_cast<const float4*>(&lx[(orow * K::TW + seg * 16 + px) * PS + 4 * g]);
       } else {
+        const E* xp = &lx[(orow * K::TW + seg * 16 + px) * PS + 4 * g];
         const uint2 zz = *reinterpret_cast<const uint2*>(xp);
         xo = make_float4(__uint_as_float(zz.x << 16), __uint_as_float(zz.x & 0xffff0000u),
                          __uint_as_float(zz.y << 16), __uint_as_float(zz.y & 0xffff0000u));
