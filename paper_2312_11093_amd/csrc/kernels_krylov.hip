@@ -28,7 +28,9 @@ int krylov_blocks(int n) { return (int)(krylov_vpad(n) / ((size_t)KG_ELEMS * KG_
 // Divergence-form 5-point diffusion with harmonic face means plus first-order upwind convection,
 // f64 arithmetic.  Tiles of 256 columns x KW_ROWS rows; each thread walks one column, keeping the
 // rows above, at and below in registers, so every vertical face coefficient is formed once and
-// every value comes from HBM once.  Reciprocals: hardware estimate refined by two Newton steps.
+// every value comes from HBM once.  In full tiles all loads of the walk are issued before the
+// arithmetic (a loop with an exit test per row keeps only one row in flight per thread).
+// Reciprocals: hardware estimate refined by two Newton steps.
 //   KW_APPLY:     y[b][ystride] = A x                      (x f32 [B][n][n])
 //   KW_RESIDUAL:  y[b][ystride] = f - A u                  (u f32 or f64 [B][n][n])
 //   KW_NORMALIZE: v[b][ystride] *= s[b];  rt = v / D       (rt [B][n][n])
@@ -79,6 +81,53 @@ __global__ __launch_bounds__(256) void kwalk_kernel(const float* __restrict__ a,
     xs = (i0 > 0) ? (double)X[(i0 - 1) * n + j] : 0.0;
   }
   const double sb = (MODE == KW_NORMALIZE) ? sc[(size_t)b * KR_LD] : 0.0;
+  if (i0 + KW_ROWS < n) {
+    // full tile, every row has a north neighbour: issue all loads of the walk first, so that
+    // the rows' loads are in flight together, then run the recurrence over the registers
+    float an_[KW_ROWS], ae_[KW_ROWS], aw_[KW_ROWS], v_[KW_ROWS];
+    XT xn_[KW_ROWS], xe_[KW_ROWS], xw_[KW_ROWS];
+#pragma unroll
+    for (int r = 0; r < KW_ROWS; ++r) {
+      const int ij = (i0 + r) * n + j;
+      an_[r] = A[ij + n];
+      ae_[r] = A[ij + dE];
+      aw_[r] = A[ij - dW];
+      if constexpr (MODE != KW_NORMALIZE) {
+        xn_[r] = X[ij + n];
+        xe_[r] = X[ij + dE];
+        xw_[r] = X[ij - dW];
+      }
+      if constexpr (MODE == KW_NORMALIZE || MODE == KW_INNER) v_[r] = y[(size_t)b * ystride + ij];
+      if constexpr (MODE == KW_RESIDUAL) v_[r] = f[base + ij];
+    }
+#pragma unroll
+    for (int r = 0; r < KW_ROWS; ++r) {
+      const int ij = (i0 + r) * n + j;
+      const double an = an_[r];
+      const double aN = !form ? kharm(ac, an) : ac;
+      const double aE = (hasE && !form) ? kharm(ac, (double)ae_[r]) : ac;
+      const double aW = (hasW && !form) ? kharm(ac, (double)aw_[r]) : ac;
+      const double sa = aE + aW + aN + aS;
+      if constexpr (MODE == KW_NORMALIZE) {
+        const double v = (double)v_[r] * sb;
+        y[(size_t)b * ystride + ij] = (float)v;
+        rt[base + ij] = (float)(v * krcp(sa * ih2 + conv_diag));
+      } else {
+        const double xn = (double)xn_[r];
+        const double xE = hasE ? (double)xe_[r] : 0.0;
+        const double xW = hasW ? (double)xw_[r] : 0.0;
+        const double Ax = (sa * xc - aE * xE - aW * xW - aN * xn - aS * xs) * ih2 +
+                          (bxp * (xc - xW) + bxm * (xE - xc) + byp * (xc - xs) + bym * (xn - xc)) * ih;
+        if constexpr (MODE == KW_INNER)
+          rt[base + ij] = (float)(((double)v_[r] - Ax) * krcp(sa * ih2 + conv_diag));
+        else
+          y[(size_t)b * ystride + ij] = (MODE == KW_RESIDUAL) ? (float)((double)v_[r] - Ax) : (float)Ax;
+        xs = xc; xc = xn;
+      }
+      ac = an; aS = form ? an : aN;
+    }
+    return;
+  }
 #pragma unroll 2
   for (int r = 0; r < KW_ROWS; ++r) {
     const int i = i0 + r;
