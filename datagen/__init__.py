@@ -35,7 +35,7 @@ __all__ = [
     "rng_for", "grf", "blocks_lognormal", "checkerboard", "inclusions",
     "mixture", "velocity", "rhs", "mldata", "weight_shapes", "num_weights",
     "xavier_weights", "Problem", "make_batch", "WORKLOADS", "levels_for", "var_sizes", "VAR_SIZES",
-    "white_noise_coef",
+    "white_noise_coef", "coef_from_tensor", "mldata_levels", "mldata_coef",
 ]
 
 WEIGHT_STREAM = 0x5EED
@@ -145,16 +145,35 @@ def mldata(n: int, rng: np.random.Generator, levels: int = 4, init_size: int = 5
     return interp(d, n)
 
 
-def white_noise_coef(n: int, rng: np.random.Generator, Re: float) -> np.ndarray:
-    """The paper's test coefficients (Sec. 4.1 "Problem settings"): a white-noise tensor
-    (i.i.d. N(0, 1)) mapped linearly onto [0, log10 Re] as a power p, then coef = 10^-p, so
-    the mesh Reynolds number 1/coef spans [1, Re].  coef = mu / h is the diffusion
-    coefficient in units of the mesh size; the returned field is mu = coef * h, the
-    coefficient of the physically scaled operator, whose rows are the paper's (Eq. (8)) times
-    1/h."""
-    w = rng.standard_normal((n, n))
+def coef_from_tensor(w: np.ndarray, Re: float) -> np.ndarray:
+    """Sec. 4.1 "Problem settings": a random tensor mapped linearly onto [0, log10 Re] as a
+    power p, then coef = 10^-p, so the mesh Reynolds number 1/coef spans [1, Re].  coef = mu / h
+    is the diffusion coefficient in units of the mesh size; the returned field is
+    mu = coef * h, the coefficient of the physically scaled operator, whose rows are the
+    paper's (Eq. (8)) times 1/h."""
+    n = w.shape[0]
     p = math.log10(Re) * (w - w.min()) / (w.max() - w.min())
     return 10.0 ** (-p) / (n + 1)
+
+
+def white_noise_coef(n: int, rng: np.random.Generator, Re: float) -> np.ndarray:
+    """The paper's test coefficients: white noise (i.i.d. N(0, 1)) through coef_from_tensor."""
+    return coef_from_tensor(rng.standard_normal((n, n)), Re)
+
+
+def mldata_levels(n: int, init_size: int = 5) -> int:
+    """Doublings of Alg. 4 for a target side n: the most that keep init_size * 2^levels <= n,
+    at least 1 (the noise then reaches down to the scale of a few mesh cells)."""
+    levels = 0
+    while init_size * 2 ** (levels + 1) <= n:
+        levels += 1
+    return max(1, levels)
+
+
+def mldata_coef(n: int, rng: np.random.Generator, Re: float) -> np.ndarray:
+    """The paper's "mldata" coefficients (Sec. 4.3, Alg. 4 with init_size 5) through
+    coef_from_tensor."""
+    return coef_from_tensor(mldata(n, rng, levels=mldata_levels(n)), Re)
 
 
 def velocity(rng: np.random.Generator, kind: str) -> np.ndarray:
@@ -253,6 +272,8 @@ WORKLOADS = {
     "paper_re10": Workload("paper_re10", 6, "white", 0.0, 0.0, "paper", "ones", 10.0, "nondiv"),
     "paper_re1e3": Workload("paper_re1e3", 7, "white", 0.0, 0.0, "paper", "ones", 1e3, "nondiv"),
     "paper_re1e5": Workload("paper_re1e5", 8, "white", 0.0, 0.0, "paper", "ones", 1e5, "nondiv"),
+    # the same problems with multi-level random coefficients (Sec. 4.3 "mldata", Alg. 4), Re = 1000
+    "paper_mldata": Workload("paper_mldata", 9, "mldata", 0.0, 0.0, "paper", "ones", 1e3, "nondiv"),
 }
 
 
@@ -275,11 +296,16 @@ def make_problem(workload: str, n: int, index: int, seed: int = 0) -> Problem:
         a = mixture(n, ra)
     elif w.coef == "white":
         a = white_noise_coef(n, ra, w.re)
+    elif w.coef == "mldata":
+        a = mldata_coef(n, ra, w.re)
     else:
         raise ValueError(w.coef)
     b = velocity(rng_for(seed, w.wid, index, STREAM_B), w.vel)
     f = rhs(n, rng_for(seed, w.wid, index, STREAM_F), w.f_kind)
-    return Problem(n, a.astype(np.float32), b.astype(np.float32), f.astype(np.float32))
+    # C-contiguous float32 (fancy indexing, as in the interpolation of mldata, can return
+    # arrays in Fortran order, and astype keeps the order)
+    c32 = lambda x: np.ascontiguousarray(x, dtype=np.float32)
+    return Problem(n, c32(a), c32(b), c32(f))
 
 
 def var_sizes(count: int, seed: int = 0, sizes=VAR_SIZES, workload: str = "mixture_var") -> list[int]:

@@ -117,6 +117,12 @@ typedef struct {
                        each restart keeps the k directions in which the preconditioned operator
                        of the finished cycle is smallest (right singular vectors of its
                        Hessenberg matrix) as the first k basis vectors of the next cycle */
+  int levels;       /* network only: levels of the setup and solve networks.  0 (default) =
+                       log2(n+1), coarsest grid 1 x 1; a negative value -d = log2(n+1) - d (-1 is
+                       the count Sec. 4.1 uses: 4, 5, 6, ... levels for 31, 63, 127, ..., coarsest
+                       3 x 3); a positive value = exactly that many levels.  The resulting count
+                       must lie in [1, log2(n+1)], checked by mgcnn_setup (MGCNN_E_ARG); mgcnn_create
+                       rejects values outside [-11, 12] */
 } mgcnn_opts;
 
 /* Default options: 16 channels, f32 state (split-bf16 matrix arithmetic), f64 u, graphs off,

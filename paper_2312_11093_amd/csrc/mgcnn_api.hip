@@ -100,6 +100,13 @@ int level_count(int n) {
   return L;
 }
 
+// Levels of the networks for grid side n under opts.levels; 0 if out of range.
+int net_levels(const mgcnn_ctx* c, int n) {
+  const int full = level_count(n), o = c->opts.levels;
+  const int L = o == 0 ? full : (o < 0 ? full + o : o);
+  return (L >= 1 && L <= full) ? L : 0;
+}
+
 void drop_graph(mgcnn_ctx* c);
 
 void free_problem(mgcnn_ctx* c) {
@@ -132,7 +139,7 @@ int alloc(mgcnn_ctx* c, void** p, size_t bytes) {
 int ensure_problem(mgcnn_ctx* c, int n, int B) {
   if (c->alloc_n == n && c->alloc_B == B) return MGCNN_OK;
   free_problem(c);
-  const int L = level_count(n);
+  const int L = c->gmg_on() ? level_count(n) : net_levels(c, n);
   c->nl.assign(L, 0);
   int m = n;
   for (int l = 0; l < L; ++l) { c->nl[l] = m; m = (m - 1) / 2; }
@@ -307,6 +314,7 @@ void mgcnn_default_opts(mgcnn_opts* o) {
   o->gmg_omega = 0.67f;
   o->op_form = MGCNN_OP_DIV;
   o->deflate = 0;
+  o->levels = 0;
 }
 
 size_t mgcnn_num_weights(int channels) {
@@ -336,6 +344,7 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.op_form != MGCNN_OP_DIV && o.op_form != MGCNN_OP_NONDIV) return MGCNN_E_ARG;
   if (o.deflate < 0 || o.deflate > 32) return MGCNN_E_ARG;
   if (o.method == MGCNN_METHOD_FGMRES && o.deflate > 0 && o.deflate >= o.restart) return MGCNN_E_ARG;
+  if (o.levels < -11 || o.levels > 12) return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
   if (!c) return MGCNN_E_NOMEM;
   c->opts = o;
@@ -375,6 +384,8 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
     if (!std::isfinite(b_host[i])) return fail(c, MGCNN_E_ARG, "setup: non-finite velocity");
   if (c->gmg_on() && gmg_levels_for(c, n) == 0)
     return fail(c, MGCNN_E_ARG, "setup: gmg_levels out of range for this n");
+  if (!c->gmg_on() && net_levels(c, n) == 0)
+    return fail(c, MGCNN_E_ARG, "setup: levels out of range for this n");
   c->ready = false;
   int r = ensure_problem(c, n, B);
   if (r) return r;

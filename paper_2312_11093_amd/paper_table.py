@@ -11,8 +11,12 @@ draws, the iteration count, setup time and solve time of
     diverge on white-noise coefficients);
 
 next to the GMG iteration counts the paper prints (Sec. 4.2, double precision table).
+--data mldata takes the coefficients from the multi-level generator of Alg. 4 instead of white
+noise (Sec. 4.3, Re = 1000); --net-levels sets the network's level count (0: log2(n+1), coarsest
+grid 1 x 1; -1: the count of Sec. 4.1, coarsest grid 3 x 3).
 
-    python -m paper_2312_11093_amd.paper_table [--re 1000] [--sizes 31,63,...] [--draws 3]
+    python -m paper_2312_11093_amd.paper_table [--re 1000] [--data white|mldata] [--net-levels 0]
+                                               [--sizes 31,63,...] [--draws 3]
 """
 from __future__ import annotations
 
@@ -38,6 +42,8 @@ def main():
     ap.add_argument("--draws", type=int, default=3)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=2000)
+    ap.add_argument("--data", default="white", choices=["white", "mldata"])
+    ap.add_argument("--net-levels", type=int, default=0)
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -46,17 +52,22 @@ def main():
     from paper_2312_11093_amd import Solver
     from paper_2312_11093_amd.handbuilt import vcycle_weights
 
-    wl = {10.0: "paper_re10", 1000.0: "paper_re1e3", 1e5: "paper_re1e5"}[args.re]
+    if args.data == "mldata":
+        if args.re != 1000.0:
+            ap.error("--data mldata is posed with Re = 1000")
+        wl = "paper_mldata"
+    else:
+        wl = {10.0: "paper_re10", 1000.0: "paper_re1e3", 1e5: "paper_re1e5"}[args.re]
     sizes = [int(x) for x in args.sizes.split(",")]
     rows = []
     for n in sizes:
-        row = {"n": n, "paper_gmg_iters": PAPER_GMG.get(n) if args.re == 1000.0 else None}
+        row = {"n": n, "paper_gmg_iters": PAPER_GMG.get(n) if wl == "paper_re1e3" else None}
         for name in ("gmg", "network"):
             if name == "gmg":
                 S = Solver(None, precond="gmg", u="f64", form="nondiv", use_graph=True)
             else:
                 S = Solver(vcycle_weights(), state="f32", u="f64", form="nondiv",
-                           method="fgmres", restart=30)
+                           method="fgmres", restart=30, levels=args.net_levels)
             its, tset, tsol, ok = [], [], [], True
             for d in range(args.draws + 1):          # draw 0 warms up
                 p = datagen.make_problem(wl, n, d, 0)

@@ -72,3 +72,36 @@ def test_var_sizes_seeded_and_in_range():
     assert s1 == s2 and set(s1) <= set(datagen.VAR_SIZES)
     assert len(set(s1)) == len(datagen.VAR_SIZES)          # 256 draws hit every size
     assert datagen.var_sizes(8, seed=1) != datagen.var_sizes(8, seed=0)
+
+
+@pytest.mark.parametrize("workload", ["paper_re1e3", "paper_mldata"])
+def test_paper_coefficients_span_the_reynolds_range(workload):
+    """Sec. 4.1: coef = mu / h spans exactly [1/Re, 1] (the linear map sends the tensor's
+    minimum to 1 and its maximum to 1/Re); the paper's velocity and a constant right-hand side."""
+    n = 63
+    p = datagen.make_problem(workload, n, 0)
+    coef = p.a.astype(np.float64) * (n + 1)
+    Re = datagen.WORKLOADS[workload].re
+    assert np.isclose(coef.max(), 1.0, rtol=1e-6) and np.isclose(coef.min(), 1.0 / Re, rtol=1e-6)
+    assert np.allclose(p.b, [np.sin(0.5), np.cos(0.5)]) and (p.f == 1).all()
+
+
+def test_mldata_levels_and_smoothness():
+    """Alg. 4: the doublings stop at the largest 5 * 2^k <= n, and the multi-level field is
+    smoother than white noise (neighbouring values correlate strongly)."""
+    assert [datagen.mldata_levels(n) for n in (7, 31, 63, 1023)] == [1, 2, 3, 7]
+    rng = np.random.default_rng(3)
+    ml = datagen.mldata(255, rng, levels=datagen.mldata_levels(255))
+    d = ml - ml.mean()
+    corr = float((d[:, 1:] * d[:, :-1]).sum() / np.sqrt((d[:, 1:] ** 2).sum() * (d[:, :-1] ** 2).sum()))
+    assert corr > 0.9
+
+
+@pytest.mark.parametrize("workload", sorted(datagen.WORKLOADS))
+def test_problems_are_c_contiguous_float32(workload):
+    """Every generated field is C-contiguous float32 (the binding takes device copies as is)."""
+    if workload in ("grf4095",):
+        pytest.skip("large")
+    p = datagen.make_problem(workload, 31, 0)
+    for x in (p.a, p.b, p.f):
+        assert x.dtype == np.float32 and x.flags["C_CONTIGUOUS"]

@@ -105,6 +105,41 @@ def test_apply_network(n, B, split):
     S.close()
 
 
+@pytest.mark.parametrize("n,levels", [(31, -1), (63, -1), (127, -2), (63, 3), (15, 1)])
+def test_apply_network_fewer_levels(n, levels):
+    """opts.levels: the networks cut short (negative = levels below log2(n+1); -1 is the count
+    of Sec. 4.1, coarsest grid 3 x 3) match the oracle with the same number of levels: setup
+    tensors and one application, and two iterations with u in f64."""
+    say("apply fewer levels", n, levels)
+    B = 2
+    full = datagen.levels_for(n)
+    L = full + levels if levels < 0 else levels
+    a, b, f = batch("mixture127", n, B, seed=5)
+    w = datagen.xavier_weights(16, 2)
+    rng = np.random.default_rng(n + 7)
+    r = rng.standard_normal((B, n, n)).astype(np.float32)
+    S = Solver(w, state="f32", u="f64", levels=levels)
+    S.setup(dev(a), b)
+    assert S.levels == L
+    z = S.apply(dev(r)).cpu().numpy()
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    S.forward(dev(f), u, 2)
+    for p in range(B):
+        ref = osv.Solver(w, a[p], b[p], levels=L)
+        got_s = S.get_setup_tensor(L).cpu().numpy()[p]
+        exp_s = np.moveaxis(ref.s[L - 1], 0, -1)
+        assert rel(got_s, exp_s) <= F32_TOL
+        e1 = rel(z[p], ref.correction(r[p].astype(np.float64)))
+        e2 = rel(u[p].cpu().numpy(), ref.forward(f[p], 2))
+        say("  rel err apply", e1, "forward", e2)
+        assert e1 <= F32_TOL and e2 <= F32_TOL
+    S.close()
+    bad = Solver(w, state="f32", levels=full + 1)
+    with pytest.raises(M.MGCNNError):
+        bad.setup(dev(a), b)
+    bad.close()
+
+
 @pytest.mark.parametrize("split", [True, False])
 @pytest.mark.parametrize("K", [1, 2, 8])
 def test_forward_grf31(K, split):

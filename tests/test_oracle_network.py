@@ -214,12 +214,14 @@ def test_jacobi_residual_l1_monotone_and_converges_to_direct_solve():
     np.testing.assert_allclose(u, u_ref, rtol=1e-8, atol=1e-10 * np.abs(u_ref).max())
 
 
-def test_additive_special_case_is_sum_of_transfers():
+@pytest.mark.parametrize("drop", [0, 1, 2])
+def test_additive_special_case_is_sum_of_transfers(drop):
     """Zero smoothers, full-weighting restriction, bilinear prolongation and
     channel-0 identities in/out: B = omega * sum_{l=0}^{L-1} P^l R^l on r/D
-    (pins stride, padding and the order of the up loop)."""
+    (pins stride, padding and the order of the up loop), also for a hierarchy cut
+    short by `drop` levels (the sum stops at the coarsest level kept)."""
     C, n, omega = 2, 15, 0.7
-    L = net.num_levels(n)
+    L = net.num_levels(n) - drop
     P = _zero_net(C)
     k = np.outer([1, 2, 1], [1, 2, 1]).astype(float)
     P["W_in"][0, 0, 1, 1] = 1.0
@@ -231,7 +233,8 @@ def test_additive_special_case_is_sum_of_transfers():
     a = np.exp(rng.standard_normal((n, n)))
     b = (0.3, 0.2)
     r = rng.standard_normal((n, n))
-    S = sv.Solver(w, a, b)
+    S = sv.Solver(w, a, b, levels=L)
+    assert len(S.s) == L
     got = S.correction(r)
     # textbook matrices, level by level
     Ps = []
