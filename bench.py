@@ -11,7 +11,8 @@ partition with log10 a ~ U(-2, 2), b = |b|(cos t, sin t) with |b| ~ U(0, 10), f 
 16 channels, 10 levels; float32 state on MFMA, f64 u / residual / norm.  Weights: the hand-set
 coefficient-aware V(1,1) cycle (no trained weights ship with the library).
 
-Prints one JSON line: metric, value (solves/s, whole batch), roofline of the dominant kernel
+Prints one JSON line: metric, value (solves/s, whole batch, setup + solve; the setup time and
+the solve-only rate beside it), roofline of the dominant kernel
 (HIP events around its launches in a profiled pass), the same solver run one problem at a time
 in FP32 ("plain FP32 unbatched") on the same GPU, and the FP64 oracle timed on the host cores.
 """
@@ -186,9 +187,15 @@ def main():
     dfl = args.deflate if args.method == "fgmres" else 0
     S = make(args.state, not args.no_graph)
 
+    setup_times = []
+
     def step():
         u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         S.setup(da, b)
+        torch.cuda.synchronize()
+        setup_times.append(time.perf_counter() - t0)
         return S.solve(df, u, args.tol, args.maxit)
 
     for _ in range(args.warmup):
@@ -196,6 +203,7 @@ def main():
         print(f"[bench] warmup step done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     times, its = [], []
+    del setup_times[:]
     for k in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -342,6 +350,9 @@ def main():
         "roofline": roof, "kernel_time_share": kernel_share, "finest_level_kernels": level0,
         "profiled_pass": {"what": "one whole solve of the batch", "kernel_ms": round(prof_ms, 2)},
         "plain_fp32_unbatched": plain,
+        "setup_ms": round(1000.0 * float(np.mean(setup_times)), 3),
+        "solves_per_s_solve_only": (round(B / ((ms - 1000.0 * float(np.mean(setup_times))) / 1000.0), 3)
+                                    if converged else 0.0),
         "speedup_vs_plain_fp32": (round(value / plain["value"], 3)
                                   if plain and plain["value"] > 0 and converged else None),
         "gmg_baseline": gmg,
