@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void dconv_kernel(ConvArgs A) {
     if constexpr (EP == EP_STORE) Y[o] = acc[o];
     if constexpr (EP == EP_ADD) Y[o] += acc[o];
     if constexpr (EP == EP_SKIP) Y[o] = A.skip[op * CO + o] + acc[o];
-    if constexpr (EP == EP_TANH_BIAS) Y[o] = tanhf(acc[o] + A.bias[o]);
+    if constexpr (EP == EP_TANH_BIAS) Y[o] = mg_tanh(acc[o] + A.bias[o]);
     if constexpr (EP == EP_SMOOTH_BWD) {
       Y[o] = A.skip[op * CO + o] + A.m2[op * CO + o] * acc[o];
       A.gs[op * CO + o] += A.m3[op * CO + o] * acc[o];

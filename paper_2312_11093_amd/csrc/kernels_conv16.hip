@@ -309,10 +309,10 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
       const float4 c = xc[tt];
       float4 o;
       if constexpr (MODE == CM_TANH) {
-        o.x = c.x + tanhf(acc[0] + bias[4 * g + 0]);
-        o.y = c.y + tanhf(acc[1] + bias[4 * g + 1]);
-        o.z = c.z + tanhf(acc[2] + bias[4 * g + 2]);
-        o.w = c.w + tanhf(acc[3] + bias[4 * g + 3]);
+        o.x = c.x + mg_tanh(acc[0] + bias[4 * g + 0]);
+        o.y = c.y + mg_tanh(acc[1] + bias[4 * g + 1]);
+        o.z = c.z + mg_tanh(acc[2] + bias[4 * g + 2]);
+        o.w = c.w + mg_tanh(acc[3] + bias[4 * g + 3]);
       } else {
         o.x = c.x + acc[0]; o.y = c.y + acc[1]; o.z = c.z + acc[2]; o.w = c.w + acc[3];
       }
@@ -670,11 +670,11 @@ static void conv16_launch(ConvMode mode, const void* x, const void* s, const flo
 void launch_conv16(ConvMode mode, StateType st_, const void* x, const void* s, const float* W,
                    const float* bias, void* y, int m, int B, const int* active, hipStream_t st,
                    bool s_bf16) {
-  // the setup network's tanh layers run in f32.  With f32 storage only the same-size smoothers
-  // use the split (measured faster there); the restriction keeps f32 MFMA (larger LDS tile,
-  // lower occupancy with three planes).
+  // With f32 storage the same-size convs (smoothers and the setup network's tanh layers) use
+  // the split when asked (measured faster there); the restriction keeps f32 MFMA (larger LDS
+  // tile, lower occupancy with three planes).  bf16 storage has no tanh layers.
   const bool sb = s_bf16 && st_ != ST_BF16 && mode == CM_SMOOTH;
-  if (mode == CM_TANH || st_ == ST_F32 || (st_ == ST_F32X && mode == CM_RESTRICT)) {
+  if (st_ == ST_F32 || (st_ == ST_F32X && mode == CM_RESTRICT)) {
     if (sb) conv16_launch<ST_F32, true>(mode, x, s, W, bias, y, m, B, active, st);
     else conv16_launch<ST_F32>(mode, x, s, W, bias, y, m, B, active, st);
   } else if (st_ == ST_F32X) {

@@ -418,8 +418,8 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
     float* ping[2] = {za, zb};
     for (int k = 0; k < NUM_SETUP_LAYERS; ++k) {
       float* zout = (k == NUM_SETUP_LAYERS - 1 && !c->s16()) ? (float*)c->s[l] : ping[k & 1];
-      launch_conv16(CM_TANH, ST_F32, zin, nullptr, c->W(c->off.res_w[k]), c->W(c->off.res_b[k]), zout,
-                    m, B, nullptr, s);
+      launch_conv16(CM_TANH, c->opts.f32_split ? ST_F32X : ST_F32, zin, nullptr, c->W(c->off.res_w[k]),
+                    c->W(c->off.res_b[k]), zout, m, B, nullptr, s);
       zin = zout;
     }
     if (c->s16()) launch_f32_to_bf16(zin, (bf16_t*)c->s[l], cnt, s);

@@ -32,6 +32,27 @@ __device__ __forceinline__ double block_sum_256(double v) {
   return s;
 }
 
+// tanh of the setup network's layers (Eq. (6)).  |x| <= 1/4: the Taylor series
+//   x - x^3/3 + 2x^5/15 - 17x^7/315 + 62x^9/2835 - 1382x^11/155925 + 21844x^13/6081075,
+// whose first omitted term is below 1e-10 |x| there; |x| > 1/4: 1 - 2 / (exp(2|x|) + 1) with the
+// sign of x, where tanh >= 0.24 keeps the cancellation below a factor 4, so the error stays
+// within a few float32 ulps of the exponential's (about 1e-6 relative at worst).
+__device__ __forceinline__ float mg_tanh(float x) {
+  const float ax = fabsf(x);
+  if (ax <= 0.25f) {
+    const float x2 = x * x;
+    float p = 21844.f / 6081075.f;
+    p = fmaf(p, x2, -1382.f / 155925.f);
+    p = fmaf(p, x2, 62.f / 2835.f);
+    p = fmaf(p, x2, -17.f / 315.f);
+    p = fmaf(p, x2, 2.f / 15.f);
+    p = fmaf(p, x2, -1.f / 3.f);
+    return fmaf(x * x2, p, x);
+  }
+  const float e = __expf(2.f * ax);
+  return copysignf(1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f), x);
+}
+
 // bf16 conversion: the hardware packed convert (round to nearest even) of gfx950.
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
