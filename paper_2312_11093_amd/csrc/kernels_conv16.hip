@@ -463,8 +463,9 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
     const int fr_local = wave * 2 + (task >> 2);   // fine row within the 8-row tile
     const int par = (task >> 1) & 1;                // fine column parity
     const int jb = task & 1;                        // 16-wide block of coarse columns
-    const int i = 2 * I0 + fr_local;
-    if (i >= m) continue;
+    const int i = 2 * I0 + fr_local;   // rows past the grid are computed too (the staged coarse
+                                       // tile is zero there) and not stored, so the segments'
+                                       // loads and MFMAs can be scheduled together
     const int jc = jb * 16 + px;                    // coarse column within the tile
     f4v acc = {0.f, 0.f, 0.f, 0.f};
     const int np = (fr_local & 1) ? 1 : 2;
@@ -483,7 +484,7 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
       }
     }
     const int j = 2 * (J0 + jc) + par;
-    if (j < m) {
+    if (i < m && j < m) {
       float4 o = yv[task];
       o.x += acc[0]; o.y += acc[1]; o.z += acc[2]; o.w += acc[3];
       st4(Fb, i * m + j, g, o);
