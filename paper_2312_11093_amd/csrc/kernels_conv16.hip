@@ -296,8 +296,7 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
   for (int tt = 0; tt < K::TPW; ++tt) {
     const int task = wave * K::TPW + tt;
     const int orow = task / K::NSEG, seg = task % K::NSEG;
-    const int gi = row0 + orow;
-    if (gi >= m || col0 + seg * 16 >= m) continue;
+    const int gi = row0 + orow;   // segments past the grid are computed (zero staged tile), not stored
     f4v acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int p = 0; p < 3; ++p)
@@ -305,7 +304,7 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
       for (int q = 0; q < 3; ++q)
         acc = fr.mma(p * 3 + q, &lds[((orow + p) * K::IC + seg * 16 + px + q) * PS], acc, PSTR);
     const int gj = col0 + seg * 16 + px;
-    if (gj < m) {
+    if (gi < m && gj < m) {
       const float4 c = xc[tt];
       float4 o;
       if constexpr (MODE == CM_TANH) {
@@ -607,8 +606,7 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
   for (int tt = 0; tt < K::TPW; ++tt) {
     const int task = wave * K::TPW + tt;
     const int orow = task / K::NSEG, seg = task % K::NSEG;
-    const int gi = row0 + orow;
-    if (gi >= m || col0 + seg * 16 >= m) continue;
+    const int gi = row0 + orow;   // segments past the grid are computed (zero staged tile), not stored
     f4v acc = {0.f, 0.f, 0.f, 0.f};
     if constexpr (SKIP_MMA) {
       // x1 at the output pixel: B[k = g][px] = rt at tap 4 s + g (zero for taps 9..11)
@@ -626,7 +624,7 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
       for (int q = 0; q < 3; ++q)
         acc = fr.mma(p * 3 + q, &lds[((orow + p) * K::IC + seg * 16 + px + q) * PS], acc, PSTR);
     const int gj = col0 + seg * 16 + px;
-    if (gj < m) {
+    if (gi < m && gj < m) {
       float4 xo;
       if constexpr (SKIP_MMA) {
         xo = make_float4(0.f, 0.f, 0.f, 0.f);
