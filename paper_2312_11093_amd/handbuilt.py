@@ -53,11 +53,13 @@ def parameter_shapes(C: int) -> list[tuple[str, tuple[int, ...]]]:
     return s
 
 
-def vcycle_weights(C: int = 16, omega: float = 0.9, alpha: float = 0.05) -> np.ndarray:
+def vcycle_weights(C: int = 16, omega: float = 0.9, alpha: float = 0.05,
+                   omega_up: float | None = None) -> np.ndarray:
     """Flat float32 weights of the hand-set V(1,1) cycle described in the module docstring.
 
     omega: Jacobi damping of both smoothers (0.9 measured best as an FGMRES preconditioner on
     the 10^4-contrast block workload; 0.8 converges faster as a stationary cycle on Poisson);
+    omega_up: damping of the up smoother alone (default: omega);
     alpha: scale of the coupling features carried through the tanh layers (the smoother taps
     divide it out again)."""
     if C < 15:
@@ -85,9 +87,10 @@ def vcycle_weights(C: int = 16, omega: float = 0.9, alpha: float = 0.05) -> np.n
     P["prolong"][E, DE] = fw
     for d in range(4):
         P["prolong"][E, DC[d]] = fw
-    P["smooth_up"][E, R, 1, 1] = omega
-    P["smooth_up"][E, DE, 1, 1] = 1.0 - omega
+    wu = omega if omega_up is None else omega_up
+    P["smooth_up"][E, R, 1, 1] = wu
+    P["smooth_up"][E, DE, 1, 1] = 1.0 - wu
     for d in range(4):
-        P["smooth_up"][E, DC[d], TAP[d][0], TAP[d][1]] = omega / alpha
+        P["smooth_up"][E, DC[d], TAP[d][0], TAP[d][1]] = wu / alpha
     P["solve_out"][0, E, 1, 1] = 1.0
     return np.concatenate([P[name].ravel() for name, _ in parameter_shapes(C)]).astype(np.float32)
