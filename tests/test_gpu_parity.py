@@ -260,6 +260,23 @@ def test_setup_rejects_bad_sizes():
     S.close()
 
 
+def test_setup_rejects_empty_batch_and_oversize_grid():
+    """Degenerate sizes are argument errors raised before any device work: an empty batch,
+    and a side beyond the 4095 the library supports (8191 = 2^13 - 1)."""
+    say("empty batch, oversize grid")
+    S = Solver(datagen.xavier_weights(16, 0))
+    empty = torch.zeros((0, 31, 31), dtype=torch.float32, device="cuda")
+    with pytest.raises(M.MGCNNError) as e:
+        S.setup(empty, np.zeros((0, 2)))
+    assert e.value.status in (M.E_SIZE, M.E_ARG)
+    big = torch.ones((1, 8191, 8191), dtype=torch.float32, device="cuda")
+    with pytest.raises(M.MGCNNError) as e:
+        S.setup(big, np.ones((1, 2)))
+    assert e.value.status == M.E_SIZE
+    del big
+    S.close()
+
+
 def test_full_size_blocks1023_sampled():
     """The batched 64 x 1023^2 workload in the launch configuration the benchmark uses:
     one fixed iteration for the whole batch, two sampled problems compared with the oracle."""
