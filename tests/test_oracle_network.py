@@ -255,6 +255,38 @@ def test_additive_special_case_is_sum_of_transfers(drop):
     np.testing.assert_allclose(got.ravel(), omega * acc, rtol=1e-12, atol=1e-13)
 
 
+def test_adjoint_weights_make_the_cycle_symmetric():
+    """With s = 1, an up smoother that is the adjoint of the down smoother (kernel flipped,
+    channel axes swapped), TCNN = RCNN (the same array, Sec. 2.4, Eq. (3)) and reChannel-out the
+    adjoint of reChannel-in, the solve network is a symmetric operator (the symmetric variant of
+    the remark in Sec. 3.3); plain sharing W_up = W_dn is not.  Pins the adjoint relations of
+    the three convolutions and the order of the up loop."""
+    C, n = 4, 7
+    rng = np.random.default_rng(21)
+    P = net.unpack_weights(datagen.xavier_weights(C, 3).astype(np.float64), C)
+    adj = lambda W: np.flip(W, (2, 3)).transpose(1, 0, 2, 3).copy()
+    P["W_T"] = P["W_R"].copy()
+    P["W_out"] = adj(P["W_in"])
+    L = net.num_levels(n)
+    ones = [np.ones((C, m, m)) for m in [n >> l for l in range(L)]]
+
+    def matrix(PP):
+        N = n * n
+        M = np.zeros((N, N))
+        for k in range(N):
+            e = np.zeros(N)
+            e[k] = 1.0
+            M[:, k] = net.vcycle(PP, ones, e.reshape(n, n)).ravel()
+        return M
+
+    P["W_up"] = adj(P["W_dn"])
+    M = matrix(P)
+    assert np.linalg.norm(M - M.T) <= 1e-13 * np.linalg.norm(M)
+    P["W_up"] = P["W_dn"].copy()
+    M = matrix(P)
+    assert np.linalg.norm(M - M.T) > 0.1 * np.linalg.norm(M)
+
+
 def test_linearity_in_rhs():
     """Principle P2: u_K is linear in f for u_0 = 0."""
     C, n, K = 4, 15, 3
