@@ -123,6 +123,12 @@ typedef struct {
                        3 x 3); a positive value = exactly that many levels.  The resulting count
                        must lie in [1, log2(n+1)], checked by mgcnn_setup (MGCNN_E_ARG); mgcnn_create
                        rejects values outside [-11, 12] */
+  int up_post;      /* network only: 0 (default) = up smoother x + W_up * (s . x) as in Alg. 3;
+                       1 = x + s . (W_up * x), the adjoint form of the down smoother: with W_up the
+                       adjoint of W_dn (kernel flipped, channel axes swapped), W_T = W_R and W_out
+                       the adjoint of W_in the solve network is a symmetric operator (the
+                       symmetric variant of the remark in Sec. 3.3).  The recorded forward and
+                       mgcnn_backward reject it (MGCNN_E_ARG) */
 } mgcnn_opts;
 
 /* Default options: 16 channels, f32 state (split-bf16 matrix arithmetic), f64 u, graphs off,

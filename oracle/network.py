@@ -142,9 +142,11 @@ def setup(P: dict, F: np.ndarray, levels: int, keep: bool = False):
 # solve phase (Alg. 3)
 # ------------------------------------------------------------------------------------------
 
-def vcycle(P: dict, s: list, r: np.ndarray, keep: bool = False):
+def vcycle(P: dict, s: list, r: np.ndarray, keep: bool = False, up_post: bool = False):
     """One application of the solve network B to a (n, n) input; returns (n, n).
-    With ``keep`` also return the per-level states for the reverse pass."""
+    With ``keep`` also return the per-level states for the reverse pass.  ``up_post``: the up
+    smoother in the form x + s * (W_up conv x), the adjoint form of the down smoother
+    x + W_dn conv (s * x) (the symmetric variant of the remark in Sec. 3.3)."""
     L = len(s)
     xin = [None] * L
     xdn = [None] * L
@@ -157,7 +159,10 @@ def vcycle(P: dict, s: list, r: np.ndarray, keep: bool = False):
             xin[l + 1] = conv_s2(P["W_R"], xdn[l])
     v[L - 1] = xdn[L - 1]
     for l in range(L - 1, -1, -1):                       # up cycle
-        xup[l] = v[l] + conv_same(P["W_up"], s[l] * v[l])
+        if up_post:
+            xup[l] = v[l] + s[l] * conv_same(P["W_up"], v[l])
+        else:
+            xup[l] = v[l] + conv_same(P["W_up"], s[l] * v[l])
         if l > 0:
             v[l - 1] = xdn[l - 1] + convT_s2(P["W_T"], xup[l])
     out = conv_same(P["W_out"], xup[0])[0]

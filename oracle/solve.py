@@ -28,7 +28,7 @@ class Solver:
     """Setup once for one problem (a, b), then iterate (Sec. 3.1, network phases)."""
 
     def __init__(self, weights: np.ndarray, a: np.ndarray, b, levels: int | None = None,
-                 form: str = "div"):
+                 form: str = "div", up_post: bool = False):
         self.C = net.channels_of(np.asarray(weights).size)
         self.P = net.unpack_weights(weights, self.C)
         self.a = np.asarray(a, dtype=np.float64)
@@ -36,6 +36,7 @@ class Solver:
         self.n = self.a.shape[0]
         self.L = levels if levels is not None else net.num_levels(self.n)
         self.form = form
+        self.up_post = up_post            # up smoother in adjoint form (symmetric variant)
         self.D = op.diagonal(self.a, self.b, form)
         self.F = op.features(self.a, self.b, form)
         self.s = net.setup(self.P, self.F, self.L)
@@ -44,7 +45,7 @@ class Solver:
         return np.asarray(f, dtype=np.float64) - op.apply_A(self.a, self.b, u, self.form)
 
     def correction(self, r):
-        return net.vcycle(self.P, self.s, r / self.D)
+        return net.vcycle(self.P, self.s, r / self.D, up_post=self.up_post)
 
     def step(self, f, u):
         """One iteration u + B((f - A u)/D)."""

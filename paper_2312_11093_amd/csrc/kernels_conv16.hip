@@ -250,8 +250,9 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
   const int row0 = (tile / tiles_x) * K::TH, col0 = (tile % tiles_x) * K::TW;
   const size_t pbase = (size_t)b * m * m * C;     // problem offset in elements
   const E* Xb = x + pbase;
-  const E* Sb = (MODE == CM_SMOOTH && !SBF) ? (const E*)s + pbase : nullptr;
-  const uint16_t* Sh = (MODE == CM_SMOOTH && SBF) ? (const uint16_t*)s + pbase : nullptr;
+  constexpr bool HAS_S = MODE == CM_SMOOTH || MODE == CM_SMOOTH_POST;
+  const E* Sb = (HAS_S && !SBF) ? (const E*)s + pbase : nullptr;
+  const uint16_t* Sh = (HAS_S && SBF) ? (const uint16_t*)s + pbase : nullptr;
   E* Yb = y + pbase;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int px = lane & 15, g = lane >> 4;
@@ -312,6 +313,13 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
         o.y = c.y + mg_tanh(acc[1] + bias[4 * g + 1]);
         o.z = c.z + mg_tanh(acc[2] + bias[4 * g + 2]);
         o.w = c.w + mg_tanh(acc[3] + bias[4 * g + 3]);
+      } else if constexpr (MODE == CM_SMOOTH_POST) {
+        // s of the output pixel's four channels multiplies the convolution (adjoint form)
+        float4 so;
+        if constexpr (SBF) so = ld4(Sh, gi * m + gj, g);
+        else so = ld4(Sb, gi * m + gj, g);
+        o.x = c.x + so.x * acc[0]; o.y = c.y + so.y * acc[1];
+        o.z = c.z + so.z * acc[2]; o.w = c.w + so.w * acc[3];
       } else {
         o.x = c.x + acc[0]; o.y = c.y + acc[1]; o.z = c.z + acc[2]; o.w = c.w + acc[3];
       }
@@ -661,6 +669,9 @@ static void conv16_launch(ConvMode mode, const void* x, const void* s, const flo
   if (mode == CM_SMOOTH)
     hipLaunchKernelGGL((conv16_same_kernel<ST, CM_SMOOTH, SBF>), dim3(tx * ty * B), dim3(256), 0, st,
                        (const E*)x, s, W, bias, (E*)y, m, tx, tx * ty, active);
+  else if (mode == CM_SMOOTH_POST)
+    hipLaunchKernelGGL((conv16_same_kernel<ST, CM_SMOOTH_POST, SBF>), dim3(tx * ty * B), dim3(256), 0, st,
+                       (const E*)x, s, W, bias, (E*)y, m, tx, tx * ty, active);
   else if constexpr (ST != ST_BF16 && !SBF)
     hipLaunchKernelGGL((conv16_same_kernel<ST, CM_TANH>), dim3(tx * ty * B), dim3(256), 0, st,
                        (const E*)x, (const void*)nullptr, W, bias, (E*)y, m, tx, tx * ty, active);
@@ -672,7 +683,7 @@ void launch_conv16(ConvMode mode, StateType st_, const void* x, const void* s, c
   // With f32 storage the same-size convs (smoothers and the setup network's tanh layers) use
   // the split when asked (measured faster there); the restriction keeps f32 MFMA (larger LDS
   // tile, lower occupancy with three planes).  bf16 storage has no tanh layers.
-  const bool sb = s_bf16 && st_ != ST_BF16 && mode == CM_SMOOTH;
+  const bool sb = s_bf16 && st_ != ST_BF16 && (mode == CM_SMOOTH || mode == CM_SMOOTH_POST);
   if (st_ == ST_F32 || (st_ == ST_F32X && mode == CM_RESTRICT)) {
     if (sb) conv16_launch<ST_F32, true>(mode, x, s, W, bias, y, m, B, active, st);
     else conv16_launch<ST_F32>(mode, x, s, W, bias, y, m, B, active, st);

@@ -227,6 +227,7 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool
   // the skip, 1 <-> 16 3x3 conv
   const double FL_CONV = 2.0 * 9 * C * C, FL_SMOOTH = FL_CONV + 2.0 * C, FL_IN = 2.0 * 9 * C;
   auto nodes = [&](int l) { return (double)c->nl[l] * c->nl[l] * B; };
+  const ConvMode up_mode = c->opts.up_post ? CM_SMOOTH_POST : CM_SMOOTH;   // up smoother form
   for (int l = 0; l < L; ++l) {
     if (l == 0) {
       // finest level: reChannel-in folded into the down smoother
@@ -246,7 +247,7 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool
   }
   {
     Prof p(c, MGCNN_K_SMOOTH_UP, L - 1, nodes(L - 1) * (2.0 * S + SS), nodes(L - 1) * FL_SMOOTH);
-    launch_conv16(CM_SMOOTH, st, c->xdn[L - 1], c->s[L - 1], c->W(c->off.smooth_up), nullptr,
+    launch_conv16(up_mode, st, c->xdn[L - 1], c->s[L - 1], c->W(c->off.smooth_up), nullptr,
                   c->xin[L - 1], c->nl[L - 1], B, active, s, sb);
   }
   for (int l = L - 2; l >= 0; --l) {
@@ -258,7 +259,7 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool
     }
     {
       Prof p(c, MGCNN_K_SMOOTH_UP, l, nodes(l) * (2.0 * S + SS), nodes(l) * FL_SMOOTH);
-      launch_conv16(CM_SMOOTH, st, c->xdn[l], c->s[l], c->W(c->off.smooth_up), nullptr, c->xin[l],
+      launch_conv16(up_mode, st, c->xdn[l], c->s[l], c->W(c->off.smooth_up), nullptr, c->xin[l],
                     c->nl[l], B, active, s, sb);
     }
   }
@@ -315,6 +316,7 @@ void mgcnn_default_opts(mgcnn_opts* o) {
   o->op_form = MGCNN_OP_DIV;
   o->deflate = 0;
   o->levels = 0;
+  o->up_post = 0;
 }
 
 size_t mgcnn_num_weights(int channels) {
@@ -345,6 +347,7 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.deflate < 0 || o.deflate > 32) return MGCNN_E_ARG;
   if (o.method == MGCNN_METHOD_FGMRES && o.deflate > 0 && o.deflate >= o.restart) return MGCNN_E_ARG;
   if (o.levels < -11 || o.levels > 12) return MGCNN_E_ARG;
+  if (o.up_post != 0 && o.up_post != 1) return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
   if (!c) return MGCNN_E_NOMEM;
   c->opts = o;

@@ -48,7 +48,8 @@ void launch_conv_in(int cin, const float* in, const float* W, void* out, StateTy
 // C->C conv on MFMA.  mode: SMOOTH  y = x + W*(s.x)        (same size, s given)
 //                           TANH    y = x + tanh(W*x + bias) (same size, f32 only)
 //                           RESTRICT y = W *_{stride 2} x    (m -> (m-1)/2)
-enum ConvMode : int { CM_SMOOTH = 0, CM_TANH = 1, CM_RESTRICT = 2 };
+//                           SMOOTH_POST y = x + s . (W*x)  (same size, s given: the adjoint form)
+enum ConvMode : int { CM_SMOOTH = 0, CM_TANH = 1, CM_RESTRICT = 2, CM_SMOOTH_POST = 3 };
 // s_bf16: s is stored as bf16 while the state is f32 (smoother only).
 void launch_conv16(ConvMode mode, StateType t, const void* x, const void* s, const float* W,
                    const float* bias, void* y, int m, int B, const int* active, hipStream_t st,

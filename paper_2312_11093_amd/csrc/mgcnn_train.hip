@@ -73,6 +73,7 @@ static int ensure_train(mgcnn_ctx* c, int K) {
 int forward_record(mgcnn_ctx* c, const float* f, float* u, int K) {
   if (c->st() == ST_BF16 || c->s16() || c->u64())
     return fail(c, MGCNN_E_ARG, "forward(record): needs f32 state and f32 u");
+  if (c->opts.up_post) return fail(c, MGCNN_E_ARG, "forward(record): no reverse pass for up_post");
   int r = ensure_train(c, K);
   if (r) return r;
   auto& T = c->tr;
@@ -313,6 +314,7 @@ int mgcnn_backward(mgcnn_ctx* c, const float* dL_du, float* dL_dweights, float* 
   if (!c) return MGCNN_E_ARG;
   if (!c->ready) return fail(c, MGCNN_E_STATE, "backward: call mgcnn_setup first");
   if (c->gmg_on()) return fail(c, MGCNN_E_STATE, "backward: no weights with the GMG preconditioner");
+  if (c->opts.up_post) return fail(c, MGCNN_E_ARG, "backward: no reverse pass for up_post");
   auto& T = c->tr;
   if (T.K <= 0 || T.f == nullptr || T.alloc_n != c->n || T.alloc_B != c->B)
     return fail(c, MGCNN_E_NORECORD, "backward: no recorded forward for this problem set");

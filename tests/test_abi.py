@@ -70,11 +70,11 @@ def test_default_options_and_option_checks(lib):
     o = mgcnn.mgcnn_opts()
     lib.mgcnn_default_opts(ctypes.byref(o))
     assert (o.channels, o.method, o.restart, o.gs_passes) == (16, 0, 30, 2)
-    assert (o.precond, o.gmg_levels, o.gmg_sweeps, o.op_form, o.deflate, o.levels) == (0, 0, 3, 0, 0, 0)
+    assert (o.precond, o.gmg_levels, o.gmg_sweeps, o.op_form, o.deflate, o.levels, o.up_post) == (0, 0, 3, 0, 0, 0, 0)
     assert abs(o.gmg_omega - 0.67) < 1e-7
     h = ctypes.c_void_p()
     for field, value in (("precond", 2), ("gmg_sweeps", 0), ("gmg_sweeps", 5), ("gmg_levels", -1),
-                         ("op_form", 2), ("deflate", -1), ("deflate", 33), ("levels", -12), ("levels", 13),
+                         ("op_form", 2), ("deflate", -1), ("deflate", 33), ("levels", -12), ("levels", 13), ("up_post", 2),
                          ("gmg_omega", 0.0), ("gmg_omega", 2.0), ("gs_passes", 3)):
         bad = mgcnn.mgcnn_opts()
         lib.mgcnn_default_opts(ctypes.byref(bad))

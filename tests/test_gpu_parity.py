@@ -141,6 +141,66 @@ def test_apply_network_fewer_levels(n, levels):
 
 
 @pytest.mark.parametrize("split", [True, False])
+@pytest.mark.parametrize("n", [31, 127])
+def test_up_post_matches_oracle(n, split):
+    """opts.up_post: the up smoother in the adjoint form x + s . (W_up * x) (symmetric variant)
+    against the oracle's: one application and two iterations, f32 state on both matrix paths;
+    the recorded forward rejects it."""
+    say("up_post", n, "split" if split else "f32 mfma")
+    B = 2
+    a, b, f = batch("mixture127", n, B, seed=7)
+    w = datagen.xavier_weights(16, 4)
+    r = np.random.default_rng(n + 11).standard_normal((B, n, n)).astype(np.float32)
+    S = Solver(w, state="f32", u="f64", f32_split=split, up_post=True)
+    S.setup(dev(a), b)
+    z = S.apply(dev(r)).cpu().numpy()
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    S.forward(dev(f), u, 2)
+    for p in range(B):
+        ref = osv.Solver(w, a[p], b[p], up_post=True)
+        e1 = rel(z[p], ref.correction(r[p].astype(np.float64)))
+        e2 = rel(u[p].cpu().numpy(), ref.forward(f[p], 2))
+        say("  rel err apply", e1, "forward", e2)
+        assert e1 <= F32_TOL and e2 <= F32_TOL
+    S.close()
+    St = Solver(w, state="f32", u="f32", up_post=True)
+    St.setup(dev(a), b)
+    u32 = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
+    with pytest.raises(M.MGCNNError):
+        St.forward(dev(f), u32, 1, record=True)
+    St.close()
+
+
+def test_up_post_with_adjoint_weights_is_symmetric():
+    """The symmetric variant on the GPU: adjoint up smoother and reChannel-out, TCNN = RCNN,
+    up_post, b = 0: the library's network operator B (columns B e_k = apply(D e_k)) is symmetric
+    to float32 rounding on a 15 x 15 grid with real setup tensors."""
+    say("symmetric variant")
+    n, C = 15, 16
+    P = onet.unpack_weights(datagen.xavier_weights(C, 6).astype(np.float64), C)
+    adj = lambda W: np.flip(W, (2, 3)).transpose(1, 0, 2, 3).copy()
+    P["W_up"] = adj(P["W_dn"])
+    P["W_T"] = P["W_R"].copy()
+    P["W_out"] = adj(P["W_in"])
+    w = onet.pack_weights(P, C).astype(np.float32)
+    a1 = np.exp(np.random.default_rng(5).standard_normal((n, n))).astype(np.float32)
+    N = n * n
+    a = np.broadcast_to(a1, (N, n, n)).copy()
+    b = np.zeros((N, 2), np.float32)
+    D = oop.diagonal(a1, (0.0, 0.0))
+    r = np.zeros((N, n, n), np.float32)
+    for k in range(N):
+        r[k].flat[k] = D.flat[k]
+    S = Solver(w, state="f32", up_post=True)
+    S.setup(dev(a), b)
+    Mb = S.apply(dev(r)).cpu().numpy().reshape(N, N).T.astype(np.float64)   # column k = B e_k
+    S.close()
+    asym = np.linalg.norm(Mb - Mb.T) / np.linalg.norm(Mb)
+    say("  ||B - B^T|| / ||B||", asym)
+    assert asym <= 1e-5
+
+
+@pytest.mark.parametrize("split", [True, False])
 @pytest.mark.parametrize("K", [1, 2, 8])
 def test_forward_grf31(K, split):
     """31x31 lognormal GRF, b = (1,1), f ~ U(-1,1), Xavier weights: K fixed iterations."""
