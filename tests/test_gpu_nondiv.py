@@ -106,13 +106,16 @@ def test_gmg_cycle_and_stationary_solve():
     S.close()
 
 
+@pytest.mark.parametrize("wl", ["paper_re1e3", "paper_mldata", "paper_re1e5"])
 @pytest.mark.parametrize("n", [127, 255, 1023])
-def test_gmg_iterations_against_the_paper(n):
-    """The paper's GMG settings on the paper's problems (3 problems): mean iteration count
-    within 15 % of the printed one at 127^2 and 255^2; at 1023^2 reported only (printed: 45)."""
+def test_gmg_iterations_against_the_paper(n, wl):
+    """The paper's GMG settings on the paper's problems (3 problems), white noise (Re = 1000,
+    1e5) and multi-level coefficients (Appendix B.1): mean iteration count within 15 % of the
+    printed one at 127^2 and 255^2; at 1023^2 reported only."""
     B = 3
-    want = json.load(open(GOLDEN))["gmg_iterations"][str(n)]
-    a, b, f = datagen.make_batch(WL, n, B, seed=7)
+    tab = json.load(open(GOLDEN))["appendix_b1"]
+    want = tab["gmg_iterations"][tab["workload_column"][wl]][str(n)]
+    a, b, f = datagen.make_batch(wl, n, B, seed=7)
     S = Solver(None, precond="gmg", u="f64", form="nondiv")
     S.setup(dev(a), b)
     u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")

@@ -72,13 +72,17 @@ def test_paper_workload_recipe():
     assert np.allclose(p.b, [np.sin(0.5), np.cos(0.5)]) and np.all(p.f == 1.0)
 
 
+@pytest.mark.parametrize("workload", ["paper_re1e3", "paper_mldata", "paper_re10", "paper_re1e5"])
 @pytest.mark.parametrize("n", [127, 255])
-def test_gmg_iterations_match_the_paper(n):
+def test_gmg_iterations_match_the_paper(n, workload):
     """GMG (levels log2(n+1) - 3, exact 15 x 15 coarsest solve, 3 + 3 sweeps of weight 0.67)
-    on the paper's problems: within 15 % of the printed mean iteration count.  (At 31 and 63 the
-    oracle needs 12 and 15 iterations against the printed 16.7 and 19.2.)"""
-    want = json.load(open(GOLDEN))["gmg_iterations"][str(n)]
-    p = datagen.make_problem("paper_re1e3", n, 0, 0)
+    on the paper's problems, for the coefficient distributions of Appendix B.1 (white noise with
+    Re = 1000, 10, 1e5, and the multi-level data of Alg. 4): within 15 % of the printed mean
+    iteration count.  (At 31 and 63 the oracle needs 12 and 15 iterations on white noise
+    against the printed 16.7 and 19.2.)"""
+    tab = json.load(open(GOLDEN))["appendix_b1"]
+    want = tab["gmg_iterations"][tab["workload_column"][workload]][str(n)]
+    p = datagen.make_problem(workload, n, 0, 0)
     G = gmg.GMG(p.a, p.b, omega=0.67, form="nondiv")
     u, st, it, rho, _ = G.solve(p.f, 1e-8, 200)
     assert st == 0
