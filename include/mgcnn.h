@@ -113,10 +113,13 @@ typedef struct {
   int gmg_sweeps;   /* GMG only: sweeps before and after the coarse correction, 1..4 (default 3) */
   float gmg_omega;  /* GMG only: weighted-Jacobi weight, in (0, 2) (default 0.67) */
   int op_form;      /* MGCNN_OP_DIV (default) or MGCNN_OP_NONDIV: the operator of every call */
-  int deflate;      /* FGMRES only: 0 = plain restarts; k in 1..32 (and < restart) = deflated restarts:
-                       each restart keeps the k directions in which the preconditioned operator
-                       of the finished cycle is smallest (right singular vectors of its
-                       Hessenberg matrix) as the first k basis vectors of the next cycle */
+  int deflate;      /* FGMRES only: 0 = plain restarts; k in 1..32 with 2k <= restart = deflated
+                       restarts: each restart keeps the k directions in which the preconditioned
+                       operator of the finished cycle is smallest (right singular vectors of its
+                       Hessenberg matrix) as the first k basis vectors of the next cycle.  The
+                       bound on k leaves every cycle at least as many new Krylov vectors as kept
+                       ones (with only a few new ones per cycle the iteration can stagnate);
+                       mgcnn_create rejects a larger k (MGCNN_E_ARG) */
   int levels;       /* network only: levels of the setup and solve networks.  0 (default) =
                        log2(n+1), coarsest grid 1 x 1; a negative value -d = log2(n+1) - d (-1 is
                        the count Sec. 4.1 uses: 4, 5, 6, ... levels for 31, 63, 127, ..., coarsest

@@ -345,7 +345,9 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (!(o.gmg_omega > 0.f && o.gmg_omega < 2.f)) return MGCNN_E_ARG;
   if (o.op_form != MGCNN_OP_DIV && o.op_form != MGCNN_OP_NONDIV) return MGCNN_E_ARG;
   if (o.deflate < 0 || o.deflate > 32) return MGCNN_E_ARG;
-  if (o.method == MGCNN_METHOD_FGMRES && o.deflate > 0 && o.deflate >= o.restart) return MGCNN_E_ARG;
+  // at least half of every deflated cycle must be new Krylov vectors: with fewer, a cycle adds
+  // too little to its kept directions and the restarted iteration can stagnate
+  if (o.method == MGCNN_METHOD_FGMRES && o.deflate > 0 && 2 * o.deflate > o.restart) return MGCNN_E_ARG;
   if (o.levels < -11 || o.levels > 12) return MGCNN_E_ARG;
   if (o.up_post != 0 && o.up_post != 1) return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();

@@ -80,3 +80,15 @@ def test_default_options_and_option_checks(lib):
         lib.mgcnn_default_opts(ctypes.byref(bad))
         setattr(bad, field, value)
         assert lib.mgcnn_create(ctypes.byref(h), ctypes.byref(bad), None, None) == -1, field
+
+
+def test_create_rejects_deflation_beyond_half_the_restart(lib):
+    """Deflated FGMRES keeps k directions per restart and needs 2k <= restart (at least as many
+    new Krylov vectors per cycle as kept ones); invalid options fail before any device call."""
+    from paper_2312_11093_amd import mgcnn
+    h = ctypes.c_void_p()
+    for restart, k in ((9, 5), (8, 8), (20, 11), (63, 32)):
+        bad = mgcnn.mgcnn_opts()
+        lib.mgcnn_default_opts(ctypes.byref(bad))
+        bad.method, bad.restart, bad.deflate = 1, restart, k
+        assert lib.mgcnn_create(ctypes.byref(h), ctypes.byref(bad), None, None) == -1, (restart, k)

@@ -175,3 +175,28 @@ def test_fgmres_deflated_restarts(precond, n, B, restart, kd):
     assert its[kd] < its[0], its
     with pytest.raises(M.MGCNNError):
         Solver(w, precond=precond, method="fgmres", restart=8, deflate=8)
+    with pytest.raises(M.MGCNNError):
+        Solver(w, precond=precond, method="fgmres", restart=9, deflate=5)
+
+
+@pytest.mark.parametrize("precond", ["network", "gmg"])
+@pytest.mark.parametrize("n", [3, 7, 15, 31])
+def test_deflation_edge_sizes(n, precond):
+    """Deflated restarts at the edge of their range: k = restart / 2 (the largest k the options
+    allow) on tiny grids (3^2 has only 9 unknowns, fewer than the basis), where cycles end early
+    on an exact solution or a numerically dependent basis; every problem still reaches 1e-10
+    and the oracle agrees."""
+    say("deflation edge", n, precond)
+    B = 3
+    a, b, f = datagen.make_batch("mixture127", n, B, seed=23)
+    w = vcycle_weights() if precond == "network" else None
+    S = Solver(w, precond=precond, state="f32", u="f64", method="fgmres", restart=9, gs_passes=1,
+               deflate=4)
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(f), u, 1e-10, 2000)
+    say("  iters", list(it))
+    assert st == M.OK and (ps == 0).all()
+    for p in range(B):
+        assert osv.relres(a[p], b[p], f[p], u[p].cpu().numpy()) <= 1e-10 * (1 + 1e-5)
+    S.close()
