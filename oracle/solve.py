@@ -47,6 +47,13 @@ class Solver:
     def correction(self, r):
         return net.vcycle(self.P, self.s, r / self.D, up_post=self.up_post)
 
+    def pcg_correction(self, r):
+        """The network as a symmetric preconditioner: D^-1/2 B(D^-1/2 r).  With B symmetric (the
+        symmetric variant of Sec. 3.3) this map is symmetric; for a constant diagonal it equals
+        the correction B(r / D) of Eq. (1)."""
+        h = 1.0 / np.sqrt(self.D)
+        return h * net.vcycle(self.P, self.s, h * r, up_post=self.up_post)
+
     def step(self, f, u):
         """One iteration u + B((f - A u)/D)."""
         return u + self.correction(self.residual(f, u))
@@ -89,6 +96,54 @@ def stationary(it, f, tol: float, maxit: int, u0=None):
         if not math.isfinite(rho) or rho > DIVERGENCE_LIMIT:
             return u, DIVERGED, k, rho, hist
         u = u + it.correction(r)
+        k += 1
+
+
+def pcg(apply_A, precond, f, tol: float, maxit: int, u0=None):
+    """Preconditioned conjugate gradients for a symmetric positive definite A with a symmetric
+    positive definite preconditioner M (the network or a V-cycle as preconditioner of a Krylov
+    method, Sec. 2.2; the short recurrence that a symmetric network allows, Sec. 3.3), in f64:
+
+        r_0 = f - A u_0,  z_0 = M r_0,  p_0 = z_0,
+        alpha_k = (r_k, z_k) / (p_k, A p_k),  u_{k+1} = u_k + alpha_k p_k,
+        r_{k+1} = r_k - alpha_k A p_k,  z_{k+1} = M r_{k+1},
+        beta_k = (r_{k+1}, z_{k+1}) / (r_k, z_k),  p_{k+1} = z_{k+1} + beta_k p_k.
+
+    ``apply_A(x)`` and ``precond(r)`` are callables.  The stopping rule is that of
+    ``stationary`` on the true residual f - A u_k (iters = k preconditioner applications
+    before u_k); (p, A p) <= 0 or (r, z) <= 0 is a breakdown and returns DIVERGED.  Returns
+    (u, status, iters, relres, history)."""
+    f = np.asarray(f, dtype=np.float64)
+    nf = math.sqrt(float(np.sum(f * f)))
+    if nf == 0.0:
+        return np.zeros_like(f), OK, 0, 0.0, [0.0]
+    u = np.zeros_like(f) if u0 is None else np.asarray(u0, dtype=np.float64).copy()
+    r = f - apply_A(u)
+    hist = []
+    k = 0
+    p = rz = None
+    while True:
+        rho = math.sqrt(float(np.sum((f - apply_A(u)) ** 2))) / nf
+        hist.append(rho)
+        if rho <= tol:
+            return u, OK, k, rho, hist
+        if k == maxit:
+            return u, NOT_CONVERGED, k, rho, hist
+        if not math.isfinite(rho) or rho > DIVERGENCE_LIMIT:
+            return u, DIVERGED, k, rho, hist
+        z = precond(r)
+        rz_new = float(np.sum(r * z))
+        if not rz_new > 0.0:
+            return u, DIVERGED, k, rho, hist
+        p = z.copy() if p is None else z + (rz_new / rz) * p
+        rz = rz_new
+        q = apply_A(p)
+        pq = float(np.sum(p * q))
+        if not pq > 0.0:
+            return u, DIVERGED, k, rho, hist
+        alpha = rz / pq
+        u = u + alpha * p
+        r = r - alpha * q
         k += 1
 
 
