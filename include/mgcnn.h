@@ -82,7 +82,24 @@ enum {
 /* Outer method of mgcnn_solve. */
 enum {
   MGCNN_METHOD_STATIONARY = 0,  /* u += B((f - A u)/D), Sec. 2.2 Eq. (1) */
-  MGCNN_METHOD_FGMRES = 1       /* restarted flexible GMRES, B((.)/D) as right preconditioner (Sec. 2.2) */
+  MGCNN_METHOD_FGMRES = 1,      /* restarted flexible GMRES, B((.)/D) as right preconditioner (Sec. 2.2) */
+  MGCNN_METHOD_PCG = 2          /* preconditioned conjugate gradients, the short recurrence that a
+                                   symmetric operator and preconditioner allow (Sec. 2.2; the
+                                   symmetric variant, Sec. 3.3).  Needs b = 0 and the divergence
+                                   form (A symmetric positive definite; mgcnn_solve returns
+                                   MGCNN_E_ARG for a problem with b != 0) and inner_steps = 1; the
+                                   preconditioner is the GMG V-cycle, or the network with up_post = 1
+                                   applied as D^-1/2 B(D^-1/2 r) (symmetric positive semi-definite
+                                   when W_up, W_T and W_out are the adjoints of W_dn, W_R and W_in:
+                                   every level is G^T (I + R^T M_coarse R) G with G the down
+                                   smoother); mgcnn_create rejects the network without up_post.
+                                   The f32 recurrence runs in cycles (an iterative refinement):
+                                   each starts from the f64 true residual f - A u and ends when its
+                                   recurrence residual has dropped by 1e-5, meets the tolerance or
+                                   the step count reaches maxit; the true residual of u then decides
+                                   the stopping rule.  iters counts the steps (u updates).
+                                   (r, z) <= 0 or (p, A p) <= 0 (a preconditioner or weights that
+                                   are not definite) ends the problem with MGCNN_E_DIVERGED */
 };
 
 typedef struct {
@@ -94,7 +111,7 @@ typedef struct {
   int check_every;  /* iterations between host convergence checks in mgcnn_solve (>= 1) */
   int method;       /* MGCNN_METHOD_STATIONARY or MGCNN_METHOD_FGMRES */
   int restart;      /* FGMRES restart length m, 1..63 (Krylov vectors are float32; the true
-                       residual is recomputed in f64 at every restart) */
+                       residual is recomputed in f64 at every restart); not used by PCG */
   int f32_split;    /* MGCNN_F32 state only: 1 = 16->16 convs on bf16 matrix cores with both
                        operands split into three bf16 parts (float32-level products, several
                        times the f32 matrix rate); 0 = float32 matrix instructions */

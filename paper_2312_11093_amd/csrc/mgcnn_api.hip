@@ -334,7 +334,12 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.state_dtype != MGCNN_F32 && o.state_dtype != MGCNN_BF16) return MGCNN_E_ARG;
   if (o.u_dtype != MGCNN_U_F32 && o.u_dtype != MGCNN_U_F64) return MGCNN_E_ARG;
   if (o.check_every < 1) return MGCNN_E_ARG;
-  if (o.method != MGCNN_METHOD_STATIONARY && o.method != MGCNN_METHOD_FGMRES) return MGCNN_E_ARG;
+  if (o.method != MGCNN_METHOD_STATIONARY && o.method != MGCNN_METHOD_FGMRES && o.method != MGCNN_METHOD_PCG)
+    return MGCNN_E_ARG;
+  // conjugate gradients need a symmetric preconditioner: the network only in its symmetric form
+  if (o.method == MGCNN_METHOD_PCG && o.precond == MGCNN_PRECOND_NETWORK && !o.up_post) return MGCNN_E_ARG;
+  if (o.method == MGCNN_METHOD_PCG && (o.op_form != MGCNN_OP_DIV || o.inner_steps != 1))
+    return MGCNN_E_ARG;
   if (o.f32_split != 0 && o.f32_split != 1) return MGCNN_E_ARG;
   if (o.s_bf16 != 0 && o.s_bf16 != 1) return MGCNN_E_ARG;
   if (o.inner_steps < 1 || o.inner_steps > 16) return MGCNN_E_ARG;
@@ -452,6 +457,8 @@ int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, in
   if (!(tol > 0.0) || maxit < 0) return fail(c, MGCNN_E_ARG, "solve: need tol > 0 and maxit >= 0");
   if (c->opts.method == MGCNN_METHOD_FGMRES)
     return fgmres_solve(c, f, u, tol, maxit, iters_host, relres_host, status_host);
+  if (c->opts.method == MGCNN_METHOD_PCG)
+    return pcg_solve(c, f, u, tol, maxit, iters_host, relres_host, status_host);
   const bool graph = c->opts.use_graph != 0 && !c->prof;
   hipStream_t user = c->stream;
   if (graph && user == nullptr) {
@@ -639,6 +646,7 @@ void mgcnn_destroy(mgcnn_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
   free_train(c);
   free_krylov(c);
+  free_pcg(c);
   drop_graph(c);
   free_problem(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

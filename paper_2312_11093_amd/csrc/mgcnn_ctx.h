@@ -70,6 +70,18 @@ struct mgcnn_ctx {
     double* coef = nullptr;   // deflation: basis combination coefficients (V, then Z)
   } kr;
 
+  // preconditioned conjugate gradients: r, p, q, z and the diagonal scaling, [B][n][n] each
+  struct Pcg {
+    int n = 0, B = 0;
+    float* vec = nullptr;     // 5 vectors of B * n * n floats: r, p, q, z, dsc
+    float* ones = nullptr;    // B * krylov_vpad(n) ones (input of the diagonal pass)
+    double* partial = nullptr;
+    double* out = nullptr;    // 2 per problem: |r|^2 or (p, A p), then (r, z)
+    double* coef = nullptr;   // 2 per problem: alpha, beta
+    double* unit = nullptr;   // B * KRYLOV_LD ones (the diagonal pass's scale factors)
+    int* lists = nullptr;     // three compact problem lists of B entries each
+  } pcg;
+
   // geometric multigrid preconditioner (opts.precond == MGCNN_PRECOND_GMG), per level l
   struct Gmg {
     int levels = 0;
@@ -130,6 +142,9 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* list, int count, bool a
 int forward_record(mgcnn_ctx* c, const float* f, float* u, int K);
 void free_train(mgcnn_ctx* c);
 void free_krylov(mgcnn_ctx* c);
+void free_pcg(mgcnn_ctx* c);
+int pcg_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int* iters_host,
+              double* relres_host, int* status_host);
 int fgmres_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int* iters_host,
                  double* relres_host, int* status_host);
 

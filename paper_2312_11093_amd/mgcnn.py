@@ -172,7 +172,7 @@ class Solver:
         o.u_dtype = {"f32": U_F32, "f64": U_F64}[u]
         o.use_graph = int(bool(use_graph))
         o.check_every = int(check_every)
-        o.method = {"stationary": 0, "fgmres": 1}[method]
+        o.method = {"stationary": 0, "fgmres": 1, "pcg": 2}[method]
         o.restart = int(restart)
         o.f32_split = int(bool(f32_split))
         o.s_bf16 = int(bool(s_bf16))
@@ -345,7 +345,7 @@ class GroupSolver:
         self._L.mgcnn_default_opts(ctypes.byref(o))
         o.state_dtype = {"f32": F32, "bf16": BF16}[state]
         o.u_dtype = {"f32": U_F32, "f64": U_F64}[u]
-        o.method = {"stationary": 0, "fgmres": 1}[method]
+        o.method = {"stationary": 0, "fgmres": 1, "pcg": 2}[method]
         o.restart = int(restart)
         o.check_every = int(check_every)
         o.f32_split = int(bool(f32_split))

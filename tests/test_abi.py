@@ -92,3 +92,17 @@ def test_create_rejects_deflation_beyond_half_the_restart(lib):
         lib.mgcnn_default_opts(ctypes.byref(bad))
         bad.method, bad.restart, bad.deflate = 1, restart, k
         assert lib.mgcnn_create(ctypes.byref(h), ctypes.byref(bad), None, None) == -1, (restart, k)
+
+
+def test_create_checks_the_pcg_options(lib):
+    """Conjugate gradients: the network preconditioner only in its symmetric form (up_post), the
+    divergence form only, one preconditioner application per step."""
+    from paper_2312_11093_amd import mgcnn
+    h = ctypes.c_void_p()
+    for changes in ({"up_post": 0}, {"op_form": 1}, {"inner_steps": 2}, {"method": 3}):
+        bad = mgcnn.mgcnn_opts()
+        lib.mgcnn_default_opts(ctypes.byref(bad))
+        bad.method, bad.up_post = 2, 1
+        for k, v in changes.items():
+            setattr(bad, k, v)
+        assert lib.mgcnn_create(ctypes.byref(h), ctypes.byref(bad), None, None) == -1, changes
