@@ -143,3 +143,23 @@ def test_pcg_float32_u_and_rejections():
     S.close()
     with pytest.raises(M.MGCNNError):
         Solver(tied_weights(), state="f32", method="pcg")
+
+
+@pytest.mark.parametrize("precond", ["gmg", "network"])
+@pytest.mark.parametrize("n", [3, 7])
+def test_pcg_edge_sizes(n, precond):
+    """Tiny grids (9 and 49 unknowns: the recurrence terminates within n^2 steps in exact
+    arithmetic), a batch of one, and maxit = 0 (no step: the true residual of u = 0 is 1)."""
+    say("pcg edge", n, precond)
+    a, b, f = symmetric_batch("mixture127", n, 1, seed=34)
+    w = tied_weights() if precond == "network" else None
+    S = make_solver(precond, w)
+    S.setup(dev(a), b)
+    u = torch.zeros((1, n, n), dtype=torch.float64, device="cuda")
+    st, it, rr, ps = S.solve(dev(f), u, 1e-10, 0)
+    assert st == M.NOT_CONVERGED and it[0] == 0 and abs(rr[0] - 1.0) <= 1e-12 and not u.any()
+    st, it, rr, ps = S.solve(dev(f), u, 1e-10, 500)
+    S.close()
+    say("  iters", int(it[0]), "relres", float(rr[0]))
+    assert st == M.OK and it[0] <= 3 * n * n
+    assert osv.relres(a[0], b[0], f[0], u[0].cpu().numpy()) <= 1e-10 * (1 + 1e-5)
