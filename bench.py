@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "solves/s to rel-residual 1e-8 (1023², batch 64) vs plain FP32; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFS = 157.3
+BF16_PEAK_TFS = 2500.0
 
 
 def load_weights(spec):
@@ -96,10 +97,30 @@ def measured_traffic_ratio(kind):
         return None
 
 
-def roofline_of(stats):
+def matrix_peak(kind, level, split):
+    """(peak in algorithmic TFLOP/s, arithmetic) of a kernel's matrix instructions.  With f32
+    state: the 16 -> 16 same-size convs run on bf16 MFMA over a k-way bf16 split of both operands
+    (k(k+1)/2 bf16 products per algorithmic product: 6 for the three-way split, 3 for the two-way
+    split of the finest down smoother when split = 2), so their algorithmic peak is the dense bf16
+    peak / that count; the restriction, the prolongation and the finest down smoother at split
+    = 1 use f32 MFMA.  split < 0: bf16 state, every conv on plain bf16 MFMA."""
+    if split < 0:
+        return BF16_PEAK_TFS, "bf16 MFMA"
+    if split == 0:
+        return FP32_PEAK_TFS, "f32 MFMA"
+    if kind == "smooth_in":
+        return (BF16_PEAK_TFS / 3, "bf16 MFMA, two-way split (3 products)") if split == 2 else (
+            FP32_PEAK_TFS, "f32 MFMA")
+    if kind in ("smooth_down", "smooth_up"):
+        return BF16_PEAK_TFS / 6, "bf16 MFMA, three-way split (6 products)"
+    return FP32_PEAK_TFS, "f32 MFMA"
+
+
+def roofline_of(stats, split=1):
     """Per-kind time shares and the roofline of the (kind, level) entry with the most time.
-    A kernel whose algorithmic intensity (flops / HBM bytes) is above the fp32 ridge point
-    (157.3 TFLOP/s / 8 TB/s) is judged against the fp32 matrix peak, otherwise against HBM."""
+    A kernel whose algorithmic intensity (flops / HBM bytes) is above the ridge point of its
+    matrix arithmetic (``matrix_peak``) / 8 TB/s is judged against that matrix peak, otherwise
+    against HBM."""
     by_kind = {}
     for s_ in stats:
         by_kind[s_["kind"]] = by_kind.get(s_["kind"], 0.0) + s_["ms_total"]
@@ -108,7 +129,8 @@ def roofline_of(stats):
     gbs = top["bytes_per_launch"] / (avg_ms / 1000.0) / 1e9
     tfs = top["flops_per_launch"] / (avg_ms / 1000.0) / 1e12
     intensity = top["flops_per_launch"] / max(top["bytes_per_launch"], 1.0)
-    ridge = FP32_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    mpeak, arith = matrix_peak(top["kind"], top["level"], split)
+    ridge = mpeak * 1e12 / (HBM_PEAK_GBS * 1e9)
     what = f"{top['kind']} (level {top['level']}, {top['launches']} launches, {avg_ms:.3f} ms avg)"
     ratio = measured_traffic_ratio(top["kind"]) if top["level"] == 0 else None
     traffic = round(ratio * top["bytes_per_launch"]) if ratio is not None else None
@@ -116,14 +138,15 @@ def roofline_of(stats):
                     "calibrated on a 1 GiB streaming kernel, as a ratio to the algorithmic bytes "
                     "(profiles/pmc_finest_level_64x1023_f32.md)") if traffic is not None else None
     if intensity > ridge:
-        roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": FP32_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": round(tfs / FP32_PEAK_TFS, 4), "traffic": traffic, "kernel": what,
+        roof = {"bound": "mfma", "achieved": round(tfs, 2), "peak": round(mpeak, 1), "unit": "TFLOP/s",
+                "frac": round(tfs / mpeak, 4), "traffic": traffic, "kernel": what, "arithmetic": arith,
                 "flops_per_launch": top["flops_per_launch"], "bytes_per_launch": top["bytes_per_launch"],
                 "traffic_note": traffic_note,
                 "intensity_flop_per_byte": round(intensity, 2), "hbm_gbs": round(gbs, 1)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": what,
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": what, "arithmetic": arith,
+                "matrix_peak_tflops": round(mpeak, 1), "achieved_tflops": round(tfs, 2),
                 "bytes_per_launch": top["bytes_per_launch"], "traffic_note": traffic_note,
                 "intensity_flop_per_byte": round(intensity, 2)}
     total = sum(by_kind.values())
@@ -148,6 +171,9 @@ def main():
     ap.add_argument("--gs-passes", type=int, default=1, choices=[1, 2],
                     help="classical Gram-Schmidt passes per Arnoldi step")
     ap.add_argument("--state", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--f32-split", type=int, default=2, choices=[0, 1, 2],
+                    help="f32 state: 0 = f32 MFMA, 1 = three-way bf16 split of the 16->16 convs, "
+                         "2 = as 1 with a two-way split in the finest down smoother")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=10000)
     ap.add_argument("--check-every", type=int, default=4)
@@ -182,7 +208,8 @@ def main():
     def make(state, use_graph):
         return Solver(weights, state=state, u="f64", check_every=args.check_every,
                       use_graph=use_graph and args.method == "stationary", method=args.method,
-                      restart=args.restart, gs_passes=args.gs_passes, deflate=dfl)
+                      restart=args.restart, gs_passes=args.gs_passes, deflate=dfl,
+                      f32_split=args.f32_split)
 
     dfl = args.deflate if args.method == "fgmres" else 0
     S = make(args.state, not args.no_graph)
@@ -223,7 +250,7 @@ def main():
 
     # time of one batched stationary iteration (residual + network + update), weight independent
     KI = 10
-    S2 = Solver(weights, state=args.state, u="f64")
+    S2 = Solver(weights, state=args.state, u="f64", f32_split=args.f32_split)
     S2.setup(da, b)
     u.zero_()
     S2.forward(df, u, 2)
@@ -241,7 +268,7 @@ def main():
     S.profile_begin()
     S.solve(df, u, args.tol, args.maxit)
     stats = S.profile_end()
-    roof, kernel_share, prof_ms, level0 = roofline_of(stats)
+    roof, kernel_share, prof_ms, level0 = roofline_of(stats, args.f32_split if args.state == "f32" else -1)
     S.close()
     print("[bench] profiled pass done", file=sys.stderr, flush=True)
 
@@ -349,7 +376,8 @@ def main():
                    "restart": args.restart if args.method == "fgmres" else None,
                    "gs_passes": args.gs_passes if args.method == "fgmres" else None,
                    "deflate": dfl if args.method == "fgmres" else None,
-                   "state": args.state, "u": "f64", "weights": wsrc, "parallelism": "single GPU"},
+                   "state": args.state, "f32_split": args.f32_split if args.state == "f32" else None,
+                   "u": "f64", "weights": wsrc, "parallelism": "single GPU"},
         "converged": converged, "mean_iters": mean_iters, "max_iters": int(np.max(its[-1])),
         "ms_per_stationary_iteration": round(iter_ms, 3),
         "oracle_relres_sampled": check,

@@ -114,7 +114,11 @@ typedef struct {
                        residual is recomputed in f64 at every restart); not used by PCG */
   int f32_split;    /* MGCNN_F32 state only: 1 = 16->16 convs on bf16 matrix cores with both
                        operands split into three bf16 parts (float32-level products, several
-                       times the f32 matrix rate); 0 = float32 matrix instructions */
+                       times the f32 matrix rate); 2 = as 1, but the finest down smoother (with
+                       the reChannel-in conv folded in) splits into two bf16 parts: products to
+                       about 2^-16 relative, half its f32 matrix time (a preconditioner setting:
+                       the solve network is then not float32-exact); 0 = float32 matrix
+                       instructions */
   int s_bf16;       /* MGCNN_F32 state only: 1 = keep the setup tensors s_l in bf16 (rounded once
                        after the setup network; the network stays a fixed linear operator, so a
                        solve still reaches its tolerance), halving their HBM traffic; 0 = f32 */

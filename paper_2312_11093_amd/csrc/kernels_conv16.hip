@@ -148,6 +148,53 @@ struct Frag<ST_F32X> {
   }
 };
 
+// Two-way bf16 split: x = hi + lo + e with |e| <= 2^-17 |x| (hi rounded to nearest, the
+// difference exact in float32, lo its bf16 rounding).
+__device__ __forceinline__ void split2_4(float4 v, uint2& H, uint2& L) {
+  H = make_uint2(pack_bf16x2(v.x, v.y), pack_bf16x2(v.z, v.w));
+  L = make_uint2(pack_bf16x2(v.x - __uint_as_float(H.x << 16), v.y - __uint_as_float(H.x & 0xffff0000u)),
+                 pack_bf16x2(v.z - __uint_as_float(H.y << 16), v.w - __uint_as_float(H.y & 0xffff0000u)));
+}
+
+// f32 state on bf16 matrix cores with a two-way split: two bf16 LDS planes (hi, lo: the bytes
+// of one float32 plane, so the tile and the occupancy of the f32 path are kept) and per tap
+// three 16x16x16 MFMAs hi.lo + lo.hi + hi.hi.  The dropped lo.lo term and the lo roundings
+// leave each product within about 2^-16 of float32: enough for a preconditioner, whose
+// rounding a flexible Krylov method absorbs, at about half the matrix time of f32 MFMA.
+template <>
+struct Frag<ST_F32X2> {
+  typedef float elem;
+  typedef uint16_t lds_t;
+  static constexpr int PLANES = 2;
+  s4v wh[9], wl[9];
+  __device__ void load_w(const float* W, bool transposed) {
+    const int l = threadIdx.x & 63;
+    const int o = l & 15, g = l >> 4;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 4 * g + e;
+        v[e] = transposed ? W[(c * C + o) * 9 + t] : W[(o * C + c) * 9 + t];
+      }
+      uint2 H, L;
+      split2_4(make_float4(v[0], v[1], v[2], v[3]), H, L);
+      wh[t] = __builtin_bit_cast(s4v, H);
+      wl[t] = __builtin_bit_cast(s4v, L);
+    }
+  }
+  __device__ __forceinline__ f4v mma(int t, const lds_t* lds_px, f4v acc, int pstride) const {
+    const int g = (threadIdx.x & 63) >> 4;
+    const s4v bh = __builtin_bit_cast(s4v, *reinterpret_cast<const uint2*>(lds_px + 4 * g));
+    const s4v bl = __builtin_bit_cast(s4v, *reinterpret_cast<const uint2*>(lds_px + pstride + 4 * g));
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wh[t], bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wl[t], bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wh[t], bh, acc, 0, 0, 0);
+    return acc;
+  }
+};
+
 // Load 4 consecutive channels (group g) of pixel `pix` of a channel-last tensor as floats.
 __device__ __forceinline__ float4 ld4(const float* X, int pix, int g) {
   return reinterpret_cast<const float4*>(X)[pix * 4 + g];
@@ -196,6 +243,15 @@ struct Chunk<ST_F32X> : Chunk<ST_F32> {
     *reinterpret_cast<uint2*>(px + 4 * h) = H;
     *reinterpret_cast<uint2*>(px + pstride + 4 * h) = M;
     *reinterpret_cast<uint2*>(px + 2 * pstride + 4 * h) = L;
+  }
+};
+template <>
+struct Chunk<ST_F32X2> : Chunk<ST_F32> {
+  static __device__ __forceinline__ void to_lds(uint16_t* px, int h, T v, int pstride) {
+    uint2 H, L;
+    split2_4(v, H, L);
+    *reinterpret_cast<uint2*>(px + 4 * h) = H;
+    *reinterpret_cast<uint2*>(px + pstride + 4 * h) = L;
   }
 };
 template <>
@@ -521,7 +577,7 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
   constexpr int RPT = (RR * RC + 255) / 256;             // rt values per thread
   constexpr int PSTR = K::NPIX * PS;                     // LDS plane stride
   __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];  // z = s . x1
-  constexpr bool SKIP_MMA = ST == ST_F32;                // skip term on the matrix cores
+  constexpr bool SKIP_MMA = ST == ST_F32 || ST == ST_F32X2;   // skip term on the matrix cores
   __shared__ __attribute__((aligned(16))) E lx[SKIP_MMA ? 4 : K::TH * K::TW * PS];  // x1 at the outputs
   __shared__ float lrt[RR * RC];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
@@ -590,11 +646,11 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
       x1[c] = acc;
       z[c] = acc * sv[r][c];
     }
-    if constexpr (ST == ST_F32X) {
+    if constexpr (ST == ST_F32X || ST == ST_F32X2) {
 #pragma unroll
       for (int h = 0; h < 4; ++h)
-        Chunk<ST_F32X>::to_lds(&lds[pix * PS], h, make_float4(z[4 * h], z[4 * h + 1], z[4 * h + 2], z[4 * h + 3]),
-                               PSTR);
+        Chunk<ST>::to_lds(&lds[pix * PS], h, make_float4(z[4 * h], z[4 * h + 1], z[4 * h + 2], z[4 * h + 3]),
+                          PSTR);
     } else {
       store16(&lds[pix * PS], z);
     }
@@ -712,6 +768,9 @@ void launch_smooth_in(StateType st_, const float* rt, const void* s, const float
   if (st_ == ST_F32 || st_ == ST_F32X) {
     if (s_bf16) smooth_in_launch<ST_F32, true>(rt, s, Win, W, y, m, B, active, st);
     else smooth_in_launch<ST_F32>(rt, s, Win, W, y, m, B, active, st);
+  } else if (st_ == ST_F32X2) {
+    if (s_bf16) smooth_in_launch<ST_F32X2, true>(rt, s, Win, W, y, m, B, active, st);
+    else smooth_in_launch<ST_F32X2>(rt, s, Win, W, y, m, B, active, st);
   } else {
     smooth_in_launch<ST_BF16>(rt, s, Win, W, y, m, B, active, st);
   }

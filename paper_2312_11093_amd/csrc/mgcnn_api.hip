@@ -232,8 +232,8 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool
     if (l == 0) {
       // finest level: reChannel-in folded into the down smoother
       Prof p(c, MGCNN_K_SMOOTH_IN, 0, nodes(0) * (4.0 + S + SS), nodes(0) * (FL_SMOOTH + FL_IN));
-      launch_smooth_in(st, c->d_rt, c->s[0], c->W(c->off.solve_in), c->W(c->off.smooth_down), c->xdn[0],
-                       c->nl[0], B, active, s, sb);
+      launch_smooth_in(st == ST_F32X && c->opts.f32_split == 2 ? ST_F32X2 : st, c->d_rt, c->s[0],
+                       c->W(c->off.solve_in), c->W(c->off.smooth_down), c->xdn[0], c->nl[0], B, active, s, sb);
     } else {
       Prof p(c, MGCNN_K_SMOOTH_DOWN, l, nodes(l) * (2.0 * S + SS), nodes(l) * FL_SMOOTH);
       launch_conv16(CM_SMOOTH, st, c->xin[l], c->s[l], c->W(c->off.smooth_down), nullptr, c->xdn[l],
@@ -340,7 +340,7 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.method == MGCNN_METHOD_PCG && o.precond == MGCNN_PRECOND_NETWORK && !o.up_post) return MGCNN_E_ARG;
   if (o.method == MGCNN_METHOD_PCG && (o.op_form != MGCNN_OP_DIV || o.inner_steps != 1))
     return MGCNN_E_ARG;
-  if (o.f32_split != 0 && o.f32_split != 1) return MGCNN_E_ARG;
+  if (o.f32_split < 0 || o.f32_split > 2) return MGCNN_E_ARG;
   if (o.s_bf16 != 0 && o.s_bf16 != 1) return MGCNN_E_ARG;
   if (o.inner_steps < 1 || o.inner_steps > 16) return MGCNN_E_ARG;
   if (o.gs_passes != 1 && o.gs_passes != 2) return MGCNN_E_ARG;

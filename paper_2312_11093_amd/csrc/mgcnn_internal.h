@@ -15,8 +15,9 @@ constexpr int NUM_SETUP_LAYERS = 4;   // tanh ResNet layers of the setup network
 //   ST_F32   float32 storage, float32 MFMA (16x16x4)
 //   ST_BF16  bf16 storage, bf16 MFMA with f32 accumulation
 //   ST_F32X  float32 storage, bf16 MFMA on a three-way bf16 split of both operands
+//   ST_F32X2 float32 storage, bf16 MFMA on a two-way bf16 split (finest down smoother only)
 //            (float32-level products at the bf16 matrix rate)
-enum StateType : int { ST_F32 = 0, ST_BF16 = 1, ST_F32X = 2 };
+enum StateType : int { ST_F32 = 0, ST_BF16 = 1, ST_F32X = 2, ST_F32X2 = 3 };
 
 // Offsets (in floats) of every parameter tensor inside the flat weight vector.
 struct WeightOffsets {

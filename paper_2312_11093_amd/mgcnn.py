@@ -154,7 +154,7 @@ class Solver:
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", use_graph: bool = False,
                  check_every: int = 4, stream=None, method: str = "stationary", restart: int = 30,
-                 f32_split: bool = True, s_bf16: bool = False, inner_steps: int = 1,
+                 f32_split: bool | int = True, s_bf16: bool = False, inner_steps: int = 1,
                  gs_passes: int = 2, precond: str = "network", gmg_levels: int = 0,
                  gmg_sweeps: int = 3, gmg_omega: float = 0.67, form: str = "div", deflate: int = 0,
                  levels: int = 0, up_post: bool = False):
@@ -174,7 +174,7 @@ class Solver:
         o.check_every = int(check_every)
         o.method = {"stationary": 0, "fgmres": 1, "pcg": 2}[method]
         o.restart = int(restart)
-        o.f32_split = int(bool(f32_split))
+        o.f32_split = 2 if f32_split == 2 else int(bool(f32_split))
         o.s_bf16 = int(bool(s_bf16))
         o.inner_steps = int(inner_steps)
         o.gs_passes = int(gs_passes)
@@ -335,7 +335,7 @@ class GroupSolver:
     problem set per size on its own stream, buckets solved concurrently."""
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", method: str = "stationary",
-                 restart: int = 30, check_every: int = 4, f32_split: bool = True, s_bf16: bool = False,
+                 restart: int = 30, check_every: int = 4, f32_split: bool | int = True, s_bf16: bool = False,
                  inner_steps: int = 1, gs_passes: int = 2, stream=None, precond: str = "network",
                  gmg_levels: int = 0, gmg_sweeps: int = 3, gmg_omega: float = 0.67,
                  form: str = "div", deflate: int = 0, levels: int = 0, up_post: bool = False):
@@ -348,7 +348,7 @@ class GroupSolver:
         o.method = {"stationary": 0, "fgmres": 1, "pcg": 2}[method]
         o.restart = int(restart)
         o.check_every = int(check_every)
-        o.f32_split = int(bool(f32_split))
+        o.f32_split = 2 if f32_split == 2 else int(bool(f32_split))
         o.s_bf16 = int(bool(s_bf16))
         o.inner_steps = int(inner_steps)
         o.gs_passes = int(gs_passes)

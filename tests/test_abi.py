@@ -75,7 +75,8 @@ def test_default_options_and_option_checks(lib):
     h = ctypes.c_void_p()
     for field, value in (("precond", 2), ("gmg_sweeps", 0), ("gmg_sweeps", 5), ("gmg_levels", -1),
                          ("op_form", 2), ("deflate", -1), ("deflate", 33), ("levels", -12), ("levels", 13), ("up_post", 2),
-                         ("gmg_omega", 0.0), ("gmg_omega", 2.0), ("gs_passes", 3)):
+                         ("gmg_omega", 0.0), ("gmg_omega", 2.0), ("gs_passes", 3), ("f32_split", 3),
+                         ("f32_split", -1)):
         bad = mgcnn.mgcnn_opts()
         lib.mgcnn_default_opts(ctypes.byref(bad))
         setattr(bad, field, value)

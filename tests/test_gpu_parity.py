@@ -105,6 +105,44 @@ def test_apply_network(n, B, split):
     S.close()
 
 
+# the two-way split leaves each product of the finest down smoother within about 2^-16 of
+# float32 (dropped lo.lo term and lo roundings); sums of 144 such products with cancellation
+# and the layers after it keep the network output within a few times that
+SPLIT2_TOL = 1e-4
+
+
+@pytest.mark.parametrize("n,B", [(3, 1), (15, 2), (63, 2), (255, 2)])
+def test_apply_network_two_way_split(n, B):
+    """f32_split = 2: the finest down smoother on a two-way bf16 split (three bf16 MFMAs per
+    tap) matches the oracle's network to the split's accuracy; a solve with it still reaches
+    1e-8 on the oracle's FP64 residual (the flexible outer method absorbs the rounding)."""
+    say("apply two-way split", n, B)
+    a, b, f = batch("mixture127", n, B, seed=3)
+    w = datagen.xavier_weights(16, 1)
+    rng = np.random.default_rng(n)
+    r = rng.standard_normal((B, n, n)).astype(np.float32)
+    S = Solver(w, state="f32", f32_split=2)
+    S.setup(dev(a), b)
+    z = S.apply(dev(r)).cpu().numpy()
+    S.close()
+    for p in range(B):
+        exp = osv.Solver(w, a[p], b[p]).correction(r[p].astype(np.float64))
+        say("  rel err", rel(z[p], exp))
+        assert rel(z[p], exp) <= SPLIT2_TOL, (p, rel(z[p], exp))
+    if n >= 15:
+        from paper_2312_11093_amd.handbuilt import vcycle_weights
+        S = Solver(vcycle_weights(), state="f32", u="f64", f32_split=2, method="fgmres", restart=63,
+                   gs_passes=1, deflate=8)
+        S.setup(dev(a), b)
+        u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+        st, it, rr, ps = S.solve(dev(f), u, 1e-8, 4000)
+        S.close()
+        say("  fgmres iters", list(it))
+        assert st == M.OK
+        for p in range(B):
+            assert osv.relres(a[p], b[p], f[p], u[p].cpu().numpy()) <= 1e-8 * (1 + 1e-6)
+
+
 @pytest.mark.parametrize("n,levels", [(31, -1), (63, -1), (127, -2), (63, 3), (15, 1)])
 def test_apply_network_fewer_levels(n, levels):
     """opts.levels: the networks cut short (negative = levels below log2(n+1); -1 is the count
