@@ -163,3 +163,25 @@ def test_pcg_edge_sizes(n, precond):
     say("  iters", int(it[0]), "relres", float(rr[0]))
     assert st == M.OK and it[0] <= 3 * n * n
     assert osv.relres(a[0], b[0], f[0], u[0].cpu().numpy()) <= 1e-10 * (1 + 1e-5)
+
+
+def test_pcg_group_of_uneven_sizes():
+    """The group API (one batched problem set per size, concurrent streams) with conjugate
+    gradients: problems of 31^2, 63^2 and 127^2 with b = 0 all reach 1e-9 on the oracle's
+    FP64 residual."""
+    from paper_2312_11093_amd import GroupSolver
+    say("pcg group")
+    sizes = [31, 63, 127, 31, 63]
+    probs = [datagen.make_problem("mixture127", n, i, 35) for i, n in enumerate(sizes)]
+    a = [dev(p.a) for p in probs]
+    f = [dev(p.f) for p in probs]
+    b = np.zeros((len(sizes), 2), np.float32)
+    u = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for n in sizes]
+    G = GroupSolver(None, precond="gmg", state="f32", u="f64", method="pcg")
+    G.setup(a, b)
+    st, it, rr, ps = G.solve(f, u, 1e-9, 1000)
+    G.close()
+    say("  iters", list(it))
+    assert st == M.OK and (np.asarray(ps) == 0).all()
+    for i, p in enumerate(probs):
+        assert osv.relres(p.a, b[i], p.f, u[i].cpu().numpy()) <= 1e-9 * (1 + 1e-5)
