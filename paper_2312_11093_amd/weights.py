@@ -40,3 +40,24 @@ def embed_channels(w, C: int | None = None) -> np.ndarray:
         out.append(t.ravel())
         off += size
     return np.concatenate(out)
+
+
+def symmetric_variant(w) -> np.ndarray:
+    """Flat weights of the symmetric variant of the solve network (Sec. 3.3): the up smoother
+    becomes the adjoint of the down smoother (3x3 taps flipped, channel axes swapped), the
+    transposed-conv prolongation takes the restriction's array and reChannel-out the adjoint of
+    reChannel-in; the setup network and the down path are kept.  With the up smoother applied
+    in its adjoint form (opts.up_post = 1) the network is then symmetric positive semi-definite
+    for any values, so it can precondition conjugate gradients (method PCG)."""
+    w = np.asarray(w, dtype=np.float32).ravel()
+    C = channels_of(w.size)
+    parts, off = {}, 0
+    for name, shape in parameter_shapes(C):
+        size = int(np.prod(shape))
+        parts[name] = w[off:off + size].reshape(shape).copy()
+        off += size
+    adj = lambda t: np.ascontiguousarray(np.flip(t, (2, 3)).transpose(1, 0, 2, 3))
+    parts["smooth_up"] = adj(parts["smooth_down"])
+    parts["prolong"] = parts["restrict"].copy()
+    parts["solve_out"] = adj(parts["solve_in"])
+    return np.concatenate([parts[name].ravel() for name, _ in parameter_shapes(C)]).astype(np.float32)

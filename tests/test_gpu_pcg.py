@@ -10,7 +10,6 @@ import pytest
 
 import datagen
 from oracle import gmg as ogmg
-from oracle import network as onet
 from oracle import operator as oop
 from oracle import solve as osv
 
@@ -22,6 +21,7 @@ if not torch.cuda.is_available():
 
 from paper_2312_11093_amd import Solver  # noqa: E402
 from paper_2312_11093_amd import mgcnn as M  # noqa: E402
+from paper_2312_11093_amd.weights import symmetric_variant  # noqa: E402
 
 
 def say(*a):
@@ -34,14 +34,10 @@ def dev(x, dtype=torch.float32):
 
 
 def tied_weights(C=16, seed=6):
-    """Xavier weights with W_up, W_T, W_out the adjoints of W_dn, W_R, W_in: with the up
-    smoother x + s . (W_up * x) the network is symmetric positive semi-definite."""
-    P = onet.unpack_weights(datagen.xavier_weights(C, seed).astype(np.float64), C)
-    adj = lambda W: np.flip(W, (2, 3)).transpose(1, 0, 2, 3).copy()
-    P["W_up"] = adj(P["W_dn"])
-    P["W_T"] = P["W_R"].copy()
-    P["W_out"] = adj(P["W_in"])
-    return onet.pack_weights(P, C).astype(np.float32)
+    """Xavier weights with W_up, W_T, W_out the adjoints of W_dn, W_R, W_in (the library's
+    helper; checked against the oracle-side construction in test_weights_symmetric): with the
+    up smoother x + s . (W_up * x) the network is symmetric positive semi-definite."""
+    return symmetric_variant(datagen.xavier_weights(C, seed))
 
 
 def symmetric_batch(workload, n, B, seed):
