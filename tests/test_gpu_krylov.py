@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import datagen
+from parity_util import assert_close
 from oracle import solve as osv
 
 torch = pytest.importorskip("torch")
@@ -47,7 +48,7 @@ def test_stationary_handbuilt_matches_oracle():
         assert ost == osv.OK
         assert abs(int(it[p]) - oit) <= 1, (p, it[p], oit)
         up = u[p].cpu().numpy()
-        assert np.linalg.norm(up - ou) <= 1e-6 * np.linalg.norm(ou)
+        assert_close(up, ou, 1e-6, f"solution {p}")
         assert osv.relres(a[p], b[p], f[p], up) <= 1e-8
     S.close()
 

@@ -1,7 +1,9 @@
 """GPU parity: the HIP library (through the C-ABI) against the FP64 oracle on the same
 seeded float32 inputs.  Tolerance for the f32 state path: relative error <= 1e-5 on the
 solution at a fixed iteration count; bf16 state: reported, bounded loosely; converged
-solves: oracle-recomputed relative residual <= tol."""
+solves: oracle-recomputed relative residual <= tol.  Every comparison of a field asserts the
+bound both on the relative 2-norm error and element by element (max |gpu - oracle| relative to
+max |oracle|), per problem."""
 import sys
 
 import numpy as np
@@ -11,6 +13,7 @@ import datagen
 from oracle import network as onet
 from oracle import operator as oop
 from oracle import solve as osv
+from parity_util import assert_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -62,7 +65,7 @@ def test_setup_tensors(n, B):
         for l in range(1, L + 1):
             got = S.get_setup_tensor(l)[p].cpu().numpy().astype(np.float64)   # (m, m, 16)
             exp = np.transpose(ref.s[l - 1], (1, 2, 0))
-            assert rel(got, exp) <= F32_TOL, (p, l, rel(got, exp))
+            assert_close(got, exp, F32_TOL, f"problem {p} level {l}")
     S.close()
 
 
@@ -100,8 +103,7 @@ def test_apply_network(n, B, split):
     for p in range(B):
         ref = osv.Solver(w, a[p], b[p])
         exp = ref.correction(r[p].astype(np.float64))
-        say("  rel err", rel(z[p], exp))
-        assert rel(z[p], exp) <= F32_TOL, (p, rel(z[p], exp))
+        assert_close(z[p], exp, F32_TOL, f"problem {p}", say)
     S.close()
 
 
@@ -127,8 +129,7 @@ def test_apply_network_two_way_split(n, B):
     S.close()
     for p in range(B):
         exp = osv.Solver(w, a[p], b[p]).correction(r[p].astype(np.float64))
-        say("  rel err", rel(z[p], exp))
-        assert rel(z[p], exp) <= SPLIT2_TOL, (p, rel(z[p], exp))
+        assert_close(z[p], exp, SPLIT2_TOL, f"problem {p}", say)
     if n >= 15:
         from paper_2312_11093_amd.handbuilt import vcycle_weights
         S = Solver(vcycle_weights(), state="f32", u="f64", f32_split=2, method="fgmres", restart=63,
@@ -166,11 +167,9 @@ def test_apply_network_fewer_levels(n, levels):
         ref = osv.Solver(w, a[p], b[p], levels=L)
         got_s = S.get_setup_tensor(L).cpu().numpy()[p]
         exp_s = np.moveaxis(ref.s[L - 1], 0, -1)
-        assert rel(got_s, exp_s) <= F32_TOL
-        e1 = rel(z[p], ref.correction(r[p].astype(np.float64)))
-        e2 = rel(u[p].cpu().numpy(), ref.forward(f[p], 2))
-        say("  rel err apply", e1, "forward", e2)
-        assert e1 <= F32_TOL and e2 <= F32_TOL
+        assert_close(got_s, exp_s, F32_TOL, f"setup level {L}", say)
+        assert_close(z[p], ref.correction(r[p].astype(np.float64)), F32_TOL, "apply", say)
+        assert_close(u[p].cpu().numpy(), ref.forward(f[p], 2), F32_TOL, "forward", say)
     S.close()
     bad = Solver(w, state="f32", levels=full + 1)
     with pytest.raises(M.MGCNNError):
@@ -196,10 +195,8 @@ def test_up_post_matches_oracle(n, split):
     S.forward(dev(f), u, 2)
     for p in range(B):
         ref = osv.Solver(w, a[p], b[p], up_post=True)
-        e1 = rel(z[p], ref.correction(r[p].astype(np.float64)))
-        e2 = rel(u[p].cpu().numpy(), ref.forward(f[p], 2))
-        say("  rel err apply", e1, "forward", e2)
-        assert e1 <= F32_TOL and e2 <= F32_TOL
+        assert_close(z[p], ref.correction(r[p].astype(np.float64)), F32_TOL, "apply", say)
+        assert_close(u[p].cpu().numpy(), ref.forward(f[p], 2), F32_TOL, "forward", say)
     S.close()
     St = Solver(w, state="f32", u="f32", up_post=True)
     St.setup(dev(a), b)
@@ -251,9 +248,7 @@ def test_forward_grf31(K, split):
         u = torch.zeros((1, 31, 31), dtype=S.u_dtype, device="cuda")
         S.forward(dev(f), u, K)
         exp = osv.Solver(w, a[0], b[0]).forward(f[0], K)
-        err = rel(u[0].cpu().numpy(), exp)
-        say("  u", udt, "rel err", err)
-        assert err <= F32_TOL
+        assert_close(u[0].cpu().numpy(), exp, F32_TOL, f"u {udt}", say)
         S.close()
 
 
@@ -271,12 +266,19 @@ def test_forward_batched_ragged():
     got = u.cpu().numpy()
     for p in range(B):
         exp = osv.Solver(w, a[p], b[p]).forward(f[p], K)
-        assert rel(got[p], exp) <= F32_TOL, (p, rel(got[p], exp))
+        assert_close(got[p], exp, F32_TOL, f"problem {p}", say)
     S.close()
 
 
-def test_forward_bf16_state_reported():
-    say("forward bf16 state")
+def test_forward_bf16_state_report_only():
+    """bf16 state, setup tensors and weights (f32 accumulation): a report of the error against
+    the oracle, not a parity bound.  Every stored tensor is rounded to 8 significant bits
+    (relative 2^-8), and the rounding of the many intermediate states is amplified by the
+    untrained network, so no tight bound follows from the arithmetic; the assertion below only
+    catches gross faults (an error of the order of the result).  The bf16 path is judged by the
+    solves it serves: a tolerance-driven solve with it must reach tol on the oracle's residual
+    (test_solve_jacobi_matches_oracle_iterations)."""
+    say("forward bf16 state (report only)")
     n, B, K = 63, 2, 1
     a, b, f = batch("mixture127", n, B, seed=5)
     w = datagen.xavier_weights(16, 3)
@@ -392,9 +394,8 @@ def test_full_size_blocks1023_sampled(split):
     for p in (0, 63):
         say("  oracle problem", p)
         exp = osv.Solver(w, a[p], b[p]).forward(f[p], 1)
-        err = rel(u[p].cpu().numpy(), exp)
-        say("  rel err", err)
-        assert err <= (F32_TOL if split == 1 else SPLIT2_TOL)
+        assert_close(u[p].cpu().numpy(), exp, F32_TOL if split == 1 else SPLIT2_TOL,
+                     f"problem {p}", say)
     S.close()
 
 

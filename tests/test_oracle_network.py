@@ -144,6 +144,14 @@ def test_setup_special_cases():
     shift = sum(np.tanh(bk) for bk in betas)
     c = net.conv_same(P["W_sc"], F)
     np.testing.assert_allclose(s[0], c + shift[:, None, None], rtol=1e-13, atol=1e-13)
+    # ... on every level: Alg. 2 restricts the coefficient tensor c_l (Setup1), not the setup
+    # output s_l, so the shift does not pass down the hierarchy: s_l = c_l + shift with
+    # c_{l+1} = RCNN(c_l).  (Restricting s_l instead would add RCNN(shift) on every coarser level.)
+    assert L >= 3
+    for l in range(L):
+        np.testing.assert_allclose(s[l], c + shift[:, None, None], rtol=1e-12, atol=1e-12)
+        if l < L - 1:
+            c = net.conv_s2(P["W_sr"], c)
     # centre-tap channel-diagonal layers act pointwise: z <- z + tanh(w_k z + beta_k)
     for k in range(4):
         Wk = np.zeros((C, C, 3, 3))
@@ -159,6 +167,41 @@ def test_setup_special_cases():
     np.testing.assert_allclose(s[0], z, rtol=1e-12, atol=1e-12)
     # setup does not depend on the right-hand side: it only sees F
     assert len(s) == L and s[-1].shape == (C, 1, 1)
+
+
+def test_setup_level_coupling_by_injection():
+    """Level coupling of the setup network (Alg. 2) in closed form.  With the setup restriction
+    a channel-diagonal centre tap (RCNN samples c at the odd nodes 2I+1, 2J+1: injection) and
+    bias-only ResNet layers (z <- z + tanh(beta_k)), level l's coefficient tensor is the finest
+    one sampled every 2^(l-1) nodes, c_l[I, J] = c_1[2^(l-1)(I+1) - 1, 2^(l-1)(J+1) - 1], and
+    s_l = c_l + sum_k tanh(beta_k).  Read by plain indexing, independently of the convolution
+    helpers.  Had the setup output s_l been restricted instead of c_l, level l would carry l
+    copies of the shift."""
+    C, n = 2, 31
+    L = net.num_levels(n)
+    assert L == 5
+    rng = np.random.default_rng(21)
+    F = rng.uniform(0, 1, (4, n, n))
+    P = _zero_net(C)
+    P["W_sc"] = rng.standard_normal((C, 4, 3, 3))
+    for ch in range(C):
+        P["W_sr"][ch, ch, 1, 1] = 1.0
+    betas = [rng.uniform(-1.5, 1.5, C) for _ in range(4)]
+    for k in range(4):
+        P[f"beta_k{k}"] = betas[k]
+    shift = sum(np.tanh(bk) for bk in betas)
+    c1 = net.conv_same(P["W_sc"], F)
+    s = net.setup(P, F, L)
+    for l in range(1, L + 1):
+        step = 2 ** (l - 1)
+        m = (n + 1) // step - 1
+        idx = step * (np.arange(m) + 1) - 1
+        expect = c1[:, idx][:, :, idx] + shift[:, None, None]
+        assert s[l - 1].shape == (C, m, m)
+        np.testing.assert_allclose(s[l - 1], expect, rtol=1e-13, atol=1e-13)
+        wrong = c1[:, idx][:, :, idx] + l * shift[:, None, None]
+        if l > 1:
+            assert np.max(np.abs(s[l - 1] - wrong)) > 0.1
 
 
 # ----------------------------------------------------------------------------------------------
