@@ -169,14 +169,19 @@ int mgcnn_create(mgcnn_ctx **ctx, const mgcnn_opts *opts, const float *weights_h
                  void *hip_stream);
 
 /* Replace the weights (copied from host).  The setup tensors of the current problem set are
- * NOT recomputed: call mgcnn_setup again. */
+ * NOT recomputed: call mgcnn_setup again.  A recorded forward (mgcnn_forward, record = 1) is
+ * discarded: mgcnn_backward then returns MGCNN_E_NORECORD until the next recorded forward. */
 int mgcnn_set_weights(mgcnn_ctx *ctx, const float *weights_host);
 
 /* Change the stream used by subsequent calls. */
 int mgcnn_set_stream(mgcnn_ctx *ctx, void *hip_stream);
 
 /* Setup phase (Sec. 3.2, Alg. 2) for `batch` problems of side n: a [batch][n][n] device
- * (a > 0), b [batch][2] host.  The library copies a and b; `a` need not outlive the call.
+ * (a > 0), b [batch][2] host.  The library copies a and b; neither need outlive the call (b is
+ * copied into a pinned staging buffer of the context before the call returns; a by a
+ * stream-ordered device copy).  The setup network's temporaries stay allocated in the context
+ * for the next setup of the same size.  A recorded forward of the previous problem set is
+ * discarded (mgcnn_backward returns MGCNN_E_NORECORD until the next recorded forward).
  * Computes and keeps the per-level setup tensors.  With MGCNN_PRECOND_GMG it builds the
  * multigrid hierarchy instead: the injected coefficient of every coarse level and the f64
  * inverse of the coarsest operator (8 N^2 bytes per problem, N = coarsest nodes <= 225). */
@@ -221,7 +226,8 @@ int mgcnn_loss(mgcnn_ctx *ctx, const float *f, const float *u, double *loss_host
  * checkpointed iterates u_0..u_{K-1} (one iteration's activations live at a time). */
 int mgcnn_backward(mgcnn_ctx *ctx, const float *dL_du, float *dL_dweights, float *dL_df);
 
-/* Replace the weights from DEVICE memory (training loops); asynchronous on the stream. */
+/* Replace the weights from DEVICE memory (training loops); asynchronous on the stream.  Like
+ * mgcnn_set_weights it discards a recorded forward. */
 int mgcnn_set_weights_device(mgcnn_ctx *ctx, const float *weights_dev);
 
 /* Apply the network once: z = B(r / D) for a residual r [batch][n][n] float32 device;

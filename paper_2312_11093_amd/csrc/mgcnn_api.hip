@@ -117,6 +117,8 @@ void free_problem(mgcnn_ctx* c) {
   for (auto p : c->s) fr(p);
   for (auto p : c->xin) fr(p);
   for (auto p : c->xdn) fr(p);
+  fr(c->setup_tmp);
+  c->setup_tmp = nullptr;
   c->s.clear(); c->xin.clear(); c->xdn.clear();
   gmg_free(c);
   c->d_a = c->d_b = c->d_rt = nullptr;
@@ -369,6 +371,8 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
 
 int mgcnn_set_weights(mgcnn_ctx* c, const float* w) {
   if (!c) return MGCNN_E_ARG;
+  c->tr.K = 0;             // a recorded forward was taken with the previous weights
+  c->tr.f = nullptr;
   if (w == nullptr) {
     launch_zero(c->d_w, c->off.total * 4, c->stream);
     LAUNCH_CHECK(c);
@@ -385,6 +389,29 @@ int mgcnn_set_stream(mgcnn_ctx* c, void* s) {
   return MGCNN_OK;
 }
 
+// Copy the host velocities [B][2] to c->d_b through the context's pinned staging buffer: the
+// host copy into it is synchronous, so b_host may be released when the call returns, and the
+// previous setup's copy out of it is waited for before it is overwritten.
+static int stage_velocities(mgcnn_ctx* c, const float* b_host, int B) {
+  if (c->bstage_pending) {
+    HIP_TRY(c, hipEventSynchronize(c->bstage_ev));
+    c->bstage_pending = false;
+  }
+  if (!c->bstage_ev) HIP_TRY(c, hipEventCreateWithFlags(&c->bstage_ev, hipEventDisableTiming));
+  if (c->bstage_cap < 2 * B) {
+    if (c->h_bstage) HIP_TRY(c, hipHostFree(c->h_bstage));
+    c->h_bstage = nullptr;
+    c->bstage_cap = 0;
+    HIP_TRY(c, hipHostMalloc((void**)&c->h_bstage, (size_t)B * 2 * 4, hipHostMallocDefault));
+    c->bstage_cap = 2 * B;
+  }
+  std::memcpy(c->h_bstage, b_host, (size_t)B * 2 * 4);
+  HIP_TRY(c, hipMemcpyAsync(c->d_b, c->h_bstage, (size_t)B * 2 * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipEventRecord(c->bstage_ev, c->stream));
+  c->bstage_pending = true;
+  return MGCNN_OK;
+}
+
 int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B) {
   if (!c) return MGCNN_E_ARG;
   if (!a || !b_host) return fail(c, MGCNN_E_ARG, "setup: null a or b");
@@ -397,6 +424,8 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
   if (!c->gmg_on() && net_levels(c, n) == 0)
     return fail(c, MGCNN_E_ARG, "setup: levels out of range for this n");
   c->ready = false;
+  c->tr.K = 0;             // a recorded forward belongs to the previous problem set
+  c->tr.f = nullptr;
   int r = ensure_problem(c, n, B);
   if (r) return r;
   c->n = n;
@@ -404,21 +433,21 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
   hipStream_t s = c->stream;
   const size_t nn = (size_t)n * n * B;
   HIP_TRY(c, hipMemcpyAsync(c->d_a, a, nn * 4, hipMemcpyDeviceToDevice, s));
-  HIP_TRY(c, hipMemcpyAsync(c->d_b, b_host, (size_t)B * 2 * 4, hipMemcpyHostToDevice, s));
+  if ((r = stage_velocities(c, b_host, B))) return r;
   if (c->gmg_on()) {
     if ((r = gmg_setup(c))) return r;
-    HIP_TRY(c, hipStreamSynchronize(s));   // b_host is read by the asynchronous copy above
     c->ready = true;
     return MGCNN_OK;
   }
-  // setup temporaries (f32): features, coefficient tensor (current, next), two ping-pong
-  float *F = nullptr, *cc = nullptr, *cn = nullptr, *za = nullptr, *zb = nullptr;
+  // setup temporaries (f32), kept in the context for the next setup of this size: features,
+  // coefficient tensor (current, next), two ping-pong buffers of the tanh layers
   const size_t t16 = nn * C * 4;
-  HIP_TRY(c, hipMallocAsync((void**)&F, nn * 16, s));
-  HIP_TRY(c, hipMallocAsync((void**)&cc, t16, s));
-  HIP_TRY(c, hipMallocAsync((void**)&cn, t16, s));
-  HIP_TRY(c, hipMallocAsync((void**)&za, t16, s));
-  HIP_TRY(c, hipMallocAsync((void**)&zb, t16, s));
+  if (!c->setup_tmp && (r = alloc(c, &c->setup_tmp, nn * 16 + 4 * t16))) return r;
+  float* F = (float*)c->setup_tmp;
+  float* cc = F + nn * 4;
+  float* cn = cc + nn * C;
+  float* za = cn + nn * C;
+  float* zb = za + nn * C;
   launch_features(c->d_a, c->d_b, F, n, B, c->form(), s);
   launch_conv_in(4, F, c->W(c->off.setup_in), cc, ST_F32, n, B, nullptr, s);
   for (int l = 0; l < c->L; ++l) {
@@ -440,11 +469,6 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
     }
   }
   LAUNCH_CHECK(c);
-  HIP_TRY(c, hipFreeAsync(F, s));
-  HIP_TRY(c, hipFreeAsync(cc, s));
-  HIP_TRY(c, hipFreeAsync(cn, s));
-  HIP_TRY(c, hipFreeAsync(za, s));
-  HIP_TRY(c, hipFreeAsync(zb, s));
   c->ready = true;
   return MGCNN_OK;
 }
@@ -651,6 +675,8 @@ void mgcnn_destroy(mgcnn_ctx* c) {
   free_problem(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+  if (c->bstage_ev) (void)hipEventDestroy(c->bstage_ev);
+  if (c->h_bstage) (void)hipHostFree(c->h_bstage);
   for (auto e : c->pool) (void)hipEventDestroy(e);
   if (c->d_w) (void)hipFree(c->d_w);
   delete c;

@@ -34,6 +34,14 @@ struct mgcnn_ctx {
   int* d_iters = nullptr;
   double* d_relres = nullptr;
   bool ready = false;
+  // setup: the host velocities go through a pinned staging buffer (the caller's array need not
+  // outlive the call; the event guards the buffer against reuse before its copy has run), and
+  // the setup network's temporaries are kept for the next setup of the same size
+  float* h_bstage = nullptr;
+  int bstage_cap = 0;
+  hipEvent_t bstage_ev = nullptr;
+  bool bstage_pending = false;
+  void* setup_tmp = nullptr;
 
   // per-launch profiling (HIP events around every kernel launch of the solve loop)
   struct ProfRec { int kind, level; double bytes, flops; hipEvent_t e0, e1; };

@@ -141,6 +141,7 @@ int mgcnn_group_setup(mgcnn_group* g, const float* const* a, const float* b_host
       if (hipMemcpyAsync(k.a + nn * q, a[i], nn * 4, hipMemcpyDeviceToDevice, k.stream) != hipSuccess)
         return gfail(g, MGCNN_E_HIP, "group_setup: copy failed");
     }
+    // mgcnn_setup copies the velocities into its pinned staging buffer before it returns
     r = mgcnn_setup(k.ctx, k.a, bb.data(), k.n, B);
     if (r != MGCNN_OK) return gfail(g, r, std::string("group_setup: ") + mgcnn_last_error(k.ctx));
   }

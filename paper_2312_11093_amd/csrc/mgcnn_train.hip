@@ -268,6 +268,8 @@ extern "C" {
 
 int mgcnn_set_weights_device(mgcnn_ctx* c, const float* w_dev) {
   if (!c || !w_dev) return MGCNN_E_ARG;
+  c->tr.K = 0;             // a recorded forward was taken with the previous weights
+  c->tr.f = nullptr;
   HIP_TRY(c, hipMemcpyAsync(c->d_w, w_dev, c->off.total * 4, hipMemcpyDeviceToDevice, c->stream));
   return MGCNN_OK;
 }
