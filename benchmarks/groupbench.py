@@ -8,7 +8,7 @@ warm-up of the same call), solves/s, per-size problem counts and mean iterations
 and 99th percentiles of the iteration counts, and the largest final relative residual (the
 library's f64 residual of every returned solution).
 
-    python -m paper_2312_11093_amd.groupbench [--count 256] [--precond network|gmg]
+    python -m benchmarks.groupbench [--count 256] [--precond network|gmg]
 """
 from __future__ import annotations
 

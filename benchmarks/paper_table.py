@@ -6,17 +6,20 @@ draws, the iteration count, setup time and solve time of
 
   * GMG: the geometric multigrid baseline with the paper's settings (levels log2(n+1) - 3,
     three sweeps of weight 0.67, exact coarsest solve);
-  * network: the MGCNN solve network with the hand-set coefficient-aware V(1,1) weights, f32
-    state, f64 u, as the preconditioner of FGMRES(30) (as a stationary iteration these weights
-    diverge on white-noise coefficients);
+  * network: the MGCNN solve network, f32 state, f64 u; by default with the hand-set
+    coefficient-aware V(1,1) weights as the preconditioner of FGMRES(30) (as a stationary
+    iteration these weights diverge on white-noise coefficients); with --weights FILE (a .npy
+    flat vector of a C-channel network, C <= 16, read with allow_pickle=False) a trained network,
+    by default in the stationary iteration of Sec. 4.1 (--method stationary|fgmres);
 
 next to the GMG iteration counts the paper prints (Sec. 4.2, double precision table).
 --data mldata takes the coefficients from the multi-level generator of Alg. 4 instead of white
 noise (Sec. 4.3, Re = 1000); --net-levels sets the network's level count (0: log2(n+1), coarsest
 grid 1 x 1; -1: the count of Sec. 4.1, coarsest grid 3 x 3).
 
-    python -m paper_2312_11093_amd.paper_table [--re 1000] [--data white|mldata] [--net-levels 0]
-                                               [--sizes 31,63,...] [--draws 3]
+    python -m benchmarks.paper_table [--re 1000] [--data white|mldata] [--net-levels 0]
+                                     [--sizes 31,63,...] [--draws 3] [--weights W.npy]
+                                     [--method stationary|fgmres] [--no-gmg]
 """
 from __future__ import annotations
 
@@ -44,6 +47,9 @@ def main():
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--data", default="white", choices=["white", "mldata"])
     ap.add_argument("--net-levels", type=int, default=0)
+    ap.add_argument("--weights", default=None)
+    ap.add_argument("--method", default=None, choices=["stationary", "fgmres"])
+    ap.add_argument("--no-gmg", action="store_true")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -51,6 +57,14 @@ def main():
     import datagen
     from paper_2312_11093_amd import Solver
     from paper_2312_11093_amd.handbuilt import vcycle_weights
+    from paper_2312_11093_amd.weights import embed_channels
+
+    if args.weights:
+        net_w = embed_channels(np.load(args.weights, allow_pickle=False))
+        method = args.method or "stationary"
+    else:
+        net_w = vcycle_weights()
+        method = args.method or "fgmres"
 
     if args.data == "mldata":
         if args.re != 1000.0:
@@ -62,12 +76,12 @@ def main():
     rows = []
     for n in sizes:
         row = {"n": n, "paper_gmg_iters": PAPER_GMG.get(n) if wl == "paper_re1e3" else None}
-        for name in ("gmg", "network"):
+        for name in (("network",) if args.no_gmg else ("gmg", "network")):
             if name == "gmg":
                 S = Solver(None, precond="gmg", u="f64", form="nondiv", use_graph=True)
             else:
-                S = Solver(vcycle_weights(), state="f32", u="f64", form="nondiv",
-                           method="fgmres", restart=30, levels=args.net_levels)
+                S = Solver(net_w, state="f32", u="f64", form="nondiv", method=method,
+                           restart=30, levels=args.net_levels)
             its, tset, tsol, ok = [], [], [], True
             for d in range(args.draws + 1):          # draw 0 warms up
                 p = datagen.make_problem(wl, n, d, 0)
@@ -94,8 +108,10 @@ def main():
                          "solve_ms": round(float(np.mean(tsol)), 3)}
         rows.append(row)
         print(json.dumps(row), flush=True)
+    if args.no_gmg:
+        return
     print(f"{'n':>6} {'paper GMG it':>12} {'GMG it':>7} {'GMG setup':>10} {'GMG solve':>10} "
-          f"{'net it':>7} {'net setup':>10} {'net solve':>10}  (ms; network: FGMRES(30))")
+          f"{'net it':>7} {'net setup':>10} {'net solve':>10}  (ms; network: {method})")
     for r in rows:
         g, w = r["gmg"], r["network"]
         pg = f"{r['paper_gmg_iters']:.1f}" if r["paper_gmg_iters"] is not None else "-"

@@ -7,7 +7,7 @@ Prints one JSON line per method: wall time of the solve of the whole batch (the 
 identical solves), solves/s, mean and largest step counts, and the largest relative residual
 (the library's f64 residual of each returned solution).
 
-    python -m paper_2312_11093_amd.pcgbench [--n 1023] [--batch 64] [--tol 1e-8]
+    python -m benchmarks.pcgbench [--n 1023] [--batch 64] [--tol 1e-8]
 """
 from __future__ import annotations
 

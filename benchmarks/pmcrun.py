@@ -7,9 +7,9 @@ Runs, in one process on one GPU:
   2. `iters` stationary iterations (residual + V-cycle + update) of the benchmark's batch:
      64 problems at 1023 x 1023, random 16 x 16 blocks, f32 state, f64 u, hand-set weights.
 
-    rocprofv3 --pmc FETCH_SIZE -d <dir> -o run -f csv -- python3 -m paper_2312_11093_amd.pmcrun
-    rocprofv3 --pmc WRITE_SIZE -d <dir> -o run -f csv -- python3 -m paper_2312_11093_amd.pmcrun
-    python -m paper_2312_11093_amd.profsum --pmc <dir>/run_counter_collection.csv
+    rocprofv3 --pmc FETCH_SIZE -d <dir> -o run -f csv -- python3 -m benchmarks.pmcrun
+    rocprofv3 --pmc WRITE_SIZE -d <dir> -o run -f csv -- python3 -m benchmarks.pmcrun
+    python -m benchmarks.profsum --pmc <dir>/run_counter_collection.csv
 """
 from __future__ import annotations
 

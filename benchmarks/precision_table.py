@@ -11,7 +11,7 @@ and the one recomputed in f64 by the library for the returned u (the floor a var
 when it cannot reach `tol`), the solve time, and the relative difference of its u from the
 f32-state / f64-u solution.
 
-    python -m paper_2312_11093_amd.precision_table [--n 4095] [--tol 1e-10] [--maxit 400]
+    python -m benchmarks.precision_table [--n 4095] [--tol 1e-10] [--maxit 400]
 """
 from __future__ import annotations
 

@@ -1,7 +1,7 @@
 """Summarise a rocprofv3 kernel trace (CSV) per kernel and grid size.
 
-    python -m paper_2312_11093_amd.profsum <run_kernel_trace.csv> [top]
-    python -m paper_2312_11093_amd.profsum --pmc <run_counter_collection.csv> [top]
+    python -m benchmarks.profsum <run_kernel_trace.csv> [top]
+    python -m benchmarks.profsum --pmc <run_counter_collection.csv> [top]
 
 Prints launches, average and total duration per kernel, then per (kernel, grid size); the
 grid size separates the levels of the multigrid hierarchy and the number of live problems.
