@@ -52,7 +52,9 @@ enum {
   MGCNN_E_NOMEM = -4,        /* device allocation failed */
   MGCNN_E_HIP = -5,          /* a HIP runtime call failed; see mgcnn_last_error */
   MGCNN_E_DIVERGED = -6,     /* relative residual non-finite or > 1e10 (solve) */
-  MGCNN_E_NORECORD = -7      /* backward without a recorded forward */
+  MGCNN_E_NORECORD = -7,     /* backward without a recorded forward */
+  MGCNN_E_SCRATCH = -8       /* mgcnn_residual_norms_noalloc: the input needs more scratch memory
+                                than MGCNN_NOALLOC_SCRATCH_BYTES */
 };
 
 /* Precision of the network state, setup tensors and conv weights. */
@@ -280,6 +282,31 @@ typedef struct {
 int mgcnn_profile_begin(mgcnn_ctx *ctx);
 /* stats may be NULL (then only *n_stats is set); at most max_stats entries are written. */
 int mgcnn_profile_end(mgcnn_ctx *ctx, mgcnn_kernel_stat *stats, int max_stats, int *n_stats);
+
+/* ---- Stopping-test norms without allocation ---------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the relative residuals of mgcnn_residual_norms,
+ * relres_host[i] = ||f_i - A_i u_i||_2 / ||f_i||_2 (0 when f_i = 0), with no context and no
+ * allocation.  The kernels are those of mgcnn_residual_norms (same results bit for bit); their
+ * scratch memory (velocities, per-tile partial sums of r^2 in f64, per-problem sums) is one
+ * fixed array of MGCNN_NOALLOC_SCRATCH_BYTES per device, held by the library until the process
+ * ends, which allows tiles(n) * batch + 2 * batch doubles plus the velocities, tiles(n) =
+ * ceil(n / 256) * ceil(n / 8) (e.g. batch <= 2000 at n = 1023, <= 127 at n = 4095).
+ *   a, f: [batch][n][n] float32 DEVICE; u: [batch][n][n] DEVICE, float32 or float64 per u_dtype
+ *   (MGCNN_U_F32 / MGCNN_U_F64; the residual arithmetic follows u_dtype, f32 or f64, as in
+ *   mgcnn_residual_norms); b_host:
+ *   [batch][2] HOST velocities; op_form: MGCNN_OP_DIV or MGCNN_OP_NONDIV; relres_host: [batch]
+ *   HOST output; hip_stream: hipStream_t of the work (NULL = default stream), on the current
+ *   device.  Blocks the host until relres_host is written.
+ * Returns MGCNN_E_ARG (null pointer, unknown form or u_dtype, non-finite velocity), MGCNN_E_SIZE
+ * (n not 2^L - 1 in [3, 4095], batch < 1), MGCNN_E_SCRATCH (input larger than the scratch array;
+ * nothing is launched), MGCNN_E_HIP.  Calls on one device share its scratch array: calls that
+ * overlap in time on the same device (several host threads or streams) race and must be
+ * serialised by the caller.  Every scratch word a call reads it has written first. */
+#define MGCNN_NOALLOC_SCRATCH_BYTES (8u << 20)
+int mgcnn_residual_norms_noalloc(const float *a, const float *b_host, int n, int batch,
+                                 int op_form, const float *f, const void *u, int u_dtype,
+                                 double *relres_host, void *hip_stream);
 
 /* Number of levels of the current problem set (0 before setup). */
 int mgcnn_levels(const mgcnn_ctx *ctx);

@@ -192,6 +192,20 @@ void launch_sum_partials(const double* partial, int tiles, double* out, int B, h
   hipLaunchKernelGGL(sum_partials_kernel, dim3(B), dim3(256), 0, st, partial, tiles, out);
 }
 
+// relres[b] = ||r_b|| / ||f_b|| from the residual's partial sums and ||f_b||^2 (0 when f_b = 0).
+__global__ __launch_bounds__(256) void relres_kernel(const double* __restrict__ partial, int tiles,
+                                                     const double* __restrict__ nf2,
+                                                     double* __restrict__ relres) {
+  const int b = blockIdx.x;
+  const double s = sum_partials_block(partial + (size_t)b * tiles, tiles);
+  if (threadIdx.x == 0) relres[b] = nf2[b] > 0.0 ? sqrt(s) / sqrt(nf2[b]) : 0.0;
+}
+
+void launch_relres(const double* partial, int tiles, const double* nf2, double* relres, int B,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(relres_kernel, dim3(B), dim3(256), 0, st, partial, tiles, nf2, relres);
+}
+
 // Stopping rule at iterate k = iters[b] (relative residual rho_k = ||r_k|| / ||f||):
 //   rho_k <= tol          -> OK, stop (iters = k)
 //   k == maxit            -> NOT_CONVERGED, stop

@@ -590,13 +590,10 @@ int mgcnn_residual_norms(mgcnn_ctx* c, const float* f, const void* u, double* re
   launch_sum_partials(c->d_partial, c->tiles, c->d_nf2, B, s);
   launch_residual(c->d_a, c->d_b, f, u, c->u64(), nullptr, c->d_partial, c->n, B, nullptr,
                   c->form(), s);
-  launch_sum_partials(c->d_partial, c->tiles, c->d_relres, B, s);
+  launch_relres(c->d_partial, c->tiles, c->d_nf2, c->d_relres, B, s);
   LAUNCH_CHECK(c);
-  std::vector<double> nf(B), rr(B);
-  HIP_TRY(c, hipMemcpyAsync(nf.data(), c->d_nf2, (size_t)B * 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, hipMemcpyAsync(rr.data(), c->d_relres, (size_t)B * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(relres_host, c->d_relres, (size_t)B * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
-  for (int b = 0; b < B; ++b) relres_host[b] = nf[b] > 0 ? std::sqrt(rr[b]) / std::sqrt(nf[b]) : 0.0;
   return MGCNN_OK;
 }
 
@@ -659,6 +656,9 @@ const char* mgcnn_status_string(int s) {
     case MGCNN_E_HIP: return "HIP runtime error";
     case MGCNN_E_DIVERGED: return "diverged";
     case MGCNN_E_NORECORD: return "no recorded forward";
+    case MGCNN_E_SCRATCH:
+      return "input exceeds the fixed scratch buffer of mgcnn_residual_norms_noalloc "
+             "(MGCNN_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }

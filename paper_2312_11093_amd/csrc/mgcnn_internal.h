@@ -87,6 +87,8 @@ void launch_finalize(const double* partial, int tiles, const double* nf2, double
 
 // nf2[b] = sum of partials (the squared norm of f), deterministic order.
 void launch_sum_partials(const double* partial, int tiles, double* out, int B, hipStream_t st);
+void launch_relres(const double* partial, int tiles, const double* nf2, double* relres, int B,
+                   hipStream_t st);
 
 // Convert f32 -> bf16 (round to nearest even), count elements.
 void launch_f32_to_bf16(const float* in, bf16_t* out, size_t count, hipStream_t st);

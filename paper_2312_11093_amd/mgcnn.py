@@ -19,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmgcnn.so")
 
 OK, NOT_CONVERGED = 0, 1
-E_ARG, E_SIZE, E_STATE, E_NOMEM, E_HIP, E_DIVERGED, E_NORECORD = -1, -2, -3, -4, -5, -6, -7
+E_ARG, E_SIZE, E_STATE, E_NOMEM, E_HIP, E_DIVERGED, E_NORECORD, E_SCRATCH = -1, -2, -3, -4, -5, -6, -7, -8
+NOALLOC_SCRATCH_BYTES = 8 << 20
 F32, BF16 = 0, 1
 U_F32, U_F64 = 0, 1
 
@@ -91,6 +92,10 @@ EXPORTS = {
     "mgcnn_group_buckets": (ctypes.c_int, [ctypes.c_void_p]),
     "mgcnn_group_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "mgcnn_group_destroy": (None, [ctypes.c_void_p]),
+    "mgcnn_residual_norms_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                                    ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                                    ctypes.c_void_p]),
 }
 
 
@@ -147,6 +152,33 @@ def _weights_ptr(owner, weights, count):
         raise ValueError(f"expected {count} weights, got {w.size}")
     owner._w = w
     return w.ctypes.data
+
+
+def residual_norms_noalloc(a, b, f, u, form: str = "div", stream=None):
+    """mgcnn_residual_norms_noalloc: relative residuals ||f - A u|| / ||f|| per problem with no
+    context and no device allocation (the library's fixed scratch array).  a, f: (B, n, n)
+    float32 device tensors; u: (B, n, n) float32 or float64 device tensor; b: (B, 2) host
+    array.  Returns a float64 numpy array (B,); raises MGCNNError on a non-zero status."""
+    import torch
+    L = lib()
+    _check_dev(a, torch.float32, "a")
+    _check_dev(f, torch.float32, "f")
+    if not isinstance(u, torch.Tensor) or not u.is_cuda or u.dtype not in (torch.float32, torch.float64):
+        raise TypeError("u must be a float32 or float64 device tensor")
+    if not u.is_contiguous():
+        raise ValueError("u must be contiguous")
+    B, n, _ = a.shape
+    if tuple(f.shape) != (B, n, n) or tuple(u.shape) != (B, n, n):
+        raise ValueError("a, f and u must have the same (B, n, n) shape")
+    bh = np.ascontiguousarray(np.asarray(b, dtype=np.float32).reshape(B, 2))
+    out = np.zeros(B, np.float64)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = L.mgcnn_residual_norms_noalloc(_ptr(a), bh.ctypes.data, n, B, FORMS[form], _ptr(f), _ptr(u),
+                                        U_F64 if u.dtype == torch.float64 else U_F32,
+                                        out.ctypes.data, ctypes.c_void_p(s.cuda_stream))
+    if st != OK:
+        raise MGCNNError(st, L.mgcnn_status_string(st).decode())
+    return out
 
 
 class Solver:

@@ -53,6 +53,29 @@ def test_host_only_calls(lib):
     assert lib.mgcnn_create(None, None, None, None) == -1
 
 
+def test_noalloc_argument_errors_before_device_work(lib):
+    """mgcnn_residual_norms_noalloc checks its arguments and its scratch bound on the host and
+    returns before any HIP call: null pointers, a bad size, and an input larger than the fixed
+    scratch array (MGCNN_E_SCRATCH: 200 problems at 4095^2 need 13 MB of partial sums)."""
+    import numpy as np
+    f = lib.mgcnn_residual_norms_noalloc
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    stand_in = np.zeros(16, np.float32)        # never dereferenced on these paths
+    p = stand_in.ctypes.data
+    out = np.zeros(200, np.float64)
+    b = np.ones((200, 2), np.float32)
+    assert f(None, b.ctypes.data, 31, 1, 0, p, p, 1, out.ctypes.data, None) == -1
+    assert f(p, b.ctypes.data, 31, 1, 2, p, p, 1, out.ctypes.data, None) == -1      # form
+    assert f(p, b.ctypes.data, 31, 1, 0, p, p, 2, out.ctypes.data, None) == -1      # u_dtype
+    assert f(p, b.ctypes.data, 30, 1, 0, p, p, 1, out.ctypes.data, None) == -2      # n
+    assert f(p, b.ctypes.data, 31, 0, 0, p, p, 1, out.ctypes.data, None) == -2      # batch
+    assert f(p, b.ctypes.data, 4095, 200, 0, p, p, 1, out.ctypes.data, None) == -8  # scratch
+    lib.mgcnn_status_string.restype = ctypes.c_char_p
+    assert b"scratch" in lib.mgcnn_status_string(-8)
+
+
 def test_no_oracle_in_product_path():
     """The product package never imports the oracle."""
     pkg = os.path.join(ROOT, "paper_2312_11093_amd")
