@@ -24,6 +24,13 @@ they stay zero and the network stays the C-channel network.
     python -m paper_2312_11093_amd.train_t5 --out DIR [--channels 8] [--batches 1000]
            [--epochs 50] [--resume] [--minutes M]
 
+The same schedule can train on the other coefficient families of this library (--data blocks:
+16 x 16 random blocks with log10 a ~ U(-2, 2); --data mixture: blocks, lognormal fields,
+checkerboards and inclusions in turn; both with random velocities |b| <= 10 and the divergence
+form, full-depth networks), with K > 1 unrolled iterations (--K), and from given weights
+(--init; --init-noise adds small random weights to channels the given network leaves at zero,
+so that they can leave the zero saddle).
+
 Writes DIR/weights_c{C}.npy (the compact C-channel vector), DIR/weights16.npy (the library
 layout), DIR/ckpt.pt (weights, Adam and scheduler state, progress) and DIR/log.jsonl.
 """
@@ -50,6 +57,8 @@ TABLE5 = {"epochs": 50, "batches": 1000, "lr": 3e-3, "lr_step_epochs": 2, "gamma
           "min_batch_size": 2}
 RE = 1000.0                      # Sec. 4.1: range limit of the mesh Reynolds number
 DATA_STREAM = 0x7A5               # seed-sequence tag of the training data
+# operator form and network depth (opts.levels) of each training family
+DATA_FORM = {"paper": ("nondiv", -1), "blocks": ("div", 0), "mixture": ("div", 0)}
 
 
 def stage(epoch: int, t=TABLE5):
@@ -66,19 +75,32 @@ def stage(epoch: int, t=TABLE5):
     return n, lev, B
 
 
-def batch_data(n: int, B: int, seed: int, step: int):
-    """Coefficients a (B, n, n), right-hand sides f (B, n, n) (float32) and the f64 squared
-    norms of f for training step `step`: white noise mapped onto coef in [1/Re, 1]
-    (Sec. 4.1) and white-noise right-hand sides (Sec. 3.4)."""
+def batch_data(n: int, B: int, seed: int, step: int, kind: str = "paper"):
+    """Coefficients a (B, n, n), velocities b (B, 2), right-hand sides f (B, n, n) (float32) and
+    the f64 squared norms of f for training step `step`.  "paper": white noise mapped onto coef
+    in [1/Re, 1] and v = (sin 0.5, cos 0.5) (Sec. 4.1); "blocks" / "mixture": the library's
+    families with random velocities.  Right-hand sides are white noise (Sec. 3.4)."""
     import datagen
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, DATA_STREAM, step])))
     a = np.empty((B, n, n), np.float32)
+    b = np.empty((B, 2), np.float32)
     f = np.empty((B, n, n), np.float32)
     for i in range(B):
-        a[i] = datagen.white_noise_coef(n, rng, RE)
+        if kind == "paper":
+            a[i] = datagen.white_noise_coef(n, rng, RE)
+            b[i] = datagen.velocity(rng, "paper")
+        elif kind == "blocks":
+            a[i] = datagen.blocks_lognormal(n, rng)
+            b[i] = datagen.velocity(rng, "random")
+        elif kind == "mixture":
+            j = (step * B + i) % 4
+            a[i] = datagen.blocks_lognormal(n, rng) if j == 0 else datagen.mixture(n, rng)
+            b[i] = datagen.velocity(rng, "random")
+        else:
+            raise ValueError(kind)
         f[i] = rng.standard_normal((n, n))
     f2 = np.einsum("bij,bij->b", f.astype(np.float64), f.astype(np.float64))
-    return a, f, f2
+    return a, b, f, f2
 
 
 def channel_mask(C: int) -> np.ndarray:
@@ -94,7 +116,8 @@ def compact(w16: np.ndarray, C: int) -> np.ndarray:
 
 def train(out: str, C: int = 8, epochs: int | None = None, batches: int | None = None,
           seed: int = 0, resume: bool = False, minutes: float = 1e9, log_every: int = 250,
-          init: str | None = None):
+          init: str | None = None, data: str = "paper", K: int = 1, init_noise: float = 0.0,
+          lr: float | None = None):
     import torch
 
     import datagen
@@ -102,6 +125,9 @@ def train(out: str, C: int = 8, epochs: int | None = None, batches: int | None =
     from paper_2312_11093_amd.weights import embed_channels
 
     t = dict(TABLE5)
+    if lr is not None:
+        t["lr"] = float(lr)
+    form, net_levels = DATA_FORM[data]
     if epochs is not None:
         t["epochs"] = int(epochs)
     if batches is not None:
@@ -111,8 +137,12 @@ def train(out: str, C: int = 8, epochs: int | None = None, batches: int | None =
     t_end = time.time() + 60.0 * minutes
     mask = torch.tensor(channel_mask(C), device="cuda")
     if init:
-        w0 = np.load(init, allow_pickle=False).astype(np.float32)
-        w0 = w0 if w0.size == mask.numel() else embed_channels(w0, C)
+        w0 = embed_channels(np.load(init, allow_pickle=False).astype(np.float32))
+        if init_noise > 0:
+            # small random weights where the given network is zero but the C-channel one is not
+            xav = embed_channels(datagen.xavier_weights(C, seed + 1), C)
+            w0 = np.where(w0 == 0, init_noise * xav, w0).astype(np.float32)
+        w0 = w0 * channel_mask(C)
     else:
         w0 = embed_channels(datagen.xavier_weights(C, seed), C)
     w = torch.tensor(w0, device="cuda")
@@ -133,30 +163,29 @@ def train(out: str, C: int = 8, epochs: int | None = None, batches: int | None =
 
     def job(s):
         n, lev, B = stage(s // t["batches"], t)
-        return s, n, lev, B, batch_data(n, B, seed, s)
+        return s, n, lev, B, batch_data(n, B, seed, s, data)
 
     pending = pool.submit(job, step) if step < total else None
     skipped = 0
     acc, cnt = 0.0, 0
     t0 = time.time()
     while pending is not None:
-        s, n, lev, B, (a_h, f_h, f2) = pending.result()
+        s, n, lev, B, (a_h, bv, f_h, f2) = pending.result()
         pending = pool.submit(job, s + 1) if s + 1 < total else None
         key = (n, B)
         if key not in solvers:
             for S_old in solvers.values():
                 S_old.close()
-            solvers = {key: Solver(w0, state="f32", u="f32", form="nondiv", levels=-1)}
+            solvers = {key: Solver(w0, state="f32", u="f32", form=form, levels=net_levels)}
             u = torch.zeros((B, n, n), device="cuda")
             du = torch.empty_like(u)
         S = solvers[key]
         a = torch.from_numpy(a_h).cuda(non_blocking=False)
         f = torch.from_numpy(f_h).cuda(non_blocking=False)
-        bv = np.tile(np.array([math.sin(0.5), math.cos(0.5)], np.float32), (B, 1))
         S.set_weights_device(w)
         S.setup(a, bv)
         u.zero_()
-        S.forward(f, u, 1, record=True)
+        S.forward(f, u, K, record=True)
         log_now = (s + 1) % log_every == 0 or s + 1 == total
         rel = S.loss(f, u, du)                      # mean_i ||r_i||^2 / ||f_i||^2
         # absolute loss of Eq. (19) per grid node: (1/B) sum_i ||r_i||^2 / n^2; its gradient is
@@ -177,7 +206,8 @@ def train(out: str, C: int = 8, epochs: int | None = None, batches: int | None =
         sched.step()
         step = s + 1
         if log_now or time.time() > t_end:
-            rec = {"step": step, "epoch": s // t["batches"], "n": n, "levels": lev, "batch": B,
+            rec = {"step": step, "epoch": s // t["batches"], "n": n, "levels": lev if data == "paper"
+                   else int(math.log2(n + 1)), "batch": B, "K": K, "data": data,
                    "relres2_mean": acc / max(cnt, 1), "lr": opt.param_groups[0]["lr"],
                    "skipped": skipped, "sec": round(time.time() - t0, 1)}
             print(json.dumps(rec), flush=True)
@@ -211,9 +241,13 @@ def main():
     ap.add_argument("--minutes", type=float, default=1e9)
     ap.add_argument("--log-every", type=int, default=250)
     ap.add_argument("--init", default=None)
+    ap.add_argument("--init-noise", type=float, default=0.0)
+    ap.add_argument("--data", default="paper", choices=sorted(DATA_FORM))
+    ap.add_argument("--K", type=int, default=1)
+    ap.add_argument("--lr", type=float, default=None)
     args = ap.parse_args()
     train(args.out, args.channels, args.epochs, args.batches, args.seed, args.resume, args.minutes,
-          args.log_every, args.init)
+          args.log_every, args.init, args.data, args.K, args.init_noise, args.lr)
 
 
 if __name__ == "__main__":
