@@ -317,10 +317,21 @@ void mgcnn_destroy(mgcnn_ctx *ctx);
 
 /* ---- Uneven-size batches ---------------------------------------------------------------
  * One call for problems of different sizes n_i = 2^k - 1 (each still the method of Sec. 2.2
- * and Alg. 2 / Alg. 3 per problem).  The group buckets the problems by size; every bucket is
- * one batched problem set on its own HIP stream (default priority), and the buckets are solved
- * concurrently, each from its own host thread.  Results per problem are identical to solving
- * that problem on its own with the same options. */
+ * and Alg. 2 / Alg. 3 per problem).  Results per problem are identical to solving that problem
+ * on its own with the same options.  Two launch structures:
+ *   - aligned levels (the stationary iteration with the network preconditioner and
+ *     opts.levels <= 0): every hierarchy halves its side down to a coarsest side that does not
+ *     depend on n, so the levels of all problems coincide in size from the coarsest up.  With
+ *     the problems sorted by decreasing n, the problems having a level of side m are a prefix,
+ *     and each level size is one batched tensor: every coarse-level operation of the V-cycle is
+ *     one launch over all problems having that level, the finest-level operations (residual,
+ *     reChannel-in smoother, reChannel-out update, stopping test) one launch per distinct size.
+ *     One HIP stream, blocks of check_every iterations captured in a hipGraph when
+ *     opts.use_graph; problems that have converged are held by their flag (u unchanged) until
+ *     the whole batch has stopped.  Device timestamps of every problem's stop are kept
+ *     (mgcnn_group_completion_times);
+ *   - buckets (every other configuration): one batched problem set per size on its own HIP
+ *     stream (default priority), solved concurrently, each from its own host thread. */
 typedef struct mgcnn_group mgcnn_group;
 
 /* Create a group: options and weights as for mgcnn_create (copied).  The group's streams are
@@ -338,8 +349,16 @@ int mgcnn_group_setup(mgcnn_group *group, const float *const *a, const float *b_
  * rule, per-problem outputs and return value as for mgcnn_solve.  Blocks the host. */
 int mgcnn_group_solve(mgcnn_group *group, const float *const *f, void *const *u, double tol,
                       int maxit, int *iters_host, double *relres_host, int *status_host);
-/* Number of size buckets of the last setup. */
+/* Number of distinct problem sizes of the last setup (buckets, or finest sizes of the aligned
+ * levels). */
 int mgcnn_group_buckets(const mgcnn_group *group);
+/* 1 if the group runs on aligned levels (one stream), 0 if on per-size buckets. */
+int mgcnn_group_aligned(const mgcnn_group *group);
+/* Aligned levels only: per problem (caller order), the seconds from the start of the last
+ * mgcnn_group_solve's iterations (after ||f|| and the solver state are initialised) to the
+ * device wall clock (wall_clock64) at which the stopping test ended that problem; 0 for a zero
+ * right-hand side.  seconds_host [count] host.  MGCNN_E_STATE without such a solve. */
+int mgcnn_group_completion_times(const mgcnn_group *group, double *seconds_host);
 const char *mgcnn_group_last_error(const mgcnn_group *group);
 void mgcnn_group_destroy(mgcnn_group *group);
 

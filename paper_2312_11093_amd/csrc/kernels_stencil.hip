@@ -214,7 +214,8 @@ void launch_relres(const double* partial, int tiles, const double* nf2, double* 
 __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ partial,
                                                        int tiles, const double* __restrict__ nf2,
                                                        double tol, int maxit, int* active,
-                                                       int* status, int* iters, double* relres) {
+                                                       int* status, int* iters, double* relres,
+                                                       long long* done_clock) {
   const int b = blockIdx.x;
   if (active[b] == 0) return;
   const double s = sum_partials_block(partial + (size_t)b * tiles, tiles);
@@ -222,24 +223,36 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   const double rho = sqrt(s) / sqrt(nf2[b]);
   const int k = iters[b];
   relres[b] = rho;
+  bool done = true;
   if (rho <= tol) {
     status[b] = 0;
-    active[b] = 0;
   } else if (k >= maxit) {
     status[b] = 1;
-    active[b] = 0;
   } else if (!(rho <= 1e10)) {
     status[b] = -6;
-    active[b] = 0;
   } else {
     iters[b] = k + 1;
+    done = false;
+  }
+  if (done) {
+    active[b] = 0;
+    if (done_clock != nullptr) done_clock[b] = wall_clock64();
   }
 }
 
+__global__ void clock_stamp_kernel(long long* out) {
+  if (threadIdx.x == 0) out[0] = wall_clock64();
+}
+
+void launch_clock_stamp(long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(clock_stamp_kernel, dim3(1), dim3(64), 0, st, out);
+}
+
 void launch_finalize(const double* partial, int tiles, const double* nf2, double tol, int maxit,
-                     int* active, int* status, int* iters, double* relres, int B, hipStream_t st) {
+                     int* active, int* status, int* iters, double* relres, int B, hipStream_t st,
+                     long long* done_clock) {
   hipLaunchKernelGGL(finalize_kernel, dim3(B), dim3(256), 0, st, partial, tiles, nf2, tol, maxit,
-                     active, status, iters, relres);
+                     active, status, iters, relres, done_clock);
 }
 
 __global__ void solve_init_kernel(const double* __restrict__ nf2, int* active, int* status,

@@ -39,7 +39,6 @@ WeightOffsets weight_offsets() {
 }
 
 void launch_bf16_to_f32(const bf16_t* in, float* out, size_t count, hipStream_t st);
-void launch_zero_if_zero_rhs(void* u, bool u_f64, const double* nf2, int n, int B, hipStream_t st);
 void launch_scale_by_diag(const float* a, const float* b, const float* r, float* rt, int n, int B,
                           int form, hipStream_t st);
 

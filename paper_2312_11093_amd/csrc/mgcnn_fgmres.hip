@@ -22,7 +22,6 @@ using namespace mg;
 using namespace mg::api;
 
 namespace mg {
-void launch_zero_if_zero_rhs(void* u, bool u_f64, const double* nf2, int n, int B, hipStream_t st);
 
 namespace api {
 

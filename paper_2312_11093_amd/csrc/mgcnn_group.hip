@@ -1,10 +1,15 @@
 // Uneven-size batches: problems of different sizes in one call.
 //
-// Problems are bucketed by size; each bucket is an ordinary batched problem set (its own
-// context, workspace and HIP stream at the default priority).  Setup gathers the coefficients
-// of a bucket into one contiguous batch; solve gathers f and u, runs the buckets' solves
-// concurrently (one host thread per bucket, since a solve blocks its thread at every host
-// check) and scatters u back.  Per problem the arithmetic is that of a batch of one.
+// The stationary iteration with the network preconditioner and a level count relative to the
+// grid (opts.levels <= 0) runs on the aligned levels of mgcnn_ladder.h: one stream, one launch
+// per operation and level size over the whole mixed batch.
+//
+// Every other configuration (FGMRES, PCG, the GMG preconditioner, a fixed level count) buckets
+// the problems by size; each bucket is an ordinary batched problem set (its own context,
+// workspace and HIP stream at the default priority).  Setup gathers the coefficients of a bucket
+// into one contiguous batch; solve gathers f and u, runs the buckets' solves concurrently (one
+// host thread per bucket, since a solve blocks its thread at every host check) and scatters u
+// back.  Per problem the arithmetic is that of a batch of one on either path.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +19,7 @@
 #include <vector>
 
 #include "../../include/mgcnn.h"
+#include "mgcnn_ladder.h"
 
 namespace {
 
@@ -36,6 +42,7 @@ struct mgcnn_group {
   hipEvent_t ready = nullptr;
   std::vector<Bucket> buckets;
   int count = 0;
+  mg::Ladder* lad = nullptr;         // aligned levels (stationary network iteration)
   std::string err;
 };
 
@@ -97,6 +104,18 @@ int mgcnn_group_create(mgcnn_group** group, const mgcnn_opts* opts, const float*
     delete g;
     return MGCNN_E_HIP;
   }
+  if (mg::ladder_supported(o)) {
+    g->lad = new (std::nothrow) mg::Ladder();
+    if (!g->lad) { (void)hipEventDestroy(g->ready); delete g; return MGCNN_E_NOMEM; }
+    r = mg::ladder_create(g->lad, o, g->weights.data());
+    if (r != MGCNN_OK) {
+      mg::ladder_free(g->lad);
+      delete g->lad;
+      (void)hipEventDestroy(g->ready);
+      delete g;
+      return r;
+    }
+  }
   *group = g;
   return MGCNN_OK;
 }
@@ -108,6 +127,13 @@ int mgcnn_group_setup(mgcnn_group* g, const float* const* a, const float* b_host
   for (int i = 0; i < count; ++i)
     if (!a[i]) return gfail(g, MGCNN_E_ARG, "group_setup: null coefficient pointer");
   free_buckets(g);
+  if (g->lad) {
+    g->count = 0;
+    int r = mg::ladder_setup(g->lad, a, b_host, n_host, count, g->user);
+    if (r != MGCNN_OK) return gfail(g, r, g->lad->err);
+    g->count = count;
+    return MGCNN_OK;
+  }
   std::map<int, std::vector<int>> by_n;
   for (int i = 0; i < count; ++i) by_n[n_host[i]].push_back(i);
   for (auto& kv : by_n) {
@@ -153,11 +179,18 @@ int mgcnn_group_setup(mgcnn_group* g, const float* const* a, const float* b_host
 int mgcnn_group_solve(mgcnn_group* g, const float* const* f, void* const* u, double tol, int maxit,
                       int* iters_host, double* relres_host, int* status_host) {
   if (!g) return MGCNN_E_ARG;
-  if (g->buckets.empty()) return gfail(g, MGCNN_E_STATE, "group_solve: call mgcnn_group_setup first");
+  if (g->lad ? !g->lad->ready : g->buckets.empty())
+    return gfail(g, MGCNN_E_STATE, "group_solve: call mgcnn_group_setup first");
   if (!f || !u) return gfail(g, MGCNN_E_ARG, "group_solve: null pointer");
   for (int i = 0; i < g->count; ++i)
     if (!f[i] || !u[i]) return gfail(g, MGCNN_E_ARG, "group_solve: null problem pointer");
   if (!(tol > 0.0) || maxit < 0) return gfail(g, MGCNN_E_ARG, "group_solve: need tol > 0 and maxit >= 0");
+  if (g->lad) {
+    if (!g->lad->ready) return gfail(g, MGCNN_E_STATE, "group_solve: call mgcnn_group_setup first");
+    int r = mg::ladder_solve(g->lad, f, u, tol, maxit, iters_host, relres_host, status_host, g->user);
+    if (r != MGCNN_OK && r != MGCNN_NOT_CONVERGED) return gfail(g, r, g->lad->err);
+    return r;
+  }
   int r = wait_user(g);
   if (r) return r;
   const size_t ub = u_bytes(g);
@@ -216,13 +249,34 @@ int mgcnn_group_solve(mgcnn_group* g, const float* const* f, void* const* u, dou
   return MGCNN_OK;
 }
 
-int mgcnn_group_buckets(const mgcnn_group* g) { return g ? (int)g->buckets.size() : 0; }
+int mgcnn_group_buckets(const mgcnn_group* g) {
+  if (!g) return 0;
+  if (g->lad) {
+    int sizes = 0;
+    for (int j = 0; j < g->lad->J; ++j) sizes += g->lad->c(j) > 0;
+    return g->lad->ready ? sizes : 0;
+  }
+  return (int)g->buckets.size();
+}
+
+int mgcnn_group_completion_times(const mgcnn_group* g, double* seconds_host) {
+  if (!g || !seconds_host) return MGCNN_E_ARG;
+  if (!g->lad || (int)g->lad->completion_s.size() != g->count || g->count == 0) return MGCNN_E_STATE;
+  std::copy(g->lad->completion_s.begin(), g->lad->completion_s.end(), seconds_host);
+  return MGCNN_OK;
+}
+
+int mgcnn_group_aligned(const mgcnn_group* g) { return g && g->lad ? 1 : 0; }
 
 const char* mgcnn_group_last_error(const mgcnn_group* g) { return g ? g->err.c_str() : "null group"; }
 
 void mgcnn_group_destroy(mgcnn_group* g) {
   if (!g) return;
   free_buckets(g);
+  if (g->lad) {
+    mg::ladder_free(g->lad);
+    delete g->lad;
+  }
   if (g->ready) (void)hipEventDestroy(g->ready);
   delete g;
 }

@@ -82,8 +82,14 @@ void launch_residual(const float* a, const float* b, const float* f, const void*
 // Per-problem stop test (one workgroup per problem).  On entry iters[b] = k of the current
 // iterate.  Computes rho_k = sqrt(sum partial)/sqrt(nf2).  If nf2 is zero, rho = 0.
 // Sets active/status/iters/relres following the solver's stopping rule.
+// done_clock (optional): the device wall clock (wall_clock64) at which a problem stops.
 void launch_finalize(const double* partial, int tiles, const double* nf2, double tol, int maxit,
-                     int* active, int* status, int* iters, double* relres, int B, hipStream_t st);
+                     int* active, int* status, int* iters, double* relres, int B, hipStream_t st,
+                     long long* done_clock = nullptr);
+// out[0] = the device wall clock (wall_clock64) when the kernel runs.
+void launch_clock_stamp(long long* out, hipStream_t st);
+// u = 0 for the problems whose ||f||^2 is zero.
+void launch_zero_if_zero_rhs(void* u, bool u_f64, const double* nf2, int n, int B, hipStream_t st);
 
 // nf2[b] = sum of partials (the squared norm of f), deterministic order.
 void launch_sum_partials(const double* partial, int tiles, double* out, int B, hipStream_t st);

@@ -90,6 +90,8 @@ EXPORTS = {
                                          ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]),
     "mgcnn_group_buckets": (ctypes.c_int, [ctypes.c_void_p]),
+    "mgcnn_group_aligned": (ctypes.c_int, [ctypes.c_void_p]),
+    "mgcnn_group_completion_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mgcnn_group_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "mgcnn_group_destroy": (None, [ctypes.c_void_p]),
     "mgcnn_residual_norms_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
@@ -363,14 +365,18 @@ class Solver:
 
 
 class GroupSolver:
-    """Problems of different sizes in one call (mgcnn_group_*): bucketed by size, one batched
-    problem set per size on its own stream, buckets solved concurrently."""
+    """Problems of different sizes in one call (mgcnn_group_*).  The stationary iteration with
+    the network (levels <= 0) runs on aligned levels: one stream, one launch per operation and
+    level size over the whole mixed batch, optionally hipGraph-captured (use_graph).  Other
+    configurations bucket the problems by size, one batched problem set per size on its own
+    stream, buckets solved concurrently."""
 
     def __init__(self, weights, state: str = "f32", u: str = "f64", method: str = "stationary",
                  restart: int = 30, check_every: int = 4, f32_split: bool | int = True, s_bf16: bool = False,
                  inner_steps: int = 1, gs_passes: int = 2, stream=None, precond: str = "network",
                  gmg_levels: int = 0, gmg_sweeps: int = 3, gmg_omega: float = 0.67,
-                 form: str = "div", deflate: int = 0, levels: int = 0, up_post: bool = False):
+                 form: str = "div", deflate: int = 0, levels: int = 0, up_post: bool = False,
+                 use_graph: bool = False):
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -389,6 +395,7 @@ class GroupSolver:
         o.deflate = int(deflate)
         o.levels = int(levels)
         o.up_post = int(bool(up_post))
+        o.use_graph = int(bool(use_graph))
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         wp = _weights_ptr(self, weights, self._L.mgcnn_num_weights(16))
         self._stream = stream if stream is not None else torch.cuda.current_stream()
@@ -440,6 +447,19 @@ class GroupSolver:
     @property
     def buckets(self) -> int:
         return self._L.mgcnn_group_buckets(self._h)
+
+    @property
+    def aligned(self) -> bool:
+        """True when the group runs on aligned levels (one stream, one launch per operation and
+        level size), False on per-size buckets."""
+        return bool(self._L.mgcnn_group_aligned(self._h))
+
+    def completion_times(self):
+        """Seconds from the start of the last solve's iterations to each problem's stop (device
+        wall clock); aligned levels only."""
+        out = np.zeros(self.count, np.float64)
+        self._raise(self._L.mgcnn_group_completion_times(self._h, out.ctypes.data))
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

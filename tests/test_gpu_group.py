@@ -66,6 +66,82 @@ def test_group_matches_individual_solves(method, maxit):
     G.close()
 
 
+@pytest.mark.parametrize("state,levels,graph", [("f32", 0, True), ("f32", -1, False), ("bf16", 0, True)])
+def test_aligned_levels_match_individual_solves(state, levels, graph):
+    """The aligned-level path (stationary network iteration: one stream, one launch per operation
+    and level size) against solving every problem on its own: bitwise the same iterates, counts
+    and residuals, with hipGraph-captured blocks, with the paper's level count (coarsest 3 x 3)
+    and with bf16 state (setup through f32 temporaries).  A zero right-hand side gives u = 0.
+    Device completion times: zero for the zero right-hand side, positive otherwise, and not
+    decreasing with the iteration count among problems that stopped at different iterations."""
+    sizes = [31, 127, 15, 63, 127, 7, 31, 63]
+    say("aligned", state, levels, graph, sizes)
+    ps = problems(sizes, seed=5)
+    ps[2].f[:] = 0.0
+    w = vcycle_weights()
+    G = GroupSolver(w, state=state, u="f64", method="stationary", check_every=3, levels=levels,
+                    use_graph=graph)
+    assert G.aligned
+    a = [dev(p.a) for p in ps]
+    f = [dev(p.f) for p in ps]
+    b = np.stack([p.b for p in ps])
+    G.setup(a, b)
+    assert G.buckets == len(set(sizes))
+    u = [torch.zeros((p.n, p.n), dtype=torch.float64, device="cuda") for p in ps]
+    maxit = 18
+    st, it, rr, stat = G.solve(f, u, 1e-8, maxit)
+    ct = G.completion_times()
+    say("  iters", list(it), "status", list(stat), "completion s", [round(x, 5) for x in ct])
+    for i, p in enumerate(ps):
+        S = Solver(w, state=state, u="f64", method="stationary", check_every=3, levels=levels)
+        S.setup(a[i].view(1, p.n, p.n), b[i:i + 1])
+        ui = torch.zeros((1, p.n, p.n), dtype=torch.float64, device="cuda")
+        _, it1, rr1, st1 = S.solve(f[i].view(1, p.n, p.n), ui, 1e-8, maxit)
+        S.close()
+        assert int(it1[0]) == int(it[i]) and int(st1[0]) == int(stat[i]), (i, it1, it[i])
+        assert torch.equal(ui[0], u[i]), i
+        assert rr1[0] == rr[i]
+    assert bool((u[2] == 0).all()) and ct[2] == 0.0 and stat[2] == M.OK
+    live = [i for i in range(len(ps)) if i != 2]
+    assert all(ct[i] > 0 for i in live)
+    order = sorted(live, key=lambda i: int(it[i]))
+    for x, y in zip(order, order[1:]):
+        if int(it[x]) < int(it[y]):
+            assert ct[x] <= ct[y], (x, y, ct[x], ct[y])
+    G.close()
+
+
+def test_aligned_levels_solve_twice_and_resetup():
+    """Two solves on one setup (the captured graph is replayed with eager work between) give the
+    same result; a new setup with other sizes gives the individual results again."""
+    say("aligned: repeat and re-setup")
+    w = vcycle_weights()
+    G = GroupSolver(w, state="f32", u="f64", method="stationary", check_every=4, use_graph=True)
+    for sizes in ([63, 15, 31, 63], [127, 7, 255]):
+        ps = problems(sizes, seed=9)
+        a = [dev(p.a) for p in ps]
+        f = [dev(p.f) for p in ps]
+        b = np.stack([p.b for p in ps])
+        G.setup(a, b)
+        outs = []
+        for rep in range(2):
+            u = [torch.zeros((p.n, p.n), dtype=torch.float64, device="cuda") for p in ps]
+            st, it, rr, stat = G.solve(f, u, 1e-8, 12)
+            torch.cuda.synchronize()
+            outs.append((it.copy(), rr.copy(), [x.clone() for x in u]))
+            _ = torch.ones(1000, device="cuda").sum().item()     # eager work between replays
+        assert (outs[0][0] == outs[1][0]).all() and (outs[0][1] == outs[1][1]).all()
+        assert all(torch.equal(x, y) for x, y in zip(outs[0][2], outs[1][2]))
+        for i, p in enumerate(ps):
+            S = Solver(w, state="f32", u="f64", method="stationary", check_every=4)
+            S.setup(a[i].view(1, p.n, p.n), b[i:i + 1])
+            ui = torch.zeros((1, p.n, p.n), dtype=torch.float64, device="cuda")
+            _, it1, _, _ = S.solve(f[i].view(1, p.n, p.n), ui, 1e-8, 12)
+            S.close()
+            assert int(it1[0]) == int(outs[0][0][i]) and torch.equal(ui[0], outs[0][2][i])
+    G.close()
+
+
 def test_group_rejects_bad_sizes():
     say("group bad sizes")
     G = GroupSolver(vcycle_weights())
