@@ -482,6 +482,8 @@ def main():
                     help="FGMRES deflated restarts: directions kept across a restart (0 = plain)")
     ap.add_argument("--no-gmg", action="store_true",
                     help="skip the geometric multigrid baseline (FGMRES(63), same batch)")
+    ap.add_argument("--no-tuning", action="store_true",
+                    help="keep the default tile of every convolution (no autotuned table)")
     ap.add_argument("--levels", type=int, default=0,
                     help="network levels: 0 = log2(n+1), -1 = the count of Sec. 4.1, ...")
     ap.add_argument("--no-legs", action="store_true",
@@ -497,6 +499,9 @@ def main():
     import torch
     import datagen
     from paper_2312_11093_amd import Solver
+
+    from paper_2312_11093_amd import autotune
+    tuned = 0 if args.no_tuning else autotune.load()
 
     n, B = args.n, args.batch
     weights, wsrc = load_weights(args.weights)
@@ -698,7 +703,9 @@ def main():
                    "gs_passes": args.gs_passes if args.method == "fgmres" else None,
                    "deflate": dfl if args.method == "fgmres" else None,
                    "state": args.state, "f32_split": args.f32_split if args.state == "f32" else None,
-                   "u": "f64", "weights": wsrc, "parallelism": "single GPU"},
+                   "u": "f64", "weights": wsrc, "parallelism": "single GPU",
+                   "tile_variants": (f"{tuned} autotuned entries "
+                                     f"({os.path.relpath(autotune.DEFAULT_FILE, ROOT)})" if tuned else "defaults")},
         "converged": converged, "mean_iters": mean_iters, "max_iters": int(np.max(its[-1])),
         "ms_per_stationary_iteration": round(iter_ms, 3),
         "oracle_relres_sampled": check,

@@ -308,6 +308,26 @@ int mgcnn_residual_norms_noalloc(const float *a, const float *b_host, int n, int
                                  int op_form, const float *f, const void *u, int u_dtype,
                                  double *relres_host, void *hip_stream);
 
+/* ---- Tile shapes (autotuning) ------------------------------------------------------------
+ * The 16 -> 16 convolutions come in tile variants that differ only in the number of output rows
+ * per workgroup (variant 0 = the default); the per-pixel arithmetic and its order are the same,
+ * so every variant gives the same results bit for bit.  A process-wide table selects the variant
+ * per operation, storage precision and level side m (levels of equal side share an entry).
+ * paper_2312_11093_amd/autotune.py times the variants on the device and stores the fastest per
+ * entry in a JSON file keyed by architecture; loading it fills this table.  Not thread-safe with
+ * launches in flight on other host threads. */
+enum { MGCNN_TILE_SMOOTHER = 0,   /* down and up smoothers (Alg. 3) */
+       MGCNN_TILE_RESTRICT = 1,   /* stride-2 restriction (RCNN) */
+       MGCNN_TILE_SETUP = 2 };    /* tanh layers of the setup network (Alg. 2; f32 only) */
+#define MGCNN_TILE_VARIANTS 3
+/* Select `variant` (0 .. MGCNN_TILE_VARIANTS - 1) for operation `op`, state_dtype MGCNN_F32 or
+ * MGCNN_BF16 and level side m (1..4095); MGCNN_E_ARG on a bad argument. */
+int mgcnn_set_tile_variant(int op, int state_dtype, int m, int variant);
+/* The selected variant, or MGCNN_E_ARG. */
+int mgcnn_tile_variant(int op, int state_dtype, int m);
+/* Output rows per workgroup of a variant, or MGCNN_E_ARG. */
+int mgcnn_tile_rows(int op, int state_dtype, int variant);
+
 /* Number of levels of the current problem set (0 before setup). */
 int mgcnn_levels(const mgcnn_ctx *ctx);
 

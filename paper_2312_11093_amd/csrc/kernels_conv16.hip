@@ -278,25 +278,26 @@ struct Chunk<ST_BF16> {
 
 // ------------------------------------------------------------------------------------------
 // same-size conv: smoother (s given) or tanh ResNet layer (bias given)
-// Tile: 8 output rows x TW columns (TW = 32 for f32, 64 for bf16); each wave owns two rows.
+// Tile: TH output rows (8 by default; 4 or 16 as tile variants) x TW columns (TW = 32 for f32,
+// 64 for bf16); each wave owns TH / 4 rows.
 // ------------------------------------------------------------------------------------------
-template <int ST>
+template <int ST, int THV = 8>
 struct SameCfg {
-  static constexpr int TH = 8, TW = (ST == ST_BF16) ? 64 : 32;
+  static constexpr int TH = THV, TW = (ST == ST_BF16) ? 64 : 32;
   static constexpr int IR = TH + 2, IC = TW + 2, NPIX = IR * IC;
   static constexpr int NCHUNK = NPIX * Chunk<ST>::CPP, NPT = (NCHUNK + 255) / 256;
   static constexpr int NSEG = TW / 16, NTASK = TH * NSEG, TPW = NTASK / 4;
 };
 
 // SBF: s stored as bf16 while the state is f32 (f32 storage only; the bf16 state has bf16 s).
-template <int ST, int MODE, bool SBF = false>
+template <int ST, int MODE, bool SBF = false, int TH = 8>
 __global__ __launch_bounds__(256) void conv16_same_kernel(
     const typename Frag<ST>::elem* __restrict__ x, const void* __restrict__ s,
     const float* __restrict__ W, const float* __restrict__ bias,
     typename Frag<ST>::elem* __restrict__ y, int m, int tiles_x, int tiles_per_prob,
     const int* __restrict__ active) {
   typedef typename Frag<ST>::elem E;
-  typedef SameCfg<ST> K;
+  typedef SameCfg<ST, TH> K;
   typedef Chunk<ST> CK;
   constexpr int PSTR = K::NPIX * PS;                  // LDS plane stride
   __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];
@@ -389,9 +390,9 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
 // Tile: TH coarse rows (4 for f32, 8 for bf16) x 32 coarse columns.  Columns of the staged
 // fine tile are de-interleaved by parity so that the stride-2 operand reads stay consecutive.
 // ------------------------------------------------------------------------------------------
-template <int ST>
+template <int ST, int THV = 0>
 struct RsCfg {
-  static constexpr int TH = (ST == ST_BF16) ? 8 : 4, TW = 32;
+  static constexpr int TH = THV ? THV : ((ST == ST_BF16) ? 8 : 4), TW = 32;
   static constexpr int IR = 2 * TH + 1, IC = 2 * TW + 1, HALF = TW + 1, ROW = 2 * HALF;
   static constexpr int NPIX = IR * IC, NCHUNK = NPIX * Chunk<ST>::CPP, NPT = (NCHUNK + 255) / 256;
   static constexpr int NSEG = TW / 16, NTASK = TH * NSEG, TPW = NTASK / 4;
@@ -400,13 +401,13 @@ struct RsCfg {
 template <int HALF>
 __device__ __forceinline__ int rs_slot(int lc) { return (lc & 1) ? HALF + (lc >> 1) : (lc >> 1); }
 
-template <int ST>
+template <int ST, int TH = 0>
 __global__ __launch_bounds__(256) void conv16_restrict_kernel(
     const typename Frag<ST>::elem* __restrict__ x, const float* __restrict__ W,
     typename Frag<ST>::elem* __restrict__ y, int m, int mo, int tiles_x, int tiles_per_prob,
     const int* __restrict__ active) {
   typedef typename Frag<ST>::elem E;
-  typedef RsCfg<ST> K;
+  typedef RsCfg<ST, TH> K;
   typedef Chunk<ST> CK;
   constexpr int PSTR = K::IR * K::ROW * PS;           // LDS plane stride
   __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];
@@ -708,29 +709,79 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
 // ------------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------------
+// ---- tile variants (autotuning) ----------------------------------------------------------
+// Rows of the output tile per variant: variant 0 is the default shape.  Variant tables per
+// (operation, storage, level side) are set through mgcnn_set_tile_variant (process-wide); the
+// per-pixel arithmetic and its order do not depend on the tile, so every variant gives the same
+// results bit for bit.
+constexpr int SAME_ROWS[TILE_VARIANTS] = {8, 4, 16};
+constexpr int RS_ROWS_F32[TILE_VARIANTS] = {4, 2, 8};
+constexpr int RS_ROWS_BF16[TILE_VARIANTS] = {8, 4, 16};
+static int g_tile_variant[TILE_OPS][2][13] = {};     // [op][bf16 storage][log2(m + 1)]
+
+static int lg2p1(int m) {
+  int p = 0;
+  while ((1 << p) < m + 1 && p < 12) ++p;
+  return p;
+}
+
+int tile_variant_rows(int op, bool bf16, int v) {
+  if (v < 0 || v >= TILE_VARIANTS) return 0;
+  if (op == TILE_RESTRICT) return bf16 ? RS_ROWS_BF16[v] : RS_ROWS_F32[v];
+  return SAME_ROWS[v];
+}
+int get_tile_variant(int op, bool bf16, int m) { return g_tile_variant[op][bf16 ? 1 : 0][lg2p1(m)]; }
+void set_tile_variant(int op, bool bf16, int m, int v) { g_tile_variant[op][bf16 ? 1 : 0][lg2p1(m)] = v; }
+
+template <int ST, int MODE, bool SBF, int TH>
+static void same_launch(const void* x, const void* s, const float* W, const float* bias, void* y, int m,
+                        int B, const int* active, hipStream_t st) {
+  typedef typename Frag<ST>::elem E;
+  typedef SameCfg<ST, TH> K;
+  const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
+  hipLaunchKernelGGL((conv16_same_kernel<ST, MODE, SBF, TH>), dim3(tx * ty * B), dim3(256), 0, st,
+                     (const E*)x, s, W, bias, (E*)y, m, tx, tx * ty, active);
+}
+
+template <int ST, int MODE, bool SBF>
+static void same_variant(int v, const void* x, const void* s, const float* W, const float* bias, void* y,
+                         int m, int B, const int* active, hipStream_t st) {
+  if (v == 1) same_launch<ST, MODE, SBF, 4>(x, s, W, bias, y, m, B, active, st);
+  else if (v == 2) same_launch<ST, MODE, SBF, 16>(x, s, W, bias, y, m, B, active, st);
+  else same_launch<ST, MODE, SBF, 8>(x, s, W, bias, y, m, B, active, st);
+}
+
+template <int ST, int TH>
+static void restrict_launch(const void* x, const float* W, void* y, int m, int B, const int* active,
+                            hipStream_t st) {
+  typedef typename Frag<ST>::elem E;
+  typedef RsCfg<ST, TH> K;
+  const int mo = (m - 1) / 2;
+  const int tx = (mo + K::TW - 1) / K::TW, ty = (mo + K::TH - 1) / K::TH;
+  hipLaunchKernelGGL((conv16_restrict_kernel<ST, TH>), dim3(tx * ty * B), dim3(256), 0, st, (const E*)x, W,
+                     (E*)y, m, mo, tx, tx * ty, active);
+}
+
 template <int ST, bool SBF = false>
 static void conv16_launch(ConvMode mode, const void* x, const void* s, const float* W, const float* bias,
                           void* y, int m, int B, const int* active, hipStream_t st) {
-  typedef typename Frag<ST>::elem E;
+  constexpr bool BF = ST == ST_BF16;
   if (mode == CM_RESTRICT) {
-    typedef RsCfg<ST> K;
-    const int mo = (m - 1) / 2;
-    const int tx = (mo + K::TW - 1) / K::TW, ty = (mo + K::TH - 1) / K::TH;
-    hipLaunchKernelGGL(conv16_restrict_kernel<ST>, dim3(tx * ty * B), dim3(256), 0, st, (const E*)x, W,
-                       (E*)y, m, mo, tx, tx * ty, active);
+    const int v = get_tile_variant(TILE_RESTRICT, BF, m);
+    constexpr int R1 = BF ? RS_ROWS_BF16[1] : RS_ROWS_F32[1], R2 = BF ? RS_ROWS_BF16[2] : RS_ROWS_F32[2];
+    if (v == 1) restrict_launch<ST, R1>(x, W, y, m, B, active, st);
+    else if (v == 2) restrict_launch<ST, R2>(x, W, y, m, B, active, st);
+    else restrict_launch<ST, 0>(x, W, y, m, B, active, st);
     return;
   }
-  typedef SameCfg<ST> K;
-  const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
   if (mode == CM_SMOOTH)
-    hipLaunchKernelGGL((conv16_same_kernel<ST, CM_SMOOTH, SBF>), dim3(tx * ty * B), dim3(256), 0, st,
-                       (const E*)x, s, W, bias, (E*)y, m, tx, tx * ty, active);
+    same_variant<ST, CM_SMOOTH, SBF>(get_tile_variant(TILE_SMOOTHER, BF, m), x, s, W, bias, y, m, B, active, st);
   else if (mode == CM_SMOOTH_POST)
-    hipLaunchKernelGGL((conv16_same_kernel<ST, CM_SMOOTH_POST, SBF>), dim3(tx * ty * B), dim3(256), 0, st,
-                       (const E*)x, s, W, bias, (E*)y, m, tx, tx * ty, active);
+    same_variant<ST, CM_SMOOTH_POST, SBF>(get_tile_variant(TILE_SMOOTHER, BF, m), x, s, W, bias, y, m, B,
+                                          active, st);
   else if constexpr (ST != ST_BF16 && !SBF)
-    hipLaunchKernelGGL((conv16_same_kernel<ST, CM_TANH>), dim3(tx * ty * B), dim3(256), 0, st,
-                       (const E*)x, (const void*)nullptr, W, bias, (E*)y, m, tx, tx * ty, active);
+    same_variant<ST, CM_TANH, false>(get_tile_variant(TILE_SETUP, BF, m), x, nullptr, W, bias, y, m, B,
+                                     active, st);
 }
 
 void launch_conv16(ConvMode mode, StateType st_, const void* x, const void* s, const float* W,

@@ -664,6 +664,29 @@ const char* mgcnn_status_string(int s) {
 
 const char* mgcnn_last_error(const mgcnn_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+static bool tile_args_ok(int op, int state_dtype) {
+  return op >= 0 && op < TILE_OPS && (state_dtype == MGCNN_F32 || state_dtype == MGCNN_BF16);
+}
+
+int mgcnn_set_tile_variant(int op, int state_dtype, int m, int variant) {
+  if (!tile_args_ok(op, state_dtype) || variant < 0 || variant >= TILE_VARIANTS || m < 1 || m > 4095)
+    return MGCNN_E_ARG;
+  if (op == TILE_SETUP && state_dtype == MGCNN_BF16) return MGCNN_E_ARG;   // the setup runs in f32
+  set_tile_variant(op, state_dtype == MGCNN_BF16, m, variant);
+  return MGCNN_OK;
+}
+
+int mgcnn_tile_variant(int op, int state_dtype, int m) {
+  if (!tile_args_ok(op, state_dtype) || m < 1 || m > 4095) return MGCNN_E_ARG;
+  return get_tile_variant(op, state_dtype == MGCNN_BF16, m);
+}
+
+int mgcnn_tile_rows(int op, int state_dtype, int variant) {
+  if (!tile_args_ok(op, state_dtype)) return MGCNN_E_ARG;
+  const int r = tile_variant_rows(op, state_dtype == MGCNN_BF16, variant);
+  return r > 0 ? r : MGCNN_E_ARG;
+}
+
 void mgcnn_destroy(mgcnn_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();

@@ -56,6 +56,14 @@ void launch_conv16(ConvMode mode, StateType t, const void* x, const void* s, con
                    const float* bias, void* y, int m, int B, const int* active, hipStream_t st,
                    bool s_bf16 = false);
 
+// Tile variants of the 16 -> 16 convolutions (process-wide table, autotuning): op = TILE_SMOOTHER
+// (down / up smoothers), TILE_RESTRICT, TILE_SETUP (tanh layers); variant 0 = the default tile.
+enum TileOp : int { TILE_SMOOTHER = 0, TILE_RESTRICT = 1, TILE_SETUP = 2, TILE_OPS = 3 };
+constexpr int TILE_VARIANTS = 3;
+int tile_variant_rows(int op, bool bf16, int variant);
+int get_tile_variant(int op, bool bf16, int m);
+void set_tile_variant(int op, bool bf16, int m, int variant);
+
 // y_fine += convT_{stride 2}(W_T, x_coarse), fine side m = 2 mc + 1, in place on y_fine.
 void launch_prolong_add(StateType t, const void* xc, const float* WT, void* yf, int mc, int B,
                         const int* active, hipStream_t st);

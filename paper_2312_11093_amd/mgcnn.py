@@ -94,6 +94,9 @@ EXPORTS = {
     "mgcnn_group_completion_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mgcnn_group_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "mgcnn_group_destroy": (None, [ctypes.c_void_p]),
+    "mgcnn_set_tile_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "mgcnn_tile_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "mgcnn_tile_rows": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "mgcnn_residual_norms_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                                     ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                                     ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,

@@ -76,6 +76,24 @@ def test_noalloc_argument_errors_before_device_work(lib):
     assert b"scratch" in lib.mgcnn_status_string(-8)
 
 
+def test_tile_variant_table(lib):
+    """Host-only: the tile-variant table (autotuning) accepts valid entries, rejects bad ones and
+    reports the rows of every variant."""
+    for fn in ("mgcnn_set_tile_variant", "mgcnn_tile_variant", "mgcnn_tile_rows"):
+        getattr(lib, fn).restype = ctypes.c_int
+    assert lib.mgcnn_tile_rows(0, 0, 0) == 8 and lib.mgcnn_tile_rows(0, 0, 1) == 4
+    assert lib.mgcnn_tile_rows(1, 0, 0) == 4 and lib.mgcnn_tile_rows(1, 1, 0) == 8
+    assert lib.mgcnn_tile_rows(0, 0, 3) == -1 and lib.mgcnn_tile_rows(5, 0, 0) == -1
+    assert lib.mgcnn_tile_variant(0, 0, 255) == 0
+    assert lib.mgcnn_set_tile_variant(0, 0, 255, 2) == 0
+    assert lib.mgcnn_tile_variant(0, 0, 255) == 2 and lib.mgcnn_tile_variant(0, 0, 511) == 0
+    assert lib.mgcnn_set_tile_variant(0, 0, 255, 0) == 0
+    assert lib.mgcnn_set_tile_variant(0, 0, 255, 3) == -1        # no such variant
+    assert lib.mgcnn_set_tile_variant(0, 2, 255, 0) == -1        # bad storage
+    assert lib.mgcnn_set_tile_variant(2, 1, 255, 0) == -1        # the setup runs in f32
+    assert lib.mgcnn_set_tile_variant(0, 0, 0, 0) == -1          # bad side
+
+
 def test_no_oracle_in_product_path():
     """The product package never imports the oracle."""
     pkg = os.path.join(ROOT, "paper_2312_11093_amd")
