@@ -316,9 +316,11 @@ int mgcnn_residual_norms_noalloc(const float *a, const float *b_host, int n, int
  * paper_2312_11093_amd/autotune.py times the variants on the device and stores the fastest per
  * entry in a JSON file keyed by architecture; loading it fills this table.  Not thread-safe with
  * launches in flight on other host threads. */
-enum { MGCNN_TILE_SMOOTHER = 0,   /* down and up smoothers (Alg. 3) */
+enum { MGCNN_TILE_SMOOTHER = 0,   /* down (coarser levels) and up smoothers (Alg. 3) */
        MGCNN_TILE_RESTRICT = 1,   /* stride-2 restriction (RCNN) */
-       MGCNN_TILE_SETUP = 2 };    /* tanh layers of the setup network (Alg. 2; f32 only) */
+       MGCNN_TILE_SETUP = 2,      /* tanh layers of the setup network (Alg. 2; f32 only) */
+       MGCNN_TILE_SMOOTH_IN = 3,  /* finest down smoother with the reChannel-in conv folded in */
+       MGCNN_TILE_PROLONG = 4 };  /* transposed-conv prolongation (TCNN), keyed by the fine side */
 #define MGCNN_TILE_VARIANTS 3
 /* Select `variant` (0 .. MGCNN_TILE_VARIANTS - 1) for operation `op`, state_dtype MGCNN_F32 or
  * MGCNN_BF16 and level side m (1..4095); MGCNN_E_ARG on a bad argument. */

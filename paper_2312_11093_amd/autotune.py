@@ -12,8 +12,8 @@ library's table from it.
     python -m paper_2312_11093_amd.autotune --out paper_2312_11093_amd/tuning/gfx950.json [--state f32]
 
 Operations tuned: the smoothers (down smoother on the coarser levels and up smoother on every
-level share one table) and the restriction.  The finest down smoother (reChannel-in folded in),
-the prolongation and the setup network keep their tiles.
+level share one table), the restriction, the finest down smoother (reChannel-in folded in) and the
+prolongation (keyed by its fine side).  The setup network keeps its tiles.
 """
 from __future__ import annotations
 
@@ -30,12 +30,14 @@ ROOT = os.path.dirname(HERE)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-OPS = {"smoother": 0, "restrict": 1, "setup": 2}
+OPS = {"smoother": 0, "restrict": 1, "setup": 2, "smooth_in": 3, "prolong": 4}
 VARIANTS = 3
 STATES = {"f32": 0, "bf16": 1}
 # profiled kernel kinds -> tuned operation (level 0 of the down smoother is the separate
 # reChannel-in kernel)
-KIND_OP = {"smooth_down": "smoother", "smooth_up": "smoother", "restrict": "restrict"}
+KIND_OP = {"smooth_down": "smoother", "smooth_up": "smoother", "restrict": "restrict",
+           "smooth_in": "smooth_in", "prolong": "prolong"}
+TUNED = ("smoother", "restrict", "smooth_in", "prolong")
 DEFAULT_FILE = os.path.join(HERE, "tuning", "gfx950.json")
 
 
@@ -72,7 +74,7 @@ def tune(n: int = 1023, batch: int = 64, state: str = "f32", workload: str = "bl
         m = (m - 1) // 2
     times = {}                                        # (op, side, variant) -> ms per launch
     for v in range(VARIANTS):
-        for op in ("smoother", "restrict"):
+        for op in TUNED:
             set_all(L, op, state, v)
         S.forward(df, u, 1)                           # warm-up of this variant's kernels
         best = {}
@@ -84,20 +86,21 @@ def tune(n: int = 1023, batch: int = 64, state: str = "f32", workload: str = "bl
                 op = KIND_OP.get(st["kind"])
                 if op is None or (st["kind"] == "smooth_down" and st["level"] == 0):
                     continue
+                # the prolongation into level l is keyed by that level's (fine) side
                 key = (op, sides[st["level"]])
                 per = st["ms_total"] / st["launches"]
                 best.setdefault(key, []).append(per)
         for (op, side), vals in best.items():
             times[(op, side, v)] = float(np.min(vals))
         log(json.dumps({"variant": v, "rows": {op: L.mgcnn_tile_rows(OPS[op], STATES[state], v)
-                                               for op in ("smoother", "restrict")},
+                                               for op in TUNED},
                         "ms": {f"{op}@{side}": round(times[(op, side, v)], 4)
                                for (op, side, vv) in times if vv == v}}))
     S.close()
-    for op in ("smoother", "restrict"):
+    for op in TUNED:
         set_all(L, op, state, 0)
     entries = []
-    for op in ("smoother", "restrict"):
+    for op in TUNED:
         for side in sides:
             cand = [(times[(op, side, v)], v) for v in range(VARIANTS) if (op, side, v) in times]
             if not cand:

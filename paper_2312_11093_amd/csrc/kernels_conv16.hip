@@ -472,18 +472,20 @@ __global__ __launch_bounds__(256) void conv16_restrict_kernel(
 // Fine pixel (i, j) receives coarse (I, J) through tap (p, q) with 2I + p = i, 2J + q = j:
 // odd i uses p = 1 only, even i uses p = 0 (I = i/2) and p = 2 (I = i/2 - 1); same for j.
 // Work is split into row segments of 16 fine pixels of equal column parity, so every lane
-// of one MFMA uses the same tap.  Tile: 4 x 32 coarse pixels = 8 x 64 fine pixels.
+// of one MFMA uses the same tap.  Tile: PL_CH x 32 coarse pixels = 2 PL_CH x 64 fine pixels
+// (PL_CH = 4 by default; 2 or 8 as tile variants); each wave owns PL_CH / 2 fine rows.
 // ------------------------------------------------------------------------------------------
-constexpr int PL_CH = 4, PL_CW = 32;                  // coarse tile
-constexpr int PL_IR = PL_CH + 1, PL_IC = PL_CW + 1;   // staged coarse rows/cols (one halo)
+constexpr int PL_CW = 32;                             // coarse tile columns
 
-template <int ST>
+template <int ST, int PL_CH = 4>
 __global__ __launch_bounds__(256) void prolong_add_kernel(
     const typename Frag<ST>::elem* __restrict__ xc, const float* __restrict__ WT,
     typename Frag<ST>::elem* __restrict__ yf, int mc, int tiles_x, int tiles_per_prob,
     const int* __restrict__ active) {
   typedef typename Frag<ST>::elem E;
   typedef Chunk<ST> CK;
+  constexpr int PL_IR = PL_CH + 1, PL_IC = PL_CW + 1;   // staged coarse rows/cols (one halo)
+  constexpr int FRW = PL_CH / 2, NT = 4 * FRW;          // fine rows and segments per wave
   constexpr int NPIX = PL_IR * PL_IC, NCHUNK = NPIX * CK::CPP, NPT = (NCHUNK + 255) / 256;
   constexpr int PSTR = NPIX * PS;                     // LDS plane stride
   __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];
@@ -496,11 +498,11 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
   E* Fb = yf + (size_t)b * m * m * C;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int px = lane & 15, g = lane >> 4;
-  // fine read-modify-write operands of this wave's 8 segments, fetched first
-  float4 yv[8];
+  // fine read-modify-write operands of this wave's segments, fetched first
+  float4 yv[NT];
 #pragma unroll
-  for (int task = 0; task < 8; ++task) {
-    const int fr_local = wave * 2 + (task >> 2), par = (task >> 1) & 1, jb = task & 1;
+  for (int task = 0; task < NT; ++task) {
+    const int fr_local = wave * FRW + (task >> 2), par = (task >> 1) & 1, jb = task & 1;
     const int i = 2 * I0 + fr_local, j = 2 * (J0 + jb * 16 + px) + par;
     yv[task] = (i < m && j < m) ? ld4(Fb, i * m + j, g) : make_float4(0.f, 0.f, 0.f, 0.f);
   }
@@ -523,8 +525,8 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
   }
   __syncthreads();
 #pragma unroll
-  for (int task = 0; task < 8; ++task) {
-    const int fr_local = wave * 2 + (task >> 2);   // fine row within the 8-row tile
+  for (int task = 0; task < NT; ++task) {
+    const int fr_local = wave * FRW + (task >> 2);  // fine row within the tile
     const int par = (task >> 1) & 1;                // fine column parity
     const int jb = task & 1;                        // 16-wide block of coarse columns
     const int i = 2 * I0 + fr_local;   // rows past the grid are computed too (the staged coarse
@@ -565,14 +567,14 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
 // (W_in as a 16 x 12 matrix, taps 9..11 zero, against the nine rt values around each pixel);
 // with bf16 state it is the rounded stored x1, kept in LDS.
 // ------------------------------------------------------------------------------------------
-template <int ST, bool SBF = false>
+template <int ST, bool SBF = false, int TH = 8>
 __global__ __launch_bounds__(256) void smooth_in_kernel(
     const float* __restrict__ rt, const void* __restrict__ s,
     const float* __restrict__ Win, const float* __restrict__ W,
     typename Frag<ST>::elem* __restrict__ y, int m, int tiles_x, int tiles_per_prob,
     const int* __restrict__ active) {
   typedef typename Frag<ST>::elem E;
-  typedef SameCfg<ST> K;
+  typedef SameCfg<ST, TH> K;
   constexpr int RR = K::IR + 2, RC = K::IC + 2;          // rt tile (two-pixel halo)
   constexpr int PPT = (K::NPIX + 255) / 256;             // staged pixels per thread
   constexpr int RPT = (RR * RC + 255) / 256;             // rt values per thread
@@ -715,6 +717,7 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
 // per-pixel arithmetic and its order do not depend on the tile, so every variant gives the same
 // results bit for bit.
 constexpr int SAME_ROWS[TILE_VARIANTS] = {8, 4, 16};
+constexpr int PROLONG_ROWS[TILE_VARIANTS] = {8, 4, 16};   // fine rows (2 x coarse rows)
 constexpr int RS_ROWS_F32[TILE_VARIANTS] = {4, 2, 8};
 constexpr int RS_ROWS_BF16[TILE_VARIANTS] = {8, 4, 16};
 static int g_tile_variant[TILE_OPS][2][13] = {};     // [op][bf16 storage][log2(m + 1)]
@@ -728,6 +731,7 @@ static int lg2p1(int m) {
 int tile_variant_rows(int op, bool bf16, int v) {
   if (v < 0 || v >= TILE_VARIANTS) return 0;
   if (op == TILE_RESTRICT) return bf16 ? RS_ROWS_BF16[v] : RS_ROWS_F32[v];
+  if (op == TILE_PROLONG) return PROLONG_ROWS[v];
   return SAME_ROWS[v];
 }
 int get_tile_variant(int op, bool bf16, int m) { return g_tile_variant[op][bf16 ? 1 : 0][lg2p1(m)]; }
@@ -802,14 +806,23 @@ void launch_conv16(ConvMode mode, StateType st_, const void* x, const void* s, c
   }
 }
 
+template <int ST, bool SBF, int TH>
+static void smooth_in_launch_th(const float* rt, const void* s, const float* Win, const float* W, void* y,
+                                int m, int B, const int* active, hipStream_t st) {
+  typedef SameCfg<ST, TH> K;
+  typedef typename Frag<ST>::elem E;
+  const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
+  hipLaunchKernelGGL((smooth_in_kernel<ST, SBF, TH>), dim3(tx * ty * B), dim3(256), 0, st, rt, s, Win, W,
+                     (E*)y, m, tx, tx * ty, active);
+}
+
 template <int ST, bool SBF = false>
 static void smooth_in_launch(const float* rt, const void* s, const float* Win, const float* W, void* y,
                              int m, int B, const int* active, hipStream_t st) {
-  typedef SameCfg<ST> K;
-  typedef typename Frag<ST>::elem E;
-  const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
-  hipLaunchKernelGGL((smooth_in_kernel<ST, SBF>), dim3(tx * ty * B), dim3(256), 0, st, rt, s, Win, W,
-                     (E*)y, m, tx, tx * ty, active);
+  const int v = get_tile_variant(TILE_SMOOTH_IN, ST == ST_BF16, m);
+  if (v == 1) smooth_in_launch_th<ST, SBF, 4>(rt, s, Win, W, y, m, B, active, st);
+  else if (v == 2) smooth_in_launch_th<ST, SBF, 16>(rt, s, Win, W, y, m, B, active, st);
+  else smooth_in_launch_th<ST, SBF, 8>(rt, s, Win, W, y, m, B, active, st);
 }
 
 void launch_smooth_in(StateType st_, const float* rt, const void* s, const float* Win, const float* W,
@@ -827,13 +840,22 @@ void launch_smooth_in(StateType st_, const float* rt, const void* s, const float
   }
 }
 
+template <int ST, int PL_CH>
+static void prolong_launch_ch(const void* xc, const float* WT, void* yf, int mc, int B, const int* active,
+                              hipStream_t st) {
+  typedef typename Frag<ST>::elem E;
+  const int tx = (mc + PL_CW - 1) / PL_CW + 1, ty = (mc + PL_CH - 1) / PL_CH + 1;
+  hipLaunchKernelGGL((prolong_add_kernel<ST, PL_CH>), dim3(tx * ty * B), dim3(256), 0, st, (const E*)xc, WT,
+                     (E*)yf, mc, tx, tx * ty, active);
+}
+
 template <int ST>
 static void prolong_launch(const void* xc, const float* WT, void* yf, int mc, int B, const int* active,
                            hipStream_t st) {
-  typedef typename Frag<ST>::elem E;
-  const int tx = (mc + PL_CW - 1) / PL_CW + 1, ty = (mc + PL_CH - 1) / PL_CH + 1;
-  hipLaunchKernelGGL(prolong_add_kernel<ST>, dim3(tx * ty * B), dim3(256), 0, st, (const E*)xc, WT,
-                     (E*)yf, mc, tx, tx * ty, active);
+  const int v = get_tile_variant(TILE_PROLONG, ST == ST_BF16, 2 * mc + 1);
+  if (v == 1) prolong_launch_ch<ST, 2>(xc, WT, yf, mc, B, active, st);
+  else if (v == 2) prolong_launch_ch<ST, 8>(xc, WT, yf, mc, B, active, st);
+  else prolong_launch_ch<ST, 4>(xc, WT, yf, mc, B, active, st);
 }
 
 void launch_prolong_add(StateType st_, const void* xc, const float* WT, void* yf, int mc, int B,

@@ -57,8 +57,10 @@ void launch_conv16(ConvMode mode, StateType t, const void* x, const void* s, con
                    bool s_bf16 = false);
 
 // Tile variants of the 16 -> 16 convolutions (process-wide table, autotuning): op = TILE_SMOOTHER
-// (down / up smoothers), TILE_RESTRICT, TILE_SETUP (tanh layers); variant 0 = the default tile.
-enum TileOp : int { TILE_SMOOTHER = 0, TILE_RESTRICT = 1, TILE_SETUP = 2, TILE_OPS = 3 };
+// (down / up smoothers), TILE_RESTRICT, TILE_SETUP (tanh layers), TILE_SMOOTH_IN (finest down
+// smoother with reChannel-in), TILE_PROLONG (keyed by the fine side); variant 0 = the default.
+enum TileOp : int { TILE_SMOOTHER = 0, TILE_RESTRICT = 1, TILE_SETUP = 2, TILE_SMOOTH_IN = 3,
+                    TILE_PROLONG = 4, TILE_OPS = 5 };
 constexpr int TILE_VARIANTS = 3;
 int tile_variant_rows(int op, bool bf16, int variant);
 int get_tile_variant(int op, bool bf16, int m);

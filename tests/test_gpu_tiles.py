@@ -29,7 +29,7 @@ def dev(x, dtype=torch.float32):
 
 
 def set_everything(state, v):
-    for op in ("smoother", "restrict") + (("setup",) if state == "f32" else ()):
+    for op in ("smoother", "restrict", "smooth_in", "prolong") + (("setup",) if state == "f32" else ()):
         AT.set_all(M.lib(), op, state, v)
 
 
