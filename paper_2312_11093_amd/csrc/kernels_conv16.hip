@@ -289,21 +289,18 @@ struct SameCfg {
   static constexpr int NSEG = TW / 16, NTASK = TH * NSEG, TPW = NTASK / 4;
 };
 
+// One output tile of the same-size conv: problem b, tile index `tile` of a grid of side m.
 // SBF: s stored as bf16 while the state is f32 (f32 storage only; the bf16 state has bf16 s).
-template <int ST, int MODE, bool SBF = false, int TH = 8>
-__global__ __launch_bounds__(256) void conv16_same_kernel(
+template <int ST, int MODE, bool SBF, int TH>
+__device__ __forceinline__ void conv16_same_tile(
     const typename Frag<ST>::elem* __restrict__ x, const void* __restrict__ s,
     const float* __restrict__ W, const float* __restrict__ bias,
-    typename Frag<ST>::elem* __restrict__ y, int m, int tiles_x, int tiles_per_prob,
-    const int* __restrict__ active) {
+    typename Frag<ST>::elem* __restrict__ y, int m, int tiles_x, int b, int tile) {
   typedef typename Frag<ST>::elem E;
   typedef SameCfg<ST, TH> K;
   typedef Chunk<ST> CK;
   constexpr int PSTR = K::NPIX * PS;                  // LDS plane stride
   __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
-  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int row0 = (tile / tiles_x) * K::TH, col0 = (tile % tiles_x) * K::TW;
   const size_t pbase = (size_t)b * m * m * C;     // problem offset in elements
   const E* Xb = x + pbase;
@@ -383,6 +380,39 @@ __global__ __launch_bounds__(256) void conv16_same_kernel(
       st4(Yb, gi * m + gj, g, o);
     }
   }
+}
+
+template <int ST, int MODE, bool SBF = false, int TH = 8>
+__global__ __launch_bounds__(256) void conv16_same_kernel(
+    const typename Frag<ST>::elem* __restrict__ x, const void* __restrict__ s,
+    const float* __restrict__ W, const float* __restrict__ bias,
+    typename Frag<ST>::elem* __restrict__ y, int m, int tiles_x, int tiles_per_prob,
+    const int* __restrict__ active) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
+  const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
+  conv16_same_tile<ST, MODE, SBF, TH>(x, s, W, bias, y, m, tiles_x, b, tile);
+}
+
+// One tanh layer of the setup network on every level at once (Alg. 2, Setup2: the levels do not
+// depend on each other once the restricted coefficient tensors exist): workgroup t belongs to
+// the level whose tile range [start_l, start_{l+1}) contains it.
+struct SetupLevels {
+  const float* x[MAX_LEVELS];
+  float* y[MAX_LEVELS];
+  int m[MAX_LEVELS], tiles_x[MAX_LEVELS], tiles_per_prob[MAX_LEVELS], start[MAX_LEVELS + 1];
+  int L;
+};
+
+template <int ST, int TH>
+__global__ __launch_bounds__(256) void conv16_tanh_levels_kernel(SetupLevels lv, const float* __restrict__ W,
+                                                                 const float* __restrict__ bias) {
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  int l = 0;
+  while (l + 1 < lv.L && t >= lv.start[l + 1]) ++l;
+  const int u = t - lv.start[l];
+  const int slot = u / lv.tiles_per_prob[l], tile = u % lv.tiles_per_prob[l];
+  conv16_same_tile<ST, CM_TANH, false, TH>(lv.x[l], nullptr, W, bias, lv.y[l], lv.m[l], lv.tiles_x[l], slot, tile);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -786,6 +816,39 @@ static void conv16_launch(ConvMode mode, const void* x, const void* s, const flo
   else if constexpr (ST != ST_BF16 && !SBF)
     same_variant<ST, CM_TANH, false>(get_tile_variant(TILE_SETUP, BF, m), x, nullptr, W, bias, y, m, B,
                                      active, st);
+}
+
+template <int ST, int TH>
+static void tanh_levels_launch(const float* const* x, float* const* y, const int* m, const int* B, int L,
+                               const float* W, const float* bias, hipStream_t st) {
+  typedef SameCfg<ST, TH> K;
+  SetupLevels lv{};
+  lv.L = L;
+  lv.start[0] = 0;
+  for (int l = 0; l < L; ++l) {
+    lv.x[l] = x[l];
+    lv.y[l] = y[l];
+    lv.m[l] = m[l];
+    lv.tiles_x[l] = (m[l] + K::TW - 1) / K::TW;
+    lv.tiles_per_prob[l] = lv.tiles_x[l] * ((m[l] + K::TH - 1) / K::TH);
+    lv.start[l + 1] = lv.start[l] + lv.tiles_per_prob[l] * B[l];
+  }
+  hipLaunchKernelGGL((conv16_tanh_levels_kernel<ST, TH>), dim3(lv.start[L]), dim3(256), 0, st, lv, W, bias);
+}
+
+void launch_tanh_levels(StateType t, const float* const* x, float* const* y, const int* m, const int* B,
+                        int L, const float* W, const float* bias, hipStream_t st) {
+  if (L < 1 || L > MAX_LEVELS) return;
+  const int v = get_tile_variant(TILE_SETUP, false, m[0]);
+  if (t == ST_F32X) {
+    if (v == 1) tanh_levels_launch<ST_F32X, 4>(x, y, m, B, L, W, bias, st);
+    else if (v == 2) tanh_levels_launch<ST_F32X, 16>(x, y, m, B, L, W, bias, st);
+    else tanh_levels_launch<ST_F32X, 8>(x, y, m, B, L, W, bias, st);
+  } else {
+    if (v == 1) tanh_levels_launch<ST_F32, 4>(x, y, m, B, L, W, bias, st);
+    else if (v == 2) tanh_levels_launch<ST_F32, 16>(x, y, m, B, L, W, bias, st);
+    else tanh_levels_launch<ST_F32, 8>(x, y, m, B, L, W, bias, st);
+  }
 }
 
 void launch_conv16(ConvMode mode, StateType st_, const void* x, const void* s, const float* W,

@@ -438,35 +438,51 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
     c->ready = true;
     return MGCNN_OK;
   }
-  // setup temporaries (f32), kept in the context for the next setup of this size: features,
-  // coefficient tensor (current, next), two ping-pong buffers of the tanh layers
-  const size_t t16 = nn * C * 4;
-  if (!c->setup_tmp && (r = alloc(c, &c->setup_tmp, nn * 16 + 4 * t16))) return r;
+  // Alg. 2 with the levels' tanh layers fused (Setup2 does not couple the levels once the
+  // restricted coefficient tensors exist): features and reChannel on the finest level, the
+  // restriction chain c_1 -> c_2 -> ... -> c_L, then each of the four tanh layers as one launch
+  // over all levels.  With f32 storage the level tensors hold the intermediates (c_l in xin_l,
+  // the layers ping-pong between xdn_l and s_l and end in s_l); bf16 storage uses f32 level
+  // pyramids kept in the context for the next setup of this size.
+  const int L = c->L;
+  const bool f32_store = c->state_bytes() == 4 && !c->s16();
+  size_t pyr = 0;                                      // floats of one f32 level pyramid
+  for (int l = 0; l < L; ++l) pyr += (size_t)c->nl[l] * c->nl[l] * B * C;
+  if (!c->setup_tmp && (r = alloc(c, &c->setup_tmp, nn * 16 + (f32_store ? 0 : 3 * pyr * 4)))) return r;
   float* F = (float*)c->setup_tmp;
-  float* cc = F + nn * 4;
-  float* cn = cc + nn * C;
-  float* za = cn + nn * C;
-  float* zb = za + nn * C;
-  launch_features(c->d_a, c->d_b, F, n, B, c->form(), s);
-  launch_conv_in(4, F, c->W(c->off.setup_in), cc, ST_F32, n, B, nullptr, s);
-  for (int l = 0; l < c->L; ++l) {
-    const int m = c->nl[l];
-    const size_t cnt = (size_t)m * m * B * C;
-    const float* zin = cc;
-    float* ping[2] = {za, zb};
-    for (int k = 0; k < NUM_SETUP_LAYERS; ++k) {
-      float* zout = (k == NUM_SETUP_LAYERS - 1 && !c->s16()) ? (float*)c->s[l] : ping[k & 1];
-      launch_conv16(CM_TANH, c->opts.f32_split ? ST_F32X : ST_F32, zin, nullptr, c->W(c->off.res_w[k]),
-                    c->W(c->off.res_b[k]), zout, m, B, nullptr, s);
-      zin = zout;
-    }
-    if (c->s16()) launch_f32_to_bf16(zin, (bf16_t*)c->s[l], cnt, s);
-    if (l < c->L - 1) {
-      launch_conv16(CM_RESTRICT, ST_F32, cc, nullptr, c->W(c->off.setup_restrict), nullptr, cn, m, B,
-                    nullptr, s);
-      float* t = cc; cc = cn; cn = t;
+  float *cl[MAX_LEVELS], *za[MAX_LEVELS], *zb[MAX_LEVELS];
+  {
+    float* p = F + nn * 4;
+    for (int l = 0; l < L; ++l) {
+      const size_t cnt = (size_t)c->nl[l] * c->nl[l] * B * C;
+      if (f32_store) {
+        cl[l] = (float*)c->xin[l];
+        za[l] = (float*)c->xdn[l];
+        zb[l] = (float*)c->s[l];
+      } else {
+        cl[l] = p;
+        za[l] = p + pyr;
+        zb[l] = p + 2 * pyr;
+        p += cnt;
+      }
     }
   }
+  launch_features(c->d_a, c->d_b, F, n, B, c->form(), s);
+  launch_conv_in(4, F, c->W(c->off.setup_in), cl[0], ST_F32, n, B, nullptr, s);
+  for (int l = 0; l + 1 < L; ++l)
+    launch_conv16(CM_RESTRICT, ST_F32, cl[l], nullptr, c->W(c->off.setup_restrict), nullptr, cl[l + 1],
+                  c->nl[l], B, nullptr, s);
+  int bl[MAX_LEVELS];
+  for (int l = 0; l < L; ++l) bl[l] = B;
+  const StateType tanh_t = c->opts.f32_split ? ST_F32X : ST_F32;
+  float** src[NUM_SETUP_LAYERS] = {cl, za, zb, za};
+  float** dst[NUM_SETUP_LAYERS] = {za, zb, za, zb};
+  for (int k = 0; k < NUM_SETUP_LAYERS; ++k)
+    launch_tanh_levels(tanh_t, src[k], dst[k], c->nl.data(), bl, L, c->W(c->off.res_w[k]),
+                       c->W(c->off.res_b[k]), s);
+  if (!f32_store)
+    for (int l = 0; l < L; ++l)
+      launch_f32_to_bf16(zb[l], (bf16_t*)c->s[l], (size_t)c->nl[l] * c->nl[l] * B * C, s);
   LAUNCH_CHECK(c);
   c->ready = true;
   return MGCNN_OK;

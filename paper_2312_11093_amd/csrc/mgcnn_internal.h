@@ -10,6 +10,7 @@ namespace mg {
 
 constexpr int C = 16;                 // hidden channels of every state / setup tensor
 constexpr int NUM_SETUP_LAYERS = 4;   // tanh ResNet layers of the setup network
+constexpr int MAX_LEVELS = 12;        // levels of a 4095 x 4095 grid
 
 // State of the solve network (x, s): storage type and matrix-core arithmetic.
 //   ST_F32   float32 storage, float32 MFMA (16x16x4)
@@ -65,6 +66,11 @@ constexpr int TILE_VARIANTS = 3;
 int tile_variant_rows(int op, bool bf16, int variant);
 int get_tile_variant(int op, bool bf16, int m);
 void set_tile_variant(int op, bool bf16, int m, int variant);
+
+// One tanh layer of the setup network on L levels in one launch: y_l = x_l + tanh(W * x_l + bias)
+// for l < L, level l of side m[l] and batch B[l] (f32 storage; t = ST_F32 or ST_F32X).
+void launch_tanh_levels(StateType t, const float* const* x, float* const* y, const int* m, const int* B,
+                        int L, const float* W, const float* bias, hipStream_t st);
 
 // y_fine += convT_{stride 2}(W_T, x_coarse), fine side m = 2 mc + 1, in place on y_fine.
 void launch_prolong_add(StateType t, const void* xc, const float* WT, void* yf, int mc, int B,

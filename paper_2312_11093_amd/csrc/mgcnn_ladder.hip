@@ -251,48 +251,58 @@ int ladder_setup(Ladder* L, const float* const* a, const float* b_host, const in
     LTRY(hipMemcpyAsync(L->a[j] + (size_t)(q - L->lo[j]) * n * n, a[L->order[q]], (size_t)n * n * 4,
                         hipMemcpyDeviceToDevice, st));
   }
-  // setup network (Alg. 2) over the aligned levels.  With f32 storage the level tensors hold the
-  // intermediates: the coefficient tensor c_j in xin_j (kept for the restriction to the next
-  // size), the tanh layers ping-pong between xdn_j and s_j and end in s_j; bf16 storage uses f32
-  // temporaries.
+  // setup network (Alg. 2) over the aligned levels: reChannel of the features at each problem's
+  // finest size, the restriction chain of the coefficient tensors down the sizes, then each tanh
+  // layer as one launch over every level size (Setup2 does not couple the levels).  With f32
+  // storage the level tensors hold the intermediates (c_j in xin_j, the layers ping-pong between
+  // xdn_j and s_j and end in s_j); bf16 storage uses f32 level pyramids.
   const bool f32_store = L->xbytes() == 4 && sbb == 4;
-  float *F = nullptr, *t0 = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
+  size_t pyr = 0;
+  for (int j = 0; j < L->J; ++j) pyr += (size_t)L->m[j] * L->m[j] * L->k[j] * C;
+  float *F = nullptr, *tmp = nullptr;
   auto cleanup = [&]() {
-    for (float* p : {F, t0, t1, t2, t3}) if (p) (void)hipFree(p);
+    for (float* p : {F, tmp}) if (p) (void)hipFree(p);
   };
   if ((r = lalloc(L, (void**)&F, max_fine * 4 * 4))) { cleanup(); return r; }
-  if (!f32_store) {
-    if ((r = lalloc(L, (void**)&t0, max_level * 4)) || (r = lalloc(L, (void**)&t1, max_level * 4)) ||
-        (r = lalloc(L, (void**)&t2, max_level * 4)) || (r = lalloc(L, (void**)&t3, max_level * 4))) {
-      cleanup();
-      return r;
+  if (!f32_store && (r = lalloc(L, (void**)&tmp, 3 * pyr * 4))) { cleanup(); return r; }
+  (void)max_level;
+  auto W = [&](size_t off) { return (const float*)(L->d_w + off); };
+  float *cl[MAX_LEVELS], *za[MAX_LEVELS], *zb[MAX_LEVELS];
+  {
+    float* p = tmp;
+    for (int j = 0; j < L->J; ++j) {
+      if (f32_store) {
+        cl[j] = (float*)L->xin[j];
+        za[j] = (float*)L->xdn[j];
+        zb[j] = (float*)L->s[j];
+      } else {
+        cl[j] = p;
+        za[j] = p + pyr;
+        zb[j] = p + 2 * pyr;
+        p += (size_t)L->m[j] * L->m[j] * L->k[j] * C;
+      }
     }
   }
-  auto W = [&](size_t off) { return (const float*)(L->d_w + off); };
-  const StateType tanh_t = o.f32_split ? ST_F32X : ST_F32;
   for (int j = 0; j < L->J; ++j) {
     const int mj = L->m[j], cj = L->c(j), lo = L->lo[j], kj = L->k[j];
     const size_t mm = (size_t)mj * mj;
-    float* cc = f32_store ? (float*)L->xin[j] : ((j & 1) ? t1 : t0);
-    float* cn = f32_store ? (j + 1 < L->J ? (float*)L->xin[j + 1] : nullptr) : ((j & 1) ? t0 : t1);
     if (cj > 0) {
       launch_features(L->a[j], L->d_b + 2 * lo, F, mj, cj, o.op_form, st);
-      launch_conv_in(4, F, W(L->off.setup_in), cc + mm * lo * C, ST_F32, mj, cj, nullptr, st);
+      launch_conv_in(4, F, W(L->off.setup_in), cl[j] + mm * lo * C, ST_F32, mj, cj, nullptr, st);
     }
-    float* ping0 = f32_store ? (float*)L->xdn[j] : t2;
-    float* ping1 = f32_store ? (float*)L->s[j] : t3;
-    const float* zin = cc;
-    for (int kk = 0; kk < NUM_SETUP_LAYERS; ++kk) {
-      float* zout = (kk & 1) ? ping1 : ping0;
-      launch_conv16(CM_TANH, tanh_t, zin, nullptr, W(L->off.res_w[kk]), W(L->off.res_b[kk]), zout, mj, kj,
-                    nullptr, st);
-      zin = zout;
-    }
-    if (!f32_store) launch_f32_to_bf16(zin, (bf16_t*)L->s[j], mm * kj * C, st);
     if (j + 1 < L->J)
-      launch_conv16(CM_RESTRICT, ST_F32, cc, nullptr, W(L->off.setup_restrict), nullptr, cn, mj, kj, nullptr,
-                    st);
+      launch_conv16(CM_RESTRICT, ST_F32, cl[j], nullptr, W(L->off.setup_restrict), nullptr, cl[j + 1], mj, kj,
+                    nullptr, st);
   }
+  const StateType tanh_t = o.f32_split ? ST_F32X : ST_F32;
+  float** src[NUM_SETUP_LAYERS] = {cl, za, zb, za};
+  float** dst[NUM_SETUP_LAYERS] = {za, zb, za, zb};
+  for (int kk = 0; kk < NUM_SETUP_LAYERS; ++kk)
+    launch_tanh_levels(tanh_t, src[kk], dst[kk], L->m.data(), L->k.data(), L->J, W(L->off.res_w[kk]),
+                       W(L->off.res_b[kk]), st);
+  if (!f32_store)
+    for (int j = 0; j < L->J; ++j)
+      launch_f32_to_bf16(zb[j], (bf16_t*)L->s[j], (size_t)L->m[j] * L->m[j] * L->k[j] * C, st);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   cleanup();
