@@ -5,7 +5,8 @@ Runs, in one process on one GPU:
      traffic is known (COPY_MIB MiB read + COPY_MIB MiB written): it calibrates what the
      counters read per byte;
   2. `iters` stationary iterations (residual + V-cycle + update) of the benchmark's batch:
-     64 problems at 1023 x 1023, random 16 x 16 blocks, f32 state, f64 u, hand-set weights.
+     64 problems at 1023 x 1023, random 16 x 16 blocks, f32 state, f64 u, hand-set weights, the
+     benchmark's autotuned tile table.
 
     rocprofv3 --pmc FETCH_SIZE -d <dir> -o run -f csv -- python3 -m benchmarks.pmcrun
     rocprofv3 --pmc WRITE_SIZE -d <dir> -o run -f csv -- python3 -m benchmarks.pmcrun
@@ -35,7 +36,10 @@ def main():
 
     import datagen
     from paper_2312_11093_amd import Solver
+    from paper_2312_11093_amd import autotune
     from paper_2312_11093_amd.handbuilt import vcycle_weights
+
+    autotune.load()                                   # the benchmark's tile table
 
     src = torch.ones(COPY_MIB * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
