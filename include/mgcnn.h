@@ -155,6 +155,17 @@ typedef struct {
                        the adjoint of W_in the solve network is a symmetric operator (the
                        symmetric variant of the remark in Sec. 3.3).  The recorded forward and
                        mgcnn_backward reject it (MGCNN_E_ARG) */
+  int pack_pairs;   /* network, stationary method only: 0 (default); 1 = packed pairs for networks
+                       of at most 8 hidden channels (Sec. 4.2 and Table 2 compare C = 4, 8, 12)
+                       given in the 16-channel layout with channels 8..15 zero
+                       (mgcnn_set_weights checks it: MGCNN_E_ARG otherwise).  Problems 2b and
+                       2b + 1 then share one 16-channel state tensor, one in channels 0..7 and one
+                       in channels 8..15, and the 16 -> 16 convolutions take the block-diagonal
+                       weights diag(W8, W8): the same network per problem (up to the rounding of
+                       the summation order) at half the state bytes per problem.  An odd batch
+                       leaves the second half of the last pair empty.  Training entry points and
+                       mgcnn_get_setup_tensor return MGCNN_E_STATE; mgcnn_create rejects it with
+                       FGMRES, PCG, GMG or s_bf16, mgcnn_group_create rejects it (MGCNN_E_ARG) */
 } mgcnn_opts;
 
 /* Default options: 16 channels, f32 state (split-bf16 matrix arithmetic), f64 u, graphs off,

@@ -596,8 +596,11 @@ __global__ __launch_bounds__(256) void prolong_add_kernel(
 // pixels is, with f32 state, three more 16x16x4 MFMAs per segment into the same accumulator
 // (W_in as a 16 x 12 matrix, taps 9..11 zero, against the nine rt values around each pixel);
 // with bf16 state it is the rounded stored x1, kept in LDS.
+// PAIR (packed pairs of problems, networks of at most 8 hidden channels): slot b carries problem
+// 2b in channels 0..7 and problem 2b + 1 in channels 8..15; rt holds 2 x slots planes, and each
+// half of x1 comes from its own plane with the first eight rows of W_in.
 // ------------------------------------------------------------------------------------------
-template <int ST, bool SBF = false, int TH = 8>
+template <int ST, bool SBF = false, int TH = 8, bool PAIR = false>
 __global__ __launch_bounds__(256) void smooth_in_kernel(
     const float* __restrict__ rt, const void* __restrict__ s,
     const float* __restrict__ Win, const float* __restrict__ W,
@@ -609,10 +612,11 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
   constexpr int PPT = (K::NPIX + 255) / 256;             // staged pixels per thread
   constexpr int RPT = (RR * RC + 255) / 256;             // rt values per thread
   constexpr int PSTR = K::NPIX * PS;                     // LDS plane stride
+  constexpr int NRT = PAIR ? 2 : 1;                      // rt planes
   __shared__ __attribute__((aligned(16))) typename Frag<ST>::lds_t lds[Frag<ST>::PLANES * PSTR];  // z = s . x1
   constexpr bool SKIP_MMA = ST == ST_F32 || ST == ST_F32X2;   // skip term on the matrix cores
   __shared__ __attribute__((aligned(16))) E lx[SKIP_MMA ? 4 : K::TH * K::TW * PS];  // x1 at the outputs
-  __shared__ float lrt[RR * RC];
+  __shared__ float lrt[NRT][RR * RC];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
@@ -621,18 +625,21 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
   typedef typename std::conditional<SBF, uint16_t, E>::type SE;   // storage type of s
   const SE* Sb = (const SE*)s + pbase * C;
   E* Yb = y + pbase * C;
-  const float* Rb = rt + pbase;
+  const float* Rb = rt + (PAIR ? 2 * pbase : pbase);     // plane h of the slot at Rb + h m^2
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int px = lane & 15, g = lane >> 4;
   // 1. every global load of this thread first: the rt tile, then s of the staged pixels
-  float rv[RPT];
+  float rv[NRT][RPT];
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int k = threadIdx.x + 256 * r;
-    const int lr = k / RC, lc = k - lr * RC;
-    const int gi = row0 + lr - 2, gj = col0 + lc - 2;
-    rv[r] = (k < RR * RC && gi >= 0 && gi < m && gj >= 0 && gj < m) ? Rb[gi * m + gj] : 0.f;
-  }
+  for (int h = 0; h < NRT; ++h)
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int k = threadIdx.x + 256 * r;
+      const int lr = k / RC, lc = k - lr * RC;
+      const int gi = row0 + lr - 2, gj = col0 + lc - 2;
+      rv[h][r] = (k < RR * RC && gi >= 0 && gi < m && gj >= 0 && gj < m) ? Rb[(size_t)h * m * m + gi * m + gj]
+                                                                       : 0.f;
+    }
   float sv[PPT][C];
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
@@ -648,10 +655,12 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
     }
   }
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int k = threadIdx.x + 256 * r;
-    if (k < RR * RC) lrt[k] = rv[r];
-  }
+  for (int h = 0; h < NRT; ++h)
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int k = threadIdx.x + 256 * r;
+      if (k < RR * RC) lrt[h][k] = rv[h][r];
+    }
   Frag<ST> fr;
   fr.load_w(W, false);
   __syncthreads();
@@ -663,17 +672,20 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
     const int lr = pix / K::IC, lc = pix - lr * K::IC;
     const int gi = row0 + lr - 1, gj = col0 + lc - 1;
     const bool in = gi >= 0 && gi < m && gj >= 0 && gj < m;
-    float nb[9];
+    float nb[NRT][9];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int h = 0; h < NRT; ++h)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) nb[p * 3 + q] = lrt[(lr + p) * RC + lc + q];
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) nb[h][p * 3 + q] = lrt[h][(lr + p) * RC + lc + q];
     float x1[C], z[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
+      const int h = PAIR ? c / 8 : 0, cw = PAIR ? c % 8 : c;
       float acc = 0.f;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) acc = fmaf(Win[c * 9 + k], nb[k], acc);
+      for (int k = 0; k < 9; ++k) acc = fmaf(Win[cw * 9 + k], nb[h][k], acc);
       acc = in ? acc : 0.f;
       if constexpr (ST == ST_BF16) acc = bf16_to_f32(f32_to_bf16_rne(acc));   // stored-state rounding
       x1[c] = acc;
@@ -690,12 +702,15 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
     if constexpr (!SKIP_MMA)
       if (lr >= 1 && lr <= K::TH && lc >= 1 && lc <= K::TW) store16(&lx[((lr - 1) * K::TW + lc - 1) * PS], x1);
   }
-  // A operand of the skip MFMAs: lane (px, g) holds W_in[channel px][tap 4 s + g] for instruction s
-  float wsk[3];
+  // A operand of the skip MFMAs: lane (px, g) holds W_in[channel px][k = 4 s + g] for instruction s,
+  // k running over the nine taps of each rt plane (PAIR: channel px reads plane px / 8 only)
+  constexpr int NSK = PAIR ? 6 : 3;
+  float wsk[NSK];
 #pragma unroll
-  for (int s3 = 0; s3 < 3; ++s3) {
-    const int tap = 4 * s3 + g;
-    wsk[s3] = (SKIP_MMA && tap < 9) ? Win[px * 9 + tap] : 0.f;
+  for (int s3 = 0; s3 < NSK; ++s3) {
+    const int kk = 4 * s3 + g, h = kk / 9, tap = kk % 9;
+    const bool use = SKIP_MMA && kk < 9 * NRT && (!PAIR || h == px / 8);
+    wsk[s3] = use ? Win[(PAIR ? px % 8 : px) * 9 + tap] : 0.f;
   }
   __syncthreads();
   // 3. implicit GEMM per 16-pixel segment, y = x1 + acc
@@ -706,13 +721,15 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
     const int gi = row0 + orow;   // segments past the grid are computed (zero staged tile), not stored
     f4v acc = {0.f, 0.f, 0.f, 0.f};
     if constexpr (SKIP_MMA) {
-      // x1 at the output pixel: B[k = g][px] = rt at tap 4 s + g (zero for taps 9..11)
+      // x1 at the output pixel: B[k = g][px] = rt of plane k / 9 at tap k % 9, k = 4 s + g (zero
+      // past the last plane)
 #pragma unroll
-      for (int s3 = 0; s3 < 3; ++s3) {
-        const int tap = 4 * s3 + g;
-        const int tp = tap < 9 ? tap : 0;
-        const float rb = lrt[(orow + 1 + tp / 3) * RC + seg * 16 + px + 1 + tp % 3];
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wsk[s3], tap < 9 ? rb : 0.f, acc, 0, 0, 0);
+      for (int s3 = 0; s3 < NSK; ++s3) {
+        const int kk = 4 * s3 + g;
+        const bool in = kk < 9 * NRT;
+        const int h = in ? kk / 9 : 0, tp = in ? kk % 9 : 0;
+        const float rb = lrt[h][(orow + 1 + tp / 3) * RC + seg * 16 + px + 1 + tp % 3];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wsk[s3], in ? rb : 0.f, acc, 0, 0, 0);
       }
     }
 #pragma unroll
@@ -869,29 +886,35 @@ void launch_conv16(ConvMode mode, StateType st_, const void* x, const void* s, c
   }
 }
 
-template <int ST, bool SBF, int TH>
+template <int ST, bool SBF, int TH, bool PAIR>
 static void smooth_in_launch_th(const float* rt, const void* s, const float* Win, const float* W, void* y,
                                 int m, int B, const int* active, hipStream_t st) {
   typedef SameCfg<ST, TH> K;
   typedef typename Frag<ST>::elem E;
   const int tx = (m + K::TW - 1) / K::TW, ty = (m + K::TH - 1) / K::TH;
-  hipLaunchKernelGGL((smooth_in_kernel<ST, SBF, TH>), dim3(tx * ty * B), dim3(256), 0, st, rt, s, Win, W,
-                     (E*)y, m, tx, tx * ty, active);
+  hipLaunchKernelGGL((smooth_in_kernel<ST, SBF, TH, PAIR>), dim3(tx * ty * B), dim3(256), 0, st, rt, s, Win,
+                     W, (E*)y, m, tx, tx * ty, active);
 }
 
-template <int ST, bool SBF = false>
+template <int ST, bool SBF = false, bool PAIR = false>
 static void smooth_in_launch(const float* rt, const void* s, const float* Win, const float* W, void* y,
                              int m, int B, const int* active, hipStream_t st) {
   const int v = get_tile_variant(TILE_SMOOTH_IN, ST == ST_BF16, m);
-  if (v == 1) smooth_in_launch_th<ST, SBF, 4>(rt, s, Win, W, y, m, B, active, st);
-  else if (v == 2) smooth_in_launch_th<ST, SBF, 16>(rt, s, Win, W, y, m, B, active, st);
-  else smooth_in_launch_th<ST, SBF, 8>(rt, s, Win, W, y, m, B, active, st);
+  if (v == 1) smooth_in_launch_th<ST, SBF, 4, PAIR>(rt, s, Win, W, y, m, B, active, st);
+  else if (v == 2) smooth_in_launch_th<ST, SBF, 16, PAIR>(rt, s, Win, W, y, m, B, active, st);
+  else smooth_in_launch_th<ST, SBF, 8, PAIR>(rt, s, Win, W, y, m, B, active, st);
 }
 
 void launch_smooth_in(StateType st_, const float* rt, const void* s, const float* Win, const float* W,
-                      void* y, int m, int B, const int* active, hipStream_t st, bool s_bf16) {
+                      void* y, int m, int B, const int* active, hipStream_t st, bool s_bf16, bool pairs) {
   // f32 storage: f32 MFMA (the split variant measured slower: its three LDS planes halve the
-  // occupancy of this kernel)
+  // occupancy of this kernel).  Packed pairs keep the setup tensors in the state's type.
+  if (pairs) {
+    if (st_ == ST_F32 || st_ == ST_F32X) smooth_in_launch<ST_F32, false, true>(rt, s, Win, W, y, m, B, active, st);
+    else if (st_ == ST_F32X2) smooth_in_launch<ST_F32X2, false, true>(rt, s, Win, W, y, m, B, active, st);
+    else smooth_in_launch<ST_BF16, false, true>(rt, s, Win, W, y, m, B, active, st);
+    return;
+  }
   if (st_ == ST_F32 || st_ == ST_F32X) {
     if (s_bf16) smooth_in_launch<ST_F32, true>(rt, s, Win, W, y, m, B, active, st);
     else smooth_in_launch<ST_F32>(rt, s, Win, W, y, m, B, active, st);

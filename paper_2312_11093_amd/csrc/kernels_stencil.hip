@@ -277,43 +277,53 @@ void launch_solve_init(const double* nf2, int* active, int* status, int* iters, 
 // ------------------------------------------------------------------------------------------
 
 // out[px][o] = sum_{c,p,q} W[o][c][p][q] in[px + (p-1, q-1)][c], CIN in {1, 4}.
-template <int CIN, typename OT>
+// PAIR (packed pairs of problems, networks of at most 8 hidden channels): output slot b holds
+// problem 2b in channels 0..7 and problem 2b + 1 in channels 8..15, each from its own input with
+// the first eight rows of W (problem 2b + 1 absent when 2b + 1 = nprob: its channels are zero).
+template <int CIN, typename OT, bool PAIR = false>
 __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ in,
                                                       const float* __restrict__ W,
                                                       OT* __restrict__ out, int n, int tiles_x,
                                                       int tiles_per_prob,
-                                                      const int* __restrict__ active) {
+                                                      const int* __restrict__ active, int nprob) {
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
   const int j = (tile % tiles_x) * 64 + (threadIdx.x & 63);
   const int i = (tile / tiles_x) * 4 + (threadIdx.x >> 6);
   if (i >= n || j >= n) return;
-  const float* X = in + (size_t)b * n * n * CIN;
-  float v[9][CIN];
+  constexpr int NIN = PAIR ? 2 : 1;
+  float v[NIN][9][CIN];
 #pragma unroll
-  for (int p = 0; p < 3; ++p) {
+  for (int h = 0; h < NIN; ++h) {
+    const int prob = PAIR ? 2 * b + h : b;
+    const bool have = !PAIR || prob < nprob;
+    const float* X = in + (size_t)(have ? prob : 0) * n * n * CIN;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int ii = i + p - 1, jj = j + q - 1;
-      const bool ok = ii >= 0 && ii < n && jj >= 0 && jj < n;
-      if constexpr (CIN == 4) {
-        float4 z = ok ? reinterpret_cast<const float4*>(X)[(size_t)ii * n + jj]
-                      : make_float4(0.f, 0.f, 0.f, 0.f);
-        v[p * 3 + q][0] = z.x; v[p * 3 + q][1] = z.y; v[p * 3 + q][2] = z.z; v[p * 3 + q][3] = z.w;
-      } else {
-        v[p * 3 + q][0] = ok ? X[(size_t)ii * n + jj] : 0.f;
+    for (int p = 0; p < 3; ++p) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int ii = i + p - 1, jj = j + q - 1;
+        const bool ok = have && ii >= 0 && ii < n && jj >= 0 && jj < n;
+        if constexpr (CIN == 4) {
+          float4 z = ok ? reinterpret_cast<const float4*>(X)[(size_t)ii * n + jj]
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+          v[h][p * 3 + q][0] = z.x; v[h][p * 3 + q][1] = z.y; v[h][p * 3 + q][2] = z.z; v[h][p * 3 + q][3] = z.w;
+        } else {
+          v[h][p * 3 + q][0] = ok ? X[(size_t)ii * n + jj] : 0.f;
+        }
       }
     }
   }
   float acc[C];
 #pragma unroll
   for (int o = 0; o < C; ++o) {
+    const int h = PAIR ? o / 8 : 0, oo = PAIR ? o % 8 : o;
     float s = 0.f;
 #pragma unroll
     for (int c = 0; c < CIN; ++c)
 #pragma unroll
-      for (int k = 0; k < 9; ++k) s = fmaf(W[(o * CIN + c) * 9 + k], v[k][c], s);
+      for (int k = 0; k < 9; ++k) s = fmaf(W[(oo * CIN + c) * 9 + k], v[h][k][c], s);
     acc[o] = s;
   }
   store16(out + ((size_t)b * n * n + (size_t)i * n + j) * C, acc);
@@ -326,18 +336,24 @@ void launch_conv_in(int cin, const float* in, const float* W, void* out, StateTy
   if (cin == 1) {
     if (ot != ST_BF16)
       hipLaunchKernelGGL((conv_in_kernel<1, float>), grid, blk, 0, st, in, W, (float*)out, n, tx,
-                         tx * ty, active);
+                         tx * ty, active, B);
     else
       hipLaunchKernelGGL((conv_in_kernel<1, bf16_t>), grid, blk, 0, st, in, W, (bf16_t*)out, n,
-                         tx, tx * ty, active);
+                         tx, tx * ty, active, B);
   } else {
     if (ot != ST_BF16)
       hipLaunchKernelGGL((conv_in_kernel<4, float>), grid, blk, 0, st, in, W, (float*)out, n, tx,
-                         tx * ty, active);
+                         tx * ty, active, B);
     else
       hipLaunchKernelGGL((conv_in_kernel<4, bf16_t>), grid, blk, 0, st, in, W, (bf16_t*)out, n,
-                         tx, tx * ty, active);
+                         tx, tx * ty, active, B);
   }
+}
+
+void launch_conv_in_pairs(const float* in, const float* W, float* out, int n, int nprob, hipStream_t st) {
+  const int tx = (n + 63) / 64, ty = (n + 3) / 4, slots = (nprob + 1) / 2;
+  hipLaunchKernelGGL((conv_in_kernel<4, float, true>), dim3(tx * ty * slots), dim3(256), 0, st, in, W, out,
+                     n, tx, tx * ty, (const int*)nullptr, nprob);
 }
 
 // u[px] += sum_{c,p,q} W[0][c][p][q] x[px + (p-1, q-1)][c]
@@ -349,74 +365,109 @@ void launch_conv_in(int cin, const float* in, const float* W, void* out, StateTy
 constexpr int OU_TH = 8, OU_TW = 64;
 constexpr int OU_SH = OU_TH + 2, OU_SW = OU_TW + 2;
 
-template <typename XT, typename UT>
+// PAIR: slot b carries problem 2b in channels 0..7 and problem 2b + 1 in channels 8..15 (packed
+// pairs); each is reduced with the first eight channels of W into its own u (absent problem
+// 2b + 1 = nprob is skipped), and `flags` holds per-problem flags.
+template <typename XT, typename UT, bool PAIR = false>
 __global__ __launch_bounds__(256) void out_update_kernel(const XT* __restrict__ x,
                                                          const float* __restrict__ W,
                                                          UT* __restrict__ u, int n, int tiles_x,
                                                          int tiles_per_prob,
                                                          const int* __restrict__ active,
                                                          const int* __restrict__ flags,
-                                                         int accumulate) {
-  __shared__ float Y[9][OU_SH * OU_SW];
+                                                         int accumulate, int nprob) {
+  constexpr int NO = PAIR ? 2 : 1;            // outputs per slot
+  __shared__ float Y[NO][9][OU_SH * OU_SW];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
-  if (flags != nullptr && flags[b] == 0) return;           // retired since the list was built
+  bool live[NO];
+  bool any = false;
+#pragma unroll
+  for (int h = 0; h < NO; ++h) {
+    const int prob = PAIR ? 2 * b + h : b;
+    live[h] = (!PAIR || prob < nprob) && (flags == nullptr || flags[prob] != 0);   // retired since the list was built
+    any = any || live[h];
+  }
+  if (!any) return;
   const int i0 = (tile / tiles_x) * OU_TH - 1, j0 = (tile % tiles_x) * OU_TW - 1;
   const XT* X = x + (size_t)b * n * n * C;
   for (int q = threadIdx.x; q < OU_SH * OU_SW; q += 256) {
     const int ii = i0 + q / OU_SW, jj = j0 + q % OU_SW;
-    float y[9];
+    float y[NO][9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) y[k] = 0.f;
+    for (int h = 0; h < NO; ++h)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) y[h][k] = 0.f;
     if (ii >= 0 && ii < n && jj >= 0 && jj < n) {
       float v[C];
       load16(X + ((size_t)ii * n + jj) * C, v);
 #pragma unroll
-      for (int c = 0; c < C; ++c)
+      for (int c = 0; c < C; ++c) {
+        const int h = PAIR ? c / 8 : 0, cc = PAIR ? c % 8 : c;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) y[k] = fmaf(W[c * 9 + k], v[c], y[k]);
+        for (int k = 0; k < 9; ++k) y[h][k] = fmaf(W[cc * 9 + k], v[c], y[h][k]);
+      }
     }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Y[k][q] = y[k];
+    for (int h = 0; h < NO; ++h)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Y[h][k][q] = y[h][k];
   }
   __syncthreads();
-  const size_t ubase = (size_t)b * n * n;
-  for (int o = threadIdx.x; o < OU_TH * OU_TW; o += 256) {
-    const int r = o / OU_TW, cc = o % OU_TW;
-    const int i = i0 + 1 + r, j = j0 + 1 + cc;
-    if (i >= n || j >= n) continue;
-    // output (r, cc) sits at staged (r + 1, cc + 1); tap (p, q) reads staged (r + p, cc + q)
-    float acc = 0.f;
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+  for (int h = 0; h < NO; ++h) {
+    if (!live[h]) continue;
+    const size_t ubase = (size_t)(PAIR ? 2 * b + h : b) * n * n;
+    for (int o = threadIdx.x; o < OU_TH * OU_TW; o += 256) {
+      const int r = o / OU_TW, cc = o % OU_TW;
+      const int i = i0 + 1 + r, j = j0 + 1 + cc;
+      if (i >= n || j >= n) continue;
+      // output (r, cc) sits at staged (r + 1, cc + 1); tap (p, q) reads staged (r + p, cc + q)
+      float acc = 0.f;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) acc += Y[p * 3 + q][(r + p) * OU_SW + cc + q];
-    UT* U = u + ubase + (size_t)i * n + j;
-    *U = accumulate ? *U + (UT)acc : (UT)acc;
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc += Y[h][p * 3 + q][(r + p) * OU_SW + cc + q];
+      UT* U = u + ubase + (size_t)i * n + j;
+      *U = accumulate ? *U + (UT)acc : (UT)acc;
+    }
+  }
+}
+
+template <bool PAIR>
+static void out_update_launch(StateType t, const void* x, const float* Wout, void* u, bool u_f64, int n,
+                              int slots, int nprob, const int* active, hipStream_t st, bool accumulate,
+                              const int* flags) {
+  const int tx = (n + OU_TW - 1) / OU_TW, ty = (n + OU_TH - 1) / OU_TH;
+  const dim3 grid(tx * ty * slots), blk(256);
+  const int acc = accumulate ? 1 : 0;
+  if (t != ST_BF16) {
+    if (u_f64)
+      hipLaunchKernelGGL((out_update_kernel<float, double, PAIR>), grid, blk, 0, st, (const float*)x,
+                         Wout, (double*)u, n, tx, tx * ty, active, flags, acc, nprob);
+    else
+      hipLaunchKernelGGL((out_update_kernel<float, float, PAIR>), grid, blk, 0, st, (const float*)x,
+                         Wout, (float*)u, n, tx, tx * ty, active, flags, acc, nprob);
+  } else {
+    if (u_f64)
+      hipLaunchKernelGGL((out_update_kernel<bf16_t, double, PAIR>), grid, blk, 0, st, (const bf16_t*)x,
+                         Wout, (double*)u, n, tx, tx * ty, active, flags, acc, nprob);
+    else
+      hipLaunchKernelGGL((out_update_kernel<bf16_t, float, PAIR>), grid, blk, 0, st, (const bf16_t*)x,
+                         Wout, (float*)u, n, tx, tx * ty, active, flags, acc, nprob);
   }
 }
 
 void launch_out_update(StateType t, const void* x, const float* Wout, void* u, bool u_f64, int n,
                        int B, const int* active, hipStream_t st, bool accumulate, const int* flags) {
-  const int tx = (n + OU_TW - 1) / OU_TW, ty = (n + OU_TH - 1) / OU_TH;
-  const dim3 grid(tx * ty * B), blk(256);
-  const int acc = accumulate ? 1 : 0;
-  if (t != ST_BF16) {
-    if (u_f64)
-      hipLaunchKernelGGL((out_update_kernel<float, double>), grid, blk, 0, st, (const float*)x,
-                         Wout, (double*)u, n, tx, tx * ty, active, flags, acc);
-    else
-      hipLaunchKernelGGL((out_update_kernel<float, float>), grid, blk, 0, st, (const float*)x,
-                         Wout, (float*)u, n, tx, tx * ty, active, flags, acc);
-  } else {
-    if (u_f64)
-      hipLaunchKernelGGL((out_update_kernel<bf16_t, double>), grid, blk, 0, st, (const bf16_t*)x,
-                         Wout, (double*)u, n, tx, tx * ty, active, flags, acc);
-    else
-      hipLaunchKernelGGL((out_update_kernel<bf16_t, float>), grid, blk, 0, st, (const bf16_t*)x,
-                         Wout, (float*)u, n, tx, tx * ty, active, flags, acc);
-  }
+  out_update_launch<false>(t, x, Wout, u, u_f64, n, B, B, active, st, accumulate, flags);
+}
+
+void launch_out_update_pairs(StateType t, const void* x, const float* Wout, void* u, bool u_f64, int n,
+                             int slots, int nprob, const int* active, hipStream_t st, bool accumulate,
+                             const int* flags) {
+  out_update_launch<true>(t, x, Wout, u, u_f64, n, slots, nprob, active, st, accumulate, flags);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -112,7 +112,7 @@ void free_problem(mgcnn_ctx* c) {
   drop_graph(c);
   auto fr = [](void* p) { if (p) (void)hipFree(p); };
   fr(c->d_a); fr(c->d_b); fr(c->d_rt); fr(c->d_partial); fr(c->d_nf2);
-  fr(c->d_active); fr(c->d_plist); fr(c->d_status); fr(c->d_iters); fr(c->d_relres);
+  fr(c->d_active); fr(c->d_plist); fr(c->d_slist); fr(c->d_status); fr(c->d_iters); fr(c->d_relres);
   for (auto p : c->s) fr(p);
   for (auto p : c->xin) fr(p);
   for (auto p : c->xdn) fr(p);
@@ -122,7 +122,7 @@ void free_problem(mgcnn_ctx* c) {
   gmg_free(c);
   c->d_a = c->d_b = c->d_rt = nullptr;
   c->d_partial = c->d_nf2 = c->d_relres = nullptr;
-  c->d_active = c->d_plist = c->d_status = c->d_iters = nullptr;
+  c->d_active = c->d_plist = c->d_slist = c->d_status = c->d_iters = nullptr;
   c->alloc_n = c->alloc_B = 0;
   c->ready = false;
 }
@@ -145,10 +145,15 @@ int ensure_problem(mgcnn_ctx* c, int n, int B) {
   int m = n;
   for (int l = 0; l < L; ++l) { c->nl[l] = m; m = (m - 1) / 2; }
   const size_t nn = (size_t)n * n * B;
+  // packed pairs: (B + 1) / 2 state slots; rt holds two planes per slot, the unused second half
+  // of an odd batch's last slot stays zero
+  const int slots = c->pairs() ? (B + 1) / 2 : B;
   int r;
   if ((r = alloc(c, (void**)&c->d_a, nn * 4))) return r;
   if ((r = alloc(c, (void**)&c->d_b, (size_t)B * 2 * 4))) return r;
-  if ((r = alloc(c, (void**)&c->d_rt, nn * 4))) return r;
+  if ((r = alloc(c, (void**)&c->d_rt, (size_t)n * n * (c->pairs() ? 2 * slots : B) * 4))) return r;
+  if (c->pairs()) HIP_TRY(c, hipMemset(c->d_rt, 0, (size_t)n * n * 2 * slots * 4));
+  if ((r = alloc(c, (void**)&c->d_slist, (size_t)slots * 4))) return r;
   c->tiles = residual_tiles(n);
   if ((r = alloc(c, (void**)&c->d_partial, (size_t)c->tiles * B * 8))) return r;
   if ((r = alloc(c, (void**)&c->d_nf2, (size_t)B * 8))) return r;
@@ -162,14 +167,15 @@ int ensure_problem(mgcnn_ctx* c, int n, int B) {
     if ((r = gmg_alloc(c, n, B))) return r;
   } else {
   for (int l = 0; l < L; ++l) {
-    const size_t bytes = (size_t)c->nl[l] * c->nl[l] * B * C * c->state_bytes();
-    if ((r = alloc(c, &c->s[l], (size_t)c->nl[l] * c->nl[l] * B * C * c->s_bytes()))) return r;
+    const size_t bytes = (size_t)c->nl[l] * c->nl[l] * slots * C * c->state_bytes();
+    if ((r = alloc(c, &c->s[l], (size_t)c->nl[l] * c->nl[l] * slots * C * c->s_bytes()))) return r;
     if ((r = alloc(c, &c->xin[l], bytes))) return r;
     if ((r = alloc(c, &c->xdn[l], bytes))) return r;
   }
   }
   c->alloc_n = n;
   c->alloc_B = B;
+  c->slots = slots;
   c->L = L;
   c->gen += 1;
   return MGCNN_OK;
@@ -194,7 +200,8 @@ int run_chunk(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int 
   }
   auto& G = c->gcache;
   const bool hit = G.exec && G.f == f && G.u == u && G.tol == tol && G.maxit == maxit &&
-                   G.chunk == chunk && G.gen == c->gen && G.count == c->plist_count;
+                   G.chunk == chunk && G.gen == c->gen && G.count == c->plist_count &&
+                   G.scount == c->slist_count;
   if (!hit) {
     drop_graph(c);
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
@@ -208,6 +215,7 @@ int run_chunk(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, int 
     if (e != hipSuccess) { (void)hipGraphDestroy(g); G.exec = nullptr; return hip_fail(c, e, "hipGraphInstantiate"); }
     G.graph = g; G.f = f; G.u = u; G.tol = tol; G.maxit = maxit; G.chunk = chunk; G.gen = c->gen;
     G.count = c->plist_count;
+    G.scount = c->slist_count;
   }
   HIP_TRY(c, hipGraphLaunch(G.exec, c->stream));
   return MGCNN_OK;
@@ -234,7 +242,8 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool
       // finest level: reChannel-in folded into the down smoother
       Prof p(c, MGCNN_K_SMOOTH_IN, 0, nodes(0) * (4.0 + S + SS), nodes(0) * (FL_SMOOTH + FL_IN));
       launch_smooth_in(st == ST_F32X && c->opts.f32_split == 2 ? ST_F32X2 : st, c->d_rt, c->s[0],
-                       c->W(c->off.solve_in), c->W(c->off.smooth_down), c->xdn[0], c->nl[0], B, active, s, sb);
+                       c->W(c->off.solve_in), c->W(c->off.smooth_down), c->xdn[0], c->nl[0], B, active, s, sb,
+                       c->pairs());
     } else {
       Prof p(c, MGCNN_K_SMOOTH_DOWN, l, nodes(l) * (2.0 * S + SS), nodes(l) * FL_SMOOTH);
       launch_conv16(CM_SMOOTH, st, c->xin[l], c->s[l], c->W(c->off.smooth_down), nullptr, c->xdn[l],
@@ -267,8 +276,12 @@ int vcycle(mgcnn_ctx* c, void* u, bool u_f64, const int* active, int count, bool
   {
     Prof p(c, MGCNN_K_OUT_UPDATE, 0, nodes(0) * (S + (accumulate ? 2.0 : 1.0) * (u_f64 ? 8 : 4)),
            nodes(0) * (FL_IN + 1.0));
-    launch_out_update(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, active, s,
-                      accumulate, flags);
+    if (c->pairs())
+      launch_out_update_pairs(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, c->B, active, s,
+                              accumulate, flags);
+    else
+      launch_out_update(st, c->xin[0], c->W(c->off.solve_out), u, u_f64, c->n, B, active, s,
+                        accumulate, flags);
   }
   LAUNCH_CHECK(c);
   return MGCNN_OK;
@@ -287,7 +300,44 @@ int solve_step(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit) {
     launch_finalize(c->d_partial, c->tiles, c->d_nf2, tol, maxit, c->d_active, c->d_status,
                     c->d_iters, c->d_relres, c->B, c->stream);
   }
+  if (c->pairs()) return vcycle(c, u, c->u64(), c->d_slist, c->slist_count, true, c->d_active);
   return vcycle(c, u, c->u64(), c->d_plist, c->plist_count, true, c->d_active);
+}
+
+// Packed pairs: the weights of a network with at most 8 hidden channels, given in the 16-channel
+// layout (every entry that reads or writes a channel >= 8 zero), turned into the weights that
+// run two problems side by side: every 16 -> 16 conv becomes diag(W8, W8) and each tanh layer's
+// bias repeats its first eight entries; the 4 -> 16, 1 -> 16 and 16 -> 1 convs stay as given
+// (their kernels use the first eight output rows / input columns for each half).  Returns false
+// if the weights use channels 8..15.
+bool pack_pair_weights(const WeightOffsets& off, const float* w, std::vector<float>& out) {
+  out.assign(w, w + off.total);
+  auto zero = [](float v) { return v == 0.f; };
+  // 16 -> 16 convs W[o][c][9]
+  const size_t sq[] = {off.res_w[0], off.res_w[1], off.res_w[2], off.res_w[3], off.setup_restrict,
+                       off.smooth_down, off.smooth_up, off.restrict_, off.prolong};
+  for (size_t base : sq) {
+    for (int o = 0; o < C; ++o)
+      for (int ci = 0; ci < C; ++ci)
+        for (int k = 0; k < 9; ++k) {
+          const float v = w[base + ((size_t)o * C + ci) * 9 + k];
+          if ((o >= 8 || ci >= 8) && !zero(v)) return false;
+          const bool diag = (o < 8) == (ci < 8);
+          out[base + ((size_t)o * C + ci) * 9 + k] = diag ? w[base + ((size_t)(o % 8) * C + ci % 8) * 9 + k] : 0.f;
+        }
+  }
+  for (int k = 0; k < NUM_SETUP_LAYERS; ++k)
+    for (int o = 0; o < C; ++o) {
+      if (o >= 8 && !zero(w[off.res_b[k] + o])) return false;
+      out[off.res_b[k] + o] = w[off.res_b[k] + o % 8];
+    }
+  for (int o = 8; o < C; ++o) {
+    for (int k = 0; k < 4 * 9; ++k)
+      if (!zero(w[off.setup_in + (size_t)o * 4 * 9 + k])) return false;
+    for (int k = 0; k < 9; ++k)
+      if (!zero(w[off.solve_in + (size_t)o * 9 + k]) || !zero(w[off.solve_out + (size_t)o * 9 + k])) return false;
+  }
+  return true;
 }
 
 }  // namespace api
@@ -318,6 +368,7 @@ void mgcnn_default_opts(mgcnn_opts* o) {
   o->deflate = 0;
   o->levels = 0;
   o->up_post = 0;
+  o->pack_pairs = 0;
 }
 
 size_t mgcnn_num_weights(int channels) {
@@ -356,6 +407,9 @@ int mgcnn_create(mgcnn_ctx** out, const mgcnn_opts* opts, const float* weights_h
   if (o.method == MGCNN_METHOD_FGMRES && o.deflate > 0 && 2 * o.deflate > o.restart) return MGCNN_E_ARG;
   if (o.levels < -11 || o.levels > 12) return MGCNN_E_ARG;
   if (o.up_post != 0 && o.up_post != 1) return MGCNN_E_ARG;
+  if (o.pack_pairs != 0 && o.pack_pairs != 1) return MGCNN_E_ARG;
+  if (o.pack_pairs && (o.method != MGCNN_METHOD_STATIONARY || o.precond != MGCNN_PRECOND_NETWORK || o.s_bf16))
+    return MGCNN_E_ARG;
   mgcnn_ctx* c = new (std::nothrow) mgcnn_ctx();
   if (!c) return MGCNN_E_NOMEM;
   c->opts = o;
@@ -376,6 +430,13 @@ int mgcnn_set_weights(mgcnn_ctx* c, const float* w) {
     launch_zero(c->d_w, c->off.total * 4, c->stream);
     LAUNCH_CHECK(c);
     return MGCNN_OK;
+  }
+  std::vector<float> packed;
+  if (c->pairs()) {
+    if (!pack_pair_weights(c->off, w, packed))
+      return fail(c, MGCNN_E_ARG, "set_weights: pack_pairs needs a network of at most 8 hidden channels "
+                                  "(channels 8..15 zero)");
+    w = packed.data();
   }
   HIP_TRY(c, hipMemcpyAsync(c->d_w, w, c->off.total * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -444,17 +505,17 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
   // over all levels.  With f32 storage the level tensors hold the intermediates (c_l in xin_l,
   // the layers ping-pong between xdn_l and s_l and end in s_l); bf16 storage uses f32 level
   // pyramids kept in the context for the next setup of this size.
-  const int L = c->L;
+  const int L = c->L, SL = c->slots;                   // SL: state slots (packed pairs: (B + 1) / 2)
   const bool f32_store = c->state_bytes() == 4 && !c->s16();
   size_t pyr = 0;                                      // floats of one f32 level pyramid
-  for (int l = 0; l < L; ++l) pyr += (size_t)c->nl[l] * c->nl[l] * B * C;
+  for (int l = 0; l < L; ++l) pyr += (size_t)c->nl[l] * c->nl[l] * SL * C;
   if (!c->setup_tmp && (r = alloc(c, &c->setup_tmp, nn * 16 + (f32_store ? 0 : 3 * pyr * 4)))) return r;
   float* F = (float*)c->setup_tmp;
   float *cl[MAX_LEVELS], *za[MAX_LEVELS], *zb[MAX_LEVELS];
   {
     float* p = F + nn * 4;
     for (int l = 0; l < L; ++l) {
-      const size_t cnt = (size_t)c->nl[l] * c->nl[l] * B * C;
+      const size_t cnt = (size_t)c->nl[l] * c->nl[l] * SL * C;
       if (f32_store) {
         cl[l] = (float*)c->xin[l];
         za[l] = (float*)c->xdn[l];
@@ -468,12 +529,13 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
     }
   }
   launch_features(c->d_a, c->d_b, F, n, B, c->form(), s);
-  launch_conv_in(4, F, c->W(c->off.setup_in), cl[0], ST_F32, n, B, nullptr, s);
+  if (c->pairs()) launch_conv_in_pairs(F, c->W(c->off.setup_in), cl[0], n, B, s);
+  else launch_conv_in(4, F, c->W(c->off.setup_in), cl[0], ST_F32, n, B, nullptr, s);
   for (int l = 0; l + 1 < L; ++l)
     launch_conv16(CM_RESTRICT, ST_F32, cl[l], nullptr, c->W(c->off.setup_restrict), nullptr, cl[l + 1],
-                  c->nl[l], B, nullptr, s);
+                  c->nl[l], SL, nullptr, s);
   int bl[MAX_LEVELS];
-  for (int l = 0; l < L; ++l) bl[l] = B;
+  for (int l = 0; l < L; ++l) bl[l] = SL;
   const StateType tanh_t = c->opts.f32_split ? ST_F32X : ST_F32;
   float** src[NUM_SETUP_LAYERS] = {cl, za, zb, za};
   float** dst[NUM_SETUP_LAYERS] = {za, zb, za, zb};
@@ -482,7 +544,7 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
                        c->W(c->off.res_b[k]), s);
   if (!f32_store)
     for (int l = 0; l < L; ++l)
-      launch_f32_to_bf16(zb[l], (bf16_t*)c->s[l], (size_t)c->nl[l] * c->nl[l] * B * C, s);
+      launch_f32_to_bf16(zb[l], (bf16_t*)c->s[l], (size_t)c->nl[l] * c->nl[l] * SL * C, s);
   LAUNCH_CHECK(c);
   c->ready = true;
   return MGCNN_OK;
@@ -522,10 +584,14 @@ int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, in
   LAUNCH_CHECK(c);
   // the launches cover a compact list of the problems still iterating, rebuilt at every host
   // check; problems that finish between checks are held by their flag (u is left unchanged)
-  std::vector<int> act(B), plist(B);
+  // (packed pairs: the state launches cover the slots with a live problem, `slist`)
+  std::vector<int> act(B), plist(B), slist(c->slots);
   for (int b = 0; b < B; ++b) plist[b] = b;
+  for (int v = 0; v < c->slots; ++v) slist[v] = v;
   c->plist_count = B;
+  c->slist_count = c->slots;
   HIP_TRY(c, hipMemcpyAsync(c->d_plist, plist.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(c->d_slist, slist.data(), (size_t)c->slots * 4, hipMemcpyHostToDevice, s));
   int steps = 0;
   const int max_steps = maxit + 1;
   while (steps < max_steps) {
@@ -543,7 +609,14 @@ int mgcnn_solve(mgcnn_ctx* c, const float* f, void* u, double tol, int maxit, in
     if (cnt != c->plist_count) {
       c->plist_count = cnt;
       HIP_TRY(c, hipMemcpyAsync(c->d_plist, plist.data(), (size_t)cnt * 4, hipMemcpyHostToDevice, s));
-      HIP_TRY(c, hipStreamSynchronize(s));   // plist is rewritten at the next check
+      if (c->pairs()) {
+        int sc = 0;
+        for (int v = 0; v < c->slots; ++v)
+          if (act[2 * v] != 0 || (2 * v + 1 < B && act[2 * v + 1] != 0)) slist[sc++] = v;
+        c->slist_count = sc;
+        HIP_TRY(c, hipMemcpyAsync(c->d_slist, slist.data(), (size_t)sc * 4, hipMemcpyHostToDevice, s));
+      }
+      HIP_TRY(c, hipStreamSynchronize(s));   // plist and slist are rewritten at the next check
     }
   }
   std::vector<int> st(B), it(B);
@@ -571,6 +644,7 @@ int mgcnn_forward(mgcnn_ctx* c, const float* f, void* u, int K, int record) {
   if (!f || !u || K < 0) return fail(c, MGCNN_E_ARG, "forward: bad argument");
   if (record && c->gmg_on())
     return fail(c, MGCNN_E_STATE, "forward: recording needs the network preconditioner");
+  if (record && c->pairs()) return fail(c, MGCNN_E_STATE, "forward: no recording with pack_pairs");
   if (record) return forward_record(c, f, (float*)u, K);
   for (int k = 0; k < K; ++k) {
     {
@@ -579,7 +653,7 @@ int mgcnn_forward(mgcnn_ctx* c, const float* f, void* u, int K, int record) {
       launch_residual(c->d_a, c->d_b, f, u, c->u64(), c->d_rt, c->d_partial, c->n, c->B, nullptr,
                       c->form(), c->stream);
     }
-    int r = vcycle(c, u, c->u64(), nullptr, c->B);
+    int r = vcycle(c, u, c->u64(), nullptr, c->slots);
     if (r) return r;
   }
   LAUNCH_CHECK(c);
@@ -591,7 +665,7 @@ int mgcnn_apply(mgcnn_ctx* c, const float* r, float* z) {
   if (!c->ready) return fail(c, MGCNN_E_STATE, "apply: call mgcnn_setup first");
   if (!r || !z) return fail(c, MGCNN_E_ARG, "apply: null pointer");
   launch_scale_by_diag(c->d_a, c->d_b, r, c->d_rt, c->n, c->B, c->form(), c->stream);
-  return vcycle(c, z, false, nullptr, c->B, false);
+  return vcycle(c, z, false, nullptr, c->slots, false);
 }
 
 int mgcnn_residual_norms(mgcnn_ctx* c, const float* f, const void* u, double* relres_host) {
@@ -616,6 +690,7 @@ int mgcnn_get_setup_tensor(mgcnn_ctx* c, int level, float* out) {
   if (!c) return MGCNN_E_ARG;
   if (!c->ready) return fail(c, MGCNN_E_STATE, "get_setup_tensor: no setup");
   if (c->gmg_on()) return fail(c, MGCNN_E_STATE, "get_setup_tensor: no setup tensors with GMG");
+  if (c->pairs()) return fail(c, MGCNN_E_STATE, "get_setup_tensor: setup tensors are packed in pairs");
   if (level < 1 || level > c->L || !out) return fail(c, MGCNN_E_ARG, "get_setup_tensor: bad level");
   const int m = c->nl[level - 1];
   const size_t cnt = (size_t)m * m * c->B * C;

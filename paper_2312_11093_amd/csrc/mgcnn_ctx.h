@@ -30,6 +30,10 @@ struct mgcnn_ctx {
   int* d_active = nullptr;          // per-problem flags of the stationary solve
   int* d_plist = nullptr;           // compact list of the problems still iterating
   int plist_count = 0;              // its length (the grid size of the solver launches)
+  // packed pairs (opts.pack_pairs): slot b of every state tensor holds problems 2b and 2b + 1
+  int slots = 0;                    // state-tensor slots: B, or (B + 1) / 2 with packed pairs
+  int* d_slist = nullptr;           // packed pairs: compact list of the slots with a live problem
+  int slist_count = 0;
   int* d_status = nullptr;
   int* d_iters = nullptr;
   double* d_relres = nullptr;
@@ -58,7 +62,7 @@ struct mgcnn_ctx {
     const void* f = nullptr;
     void* u = nullptr;
     double tol = 0.0;
-    int maxit = -1, chunk = 0, gen = -1, count = -1;
+    int maxit = -1, chunk = 0, gen = -1, count = -1, scount = -1;
   } gcache;
   int gen = 0;                      // bumped whenever problem buffers are reallocated
   hipStream_t cap_stream = nullptr; // capture stream used when the context stream is the null stream
@@ -128,6 +132,7 @@ struct mgcnn_ctx {
     return opts.f32_split ? mg::ST_F32X : mg::ST_F32;
   }
   bool u64() const { return opts.u_dtype == MGCNN_U_F64; }
+  bool pairs() const { return opts.pack_pairs != 0; }
   bool gmg_on() const { return opts.precond == MGCNN_PRECOND_GMG; }
   int form() const { return opts.op_form; }
   const float* W(size_t o) const { return d_w + o; }

@@ -77,15 +77,26 @@ void launch_prolong_add(StateType t, const void* xc, const float* WT, void* yf, 
                         const int* active, hipStream_t st);
 
 // Finest-level down smoother with the reChannel-in conv folded in: y = x1 + W*(s.x1) with
-// x1 = W_in * rt computed on the staged tile.
+// x1 = W_in * rt computed on the staged tile.  pairs: packed pairs (slot b = problems 2b and
+// 2b + 1 in channels 0..7 / 8..15, rt [2 B][m][m], W_in's first eight rows; s in the state type).
 void launch_smooth_in(StateType t, const float* rt, const void* s, const float* Win, const float* W,
-                      void* y, int m, int B, const int* active, hipStream_t st, bool s_bf16 = false);
+                      void* y, int m, int B, const int* active, hipStream_t st, bool s_bf16 = false,
+                      bool pairs = false);
 
 // u += W_out * x (16 -> 1 same-size conv), u f32 or f64; u = W_out * x when !accumulate.
 // flags (optional, indexed by problem): problems whose flag is 0 keep u unchanged.
 void launch_out_update(StateType t, const void* x, const float* Wout, void* u, bool u_f64,
                        int n, int B, const int* active, hipStream_t st, bool accumulate = true,
                        const int* flags = nullptr);
+// Packed pairs: `slots` slots (a list of slot indices in `active`, or all), problem 2b + h from
+// channels 8h..8h+7 of slot b with W_out's first eight columns; nprob problems in u (an odd
+// nprob leaves the last slot's second half unused); flags per problem.
+void launch_out_update_pairs(StateType t, const void* x, const float* Wout, void* u, bool u_f64, int n,
+                             int slots, int nprob, const int* active, hipStream_t st, bool accumulate,
+                             const int* flags);
+// Setup reChannel of packed pairs: F [nprob][n][n][4] -> out [(nprob + 1) / 2][n][n][16] (f32),
+// problem 2b + h into channels 8h..8h+7 of slot b with the first eight rows of W.
+void launch_conv_in_pairs(const float* in, const float* W, float* out, int n, int nprob, hipStream_t st);
 
 // r = f - A(a,b) u ; rt = r / D (f32) ; partial[b][tile] = sum r^2 (f64).
 // u == nullptr means u = 0.  mode64: u is f64 and the arithmetic is f64; otherwise u is f32 and

@@ -268,6 +268,7 @@ extern "C" {
 
 int mgcnn_set_weights_device(mgcnn_ctx* c, const float* w_dev) {
   if (!c || !w_dev) return MGCNN_E_ARG;
+  if (c->pairs()) return fail(c, MGCNN_E_STATE, "set_weights_device: not with pack_pairs (host weights only)");
   c->tr.K = 0;             // a recorded forward was taken with the previous weights
   c->tr.f = nullptr;
   HIP_TRY(c, hipMemcpyAsync(c->d_w, w_dev, c->off.total * 4, hipMemcpyDeviceToDevice, c->stream));
@@ -288,6 +289,7 @@ int mgcnn_loss(mgcnn_ctx* c, const float* f, const float* u, double* loss_host, 
   if (!c) return MGCNN_E_ARG;
   if (!c->ready) return fail(c, MGCNN_E_STATE, "loss: call mgcnn_setup first");
   if (!f || !u) return fail(c, MGCNN_E_ARG, "loss: null f or u");
+  if (c->pairs()) return fail(c, MGCNN_E_STATE, "loss: no training with pack_pairs");
   if (c->u64()) return fail(c, MGCNN_E_ARG, "loss: needs f32 u");
   int r = ensure_train(c, std::max(c->tr.alloc_K, 1));
   if (r) return r;
@@ -316,6 +318,7 @@ int mgcnn_backward(mgcnn_ctx* c, const float* dL_du, float* dL_dweights, float* 
   if (!c) return MGCNN_E_ARG;
   if (!c->ready) return fail(c, MGCNN_E_STATE, "backward: call mgcnn_setup first");
   if (c->gmg_on()) return fail(c, MGCNN_E_STATE, "backward: no weights with the GMG preconditioner");
+  if (c->pairs()) return fail(c, MGCNN_E_STATE, "backward: no training with pack_pairs");
   if (c->opts.up_post) return fail(c, MGCNN_E_ARG, "backward: no reverse pass for up_post");
   auto& T = c->tr;
   if (T.K <= 0 || T.f == nullptr || T.alloc_n != c->n || T.alloc_B != c->B)

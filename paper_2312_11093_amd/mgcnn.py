@@ -34,7 +34,7 @@ class mgcnn_opts(ctypes.Structure):
                 ("s_bf16", ctypes.c_int), ("inner_steps", ctypes.c_int), ("gs_passes", ctypes.c_int),
                 ("precond", ctypes.c_int), ("gmg_levels", ctypes.c_int), ("gmg_sweeps", ctypes.c_int),
                 ("gmg_omega", ctypes.c_float), ("op_form", ctypes.c_int), ("deflate", ctypes.c_int),
-                ("levels", ctypes.c_int), ("up_post", ctypes.c_int)]
+                ("levels", ctypes.c_int), ("up_post", ctypes.c_int), ("pack_pairs", ctypes.c_int)]
 
 
 class mgcnn_kernel_stat(ctypes.Structure):
@@ -194,12 +194,14 @@ class Solver:
                  f32_split: bool | int = True, s_bf16: bool = False, inner_steps: int = 1,
                  gs_passes: int = 2, precond: str = "network", gmg_levels: int = 0,
                  gmg_sweeps: int = 3, gmg_omega: float = 0.67, form: str = "div", deflate: int = 0,
-                 levels: int = 0, up_post: bool = False):
+                 levels: int = 0, up_post: bool = False, pack_pairs: bool = False):
         """weights: the flat network weights, or None with precond="gmg" (the geometric
         multigrid baseline has none).  form: "div" (divergence form, harmonic face
         coefficients) or "nondiv" (the non-divergence form -a Lap(u) + b . grad u).
         levels: network levels, 0 = log2(n+1), -d = log2(n+1) - d, > 0 = that many.
-        up_post: up smoother in the adjoint form x + s . (W_up * x) (symmetric variant)."""
+        up_post: up smoother in the adjoint form x + s . (W_up * x) (symmetric variant).
+        pack_pairs: two problems per 16-channel state slot, for weights of at most 8 hidden
+        channels in the 16-channel layout (stationary method, network preconditioner)."""
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -220,6 +222,7 @@ class Solver:
         o.deflate = int(deflate)
         o.levels = int(levels)
         o.up_post = int(bool(up_post))
+        o.pack_pairs = int(bool(pack_pairs))
         self.opts = o
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         wp = _weights_ptr(self, weights, self._L.mgcnn_num_weights(16))

@@ -112,16 +112,37 @@ def test_default_options_and_option_checks(lib):
     lib.mgcnn_default_opts(ctypes.byref(o))
     assert (o.channels, o.method, o.restart, o.gs_passes) == (16, 0, 30, 2)
     assert (o.precond, o.gmg_levels, o.gmg_sweeps, o.op_form, o.deflate, o.levels, o.up_post) == (0, 0, 3, 0, 0, 0, 0)
+    assert o.pack_pairs == 0
     assert abs(o.gmg_omega - 0.67) < 1e-7
     h = ctypes.c_void_p()
     for field, value in (("precond", 2), ("gmg_sweeps", 0), ("gmg_sweeps", 5), ("gmg_levels", -1),
                          ("op_form", 2), ("deflate", -1), ("deflate", 33), ("levels", -12), ("levels", 13), ("up_post", 2),
                          ("gmg_omega", 0.0), ("gmg_omega", 2.0), ("gs_passes", 3), ("f32_split", 3),
-                         ("f32_split", -1)):
+                         ("f32_split", -1), ("pack_pairs", 2)):
         bad = mgcnn.mgcnn_opts()
         lib.mgcnn_default_opts(ctypes.byref(bad))
         setattr(bad, field, value)
         assert lib.mgcnn_create(ctypes.byref(h), ctypes.byref(bad), None, None) == -1, field
+
+
+def test_create_checks_the_pack_pairs_options(lib):
+    """Packed pairs run the stationary method with the network preconditioner and f32 or bf16
+    setup tensors in the state's type: FGMRES, PCG, GMG and s_bf16 are rejected before any
+    device call; a group with packed pairs is rejected too."""
+    from paper_2312_11093_amd import mgcnn
+    h = ctypes.c_void_p()
+    for changes in ({"method": 1, "restart": 30}, {"method": 2, "up_post": 1}, {"precond": 1}, {"s_bf16": 1}):
+        bad = mgcnn.mgcnn_opts()
+        lib.mgcnn_default_opts(ctypes.byref(bad))
+        bad.pack_pairs = 1
+        for k, v in changes.items():
+            setattr(bad, k, v)
+        assert lib.mgcnn_create(ctypes.byref(h), ctypes.byref(bad), None, None) == -1, changes
+    o = mgcnn.mgcnn_opts()
+    lib.mgcnn_default_opts(ctypes.byref(o))
+    o.pack_pairs = 1
+    g = ctypes.c_void_p()
+    assert lib.mgcnn_group_create(ctypes.byref(g), ctypes.byref(o), None, None) == -1
 
 
 def test_create_rejects_deflation_beyond_half_the_restart(lib):

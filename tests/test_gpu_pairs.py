@@ -1,0 +1,142 @@
+"""GPU: packed pairs (opts.pack_pairs) for networks of at most 8 hidden channels.  Two problems
+share one 16-channel state slot with block-diagonal 16 -> 16 weights; per problem the network
+must stay the C-channel network of the oracle (the same operator as its zero-padded 16-channel
+form), including the empty half of an odd batch's last slot.  f32 state is held to the f32
+tolerance element by element; solves are checked on the oracle's residual and against the
+unpacked library's iteration counts."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import solve as osv
+from parity_util import assert_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_11093_amd import Solver  # noqa: E402
+from paper_2312_11093_amd import mgcnn as M  # noqa: E402
+from paper_2312_11093_amd.weights import embed_channels  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TRAINED = os.path.join(ROOT, "paper_2312_11093_amd", "trained", "t5_c8.npy")
+F32_TOL = 1e-5
+SPLIT2_TOL = 1e-4
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dtype)
+
+
+def weights(kind):
+    if kind == "xavier8":
+        return embed_channels(datagen.xavier_weights(8, 2))
+    if kind == "xavier4":
+        return embed_channels(datagen.xavier_weights(4, 3))
+    return embed_channels(np.load(TRAINED, allow_pickle=False))
+
+
+@pytest.mark.parametrize("kind,workload,form,levels", [
+    ("xavier8", "mixture127", "div", 0), ("xavier4", "mixture127", "div", 0),
+    ("trained", "paper_re1e3", "nondiv", -1)])
+@pytest.mark.parametrize("n,B", [(15, 3), (63, 4), (127, 5)])
+@pytest.mark.parametrize("split", [0, 1, 2])
+def test_pairs_apply_matches_oracle(kind, workload, form, levels, n, B, split):
+    """z = B(r / D) per problem with packed pairs against the oracle (f32 state: f32 matrix
+    instructions, the three-way split, the two-way split in the finest down smoother)."""
+    say("pairs apply", kind, n, B, "split", split)
+    w = weights(kind)
+    a, b, f = datagen.make_batch(workload, n, B, seed=7)
+    r = np.random.default_rng(n + B).standard_normal((B, n, n)).astype(np.float32)
+    S = Solver(w, state="f32", f32_split=split, form=form, levels=levels, pack_pairs=True)
+    S.setup(dev(a), b)
+    L = S.levels
+    z = S.apply(dev(r)).cpu().numpy()
+    S.close()
+    tol = SPLIT2_TOL if split == 2 else F32_TOL
+    for p in range(B):
+        exp = osv.Solver(w, a[p], b[p], levels=L, form=form).correction(r[p].astype(np.float64))
+        assert_close(z[p], exp, tol, f"problem {p}", say)
+
+
+@pytest.mark.parametrize("state", ["f32", "bf16"])
+def test_pairs_forward_matches_unpacked(state):
+    """Three fixed iterations u += B((f - A u) / D) on a ragged batch (odd B, n = 127): the packed
+    library against the unpacked one with the same weights, per problem (f32: the f32 tolerance;
+    bf16: the same tolerance scaled by 2^-8 / 2^-24 would be vacuous, so bf16 is held to 1e-2,
+    the size of one bf16 rounding of the state times the few layers between roundings)."""
+    say("pairs forward vs unpacked", state)
+    n, B, K = 127, 5, 3
+    w = weights("trained")
+    a, b, f = datagen.make_batch("paper_re1e3", n, B, seed=11)
+    out = {}
+    for pack in (False, True):
+        S = Solver(w, state=state, u="f64", form="nondiv", levels=-1, pack_pairs=pack)
+        S.setup(dev(a), b)
+        u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+        S.forward(dev(f), u, K)
+        out[pack] = u.cpu().numpy()
+        S.close()
+    tol = F32_TOL if state == "f32" else 1e-2
+    for p in range(B):
+        assert_close(out[True][p], out[False][p], tol, f"problem {p}", say)
+
+
+@pytest.mark.parametrize("state,graph", [("f32", False), ("f32", True), ("bf16", True)])
+def test_pairs_solve_paper_problems(state, graph):
+    """Stationary solves of five 63^2 paper problems (odd batch, one with f = 0) to 1e-8 with the
+    trained network: the oracle's f64 residual of every returned solution is <= tol, u = 0 for
+    the zero right-hand side, and the iteration counts are those of the unpacked library within
+    one (the summation order of the block-diagonal products differs)."""
+    say("pairs solve", state, "graph" if graph else "eager")
+    n, B, tol = 63, 5, 1e-8
+    w = weights("trained")
+    a, b, f = datagen.make_batch("paper_re1e3", n, B, seed=3)
+    f[3] = 0.0
+    its = {}
+    for pack in (False, True):
+        S = Solver(w, state=state, u="f64", form="nondiv", levels=-1, use_graph=graph, check_every=1,
+                   pack_pairs=pack)
+        S.setup(dev(a), b)
+        u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+        st, it, rr, ps = S.solve(dev(f), u, tol, 100)
+        S.close()
+        say("  pack" if pack else "  unpacked", "iters", list(map(int, it)))
+        assert st == M.OK and (ps == 0).all()
+        un = u.cpu().numpy()
+        for p in range(B):
+            if p == 3:
+                assert not un[p].any() and int(it[p]) == 0
+                continue
+            assert osv.relres(a[p], b[p], f[p], un[p], "nondiv") <= tol * (1 + 1e-6)
+        its[pack] = np.asarray(it)
+    assert (np.abs(its[True] - its[False]) <= 1).all()
+
+
+def test_pairs_reject_wider_networks_and_training():
+    """A network that uses channels 8..15 cannot be packed (E_ARG when the weights are set);
+    the recorded forward and the setup-tensor read-out report E_STATE."""
+    say("pairs rejections")
+    with pytest.raises(M.MGCNNError) as e:
+        Solver(datagen.xavier_weights(16, 0), pack_pairs=True)
+    assert e.value.status == M.E_ARG
+    n, B = 15, 2
+    a, b, f = datagen.make_batch("mixture127", n, B, seed=1)
+    S = Solver(weights("xavier8"), state="f32", u="f32", pack_pairs=True)
+    S.setup(dev(a), b)
+    u = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
+    with pytest.raises(M.MGCNNError) as e:
+        S.forward(dev(f), u, 1, record=True)
+    assert e.value.status == M.E_STATE
+    S.close()
