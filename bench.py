@@ -377,9 +377,10 @@ def leg_paper1023(B=64, steps=3):
     white-noise coefficients with Re = 1000, v = (sin 0.5, cos 0.5), f = 1; Sec. 4.1), solved to
     1e-8 by the stationary iteration of Eq. (1) with the network trained by the paper's protocol
     (8 channels, Table 5; log2(n+1) - 1 levels), hipGraph-captured blocks of 4 iterations:
-    f32 state and bf16 state (both with f64 u, residual and norm), against the plain FP32 form
-    (f32 state on f32 MFMA, one problem per call, no graphs) and against the paper's GMG
-    (stationary, Sec. 4.1 settings) on the same batch."""
+    f32 state and bf16 state (both with f64 u, residual and norm), each also with packed pairs
+    (two problems per 16-channel state slot, which the 8-channel network allows), against the
+    plain FP32 form (f32 state on f32 MFMA, one problem per call, no graphs) and against the
+    paper's GMG (stationary, Sec. 4.1 settings) on the same batch."""
     import torch
     import datagen
     from paper_2312_11093_amd import Solver
@@ -405,11 +406,15 @@ def leg_paper1023(B=64, steps=3):
 
     res = {"workload": f"paper_re1e3: {B} problems at {n}x{n}, stationary, tol 1e-8",
            "weights": os.path.relpath(PAPER_WEIGHTS, ROOT)}
-    for name, state in (("network_f32_state", "f32"), ("network_bf16_state", "bf16")):
+    nets = (("network_f32_state", "f32", False), ("network_bf16_state", "bf16", False),
+            ("network_f32_pairs", "f32", True), ("network_bf16_pairs", "bf16", True))
+    sampled = {}                                   # the oracle re-checks problems 0 and B - 1 (CPU leg)
+    for name, state, pack in nets:
         S = Solver(w, state=state, u="f64", form="nondiv", levels=-1, use_graph=True, check_every=1,
-                   f32_split=2)
+                   f32_split=2, pack_pairs=pack)
         sec, it, ps = timed(S, da, b, df, u, steps)
         S.close()
+        sampled[name] = {p: u[p].cpu().numpy() for p in (0, B - 1)}
         res[name] = {"solves_per_s": round(B / sec, 2) if (ps == 0).all() else 0.0,
                      "ms_per_batch": round(1e3 * sec, 2), "iters_mean": float(np.mean(it)),
                      "iters_max": int(np.max(it)), "converged": int((ps == 0).sum())}
@@ -431,16 +436,17 @@ def leg_paper1023(B=64, steps=3):
                              "ms_per_batch": round(1e3 * sec, 2), "iters_mean": float(np.mean(it)),
                              "converged": int((ps == 0).sum())}
     pl = res["plain_fp32_unbatched"]["solves_per_s"]
-    for name in ("network_f32_state", "network_bf16_state"):
+    for name, _, _ in nets:
         res[name]["over_plain_fp32_unbatched"] = round(res[name]["solves_per_s"] / pl, 3)
         if res["gmg_stationary"]["solves_per_s"] > 0:
             res[name]["over_gmg"] = round(res[name]["solves_per_s"] / res["gmg_stationary"]["solves_per_s"], 3)
-    return res
+    check = {p: (a[p], b[p], f[p]) for p in (0, B - 1)}
+    return res, (check, sampled)
 
 
 def run_legs(weights, args):
     legs = {}
-    legs["paper_1023_batch64"] = leg_paper1023()
+    legs["paper_1023_batch64"], paper = leg_paper1023()
     print("[bench] leg paper problem 1023^2 x 64 done", file=sys.stderr, flush=True)
     legs["latency_31"] = leg_latency31(weights, args.levels)
     print("[bench] leg 31^2 done", file=sys.stderr, flush=True)
@@ -450,7 +456,7 @@ def run_legs(weights, args):
     print("[bench] leg training step done", file=sys.stderr, flush=True)
     legs["uneven_batch"], uneven = leg_uneven256(weights, args.levels)
     print("[bench] leg uneven batch done", file=sys.stderr, flush=True)
-    return legs, (check, uneven)
+    return legs, (check, uneven, paper)
 
 
 def main():
@@ -680,7 +686,10 @@ def main():
         # the oracle's f64 residual of every 4095^2 solution and of one problem of each size of
         # the uneven batch (CPU leg)
         from oracle import solve as osv
-        checks4, uneven_checks = legs_check
+        checks4, uneven_checks, (paper_probs, paper_sols) = legs_check
+        for name, sols in paper_sols.items():
+            legs["paper_1023_batch64"][name]["oracle_relres_sampled"] = [
+                float(osv.relres(*paper_probs[p], x, "nondiv")) for p, x in sorted(sols.items())]
         for wl, (a4, b4, f4, form4, sols) in checks4.items():
             for name, x in sols.items():
                 legs["precision_4095"][wl][name]["relres_oracle"] = float(osv.relres(a4, b4, f4, x, form4))
