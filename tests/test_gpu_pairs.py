@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import datagen
+from oracle import network as onet
 from oracle import solve as osv
 from parity_util import assert_close
 
@@ -28,6 +29,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 TRAINED = os.path.join(ROOT, "paper_2312_11093_amd", "trained", "t5_c8.npy")
 F32_TOL = 1e-5
 SPLIT2_TOL = 1e-4
+U_BF16 = 2.0 ** -8
 
 
 def say(*a):
@@ -70,12 +72,41 @@ def test_pairs_apply_matches_oracle(kind, workload, form, levels, n, B, split):
         assert_close(z[p], exp, tol, f"problem {p}", say)
 
 
+@pytest.mark.parametrize("n,B", [(63, 3), (127, 4)])
+def test_pairs_bf16_apply_within_derived_bound(n, B):
+    """bf16 state in packed pairs: per problem, |z - z_oracle| <= gamma_N |B|(|r / D|) element by
+    element, with N = 12 L + 3 bf16 roundings along the longest path and u = 2^-8 (the bound of
+    the unpacked bf16 test; |B| is the oracle's network with every weight and setup tensor
+    replaced by its absolute value)."""
+    say("pairs bf16 apply vs derived bound", n, B)
+    w = weights("trained")
+    a, b, f = datagen.make_batch("paper_re1e3", n, B, seed=5)
+    r = np.random.default_rng(3 * n + B).standard_normal((B, n, n)).astype(np.float32)
+    S = Solver(w, state="bf16", form="nondiv", levels=-1, pack_pairs=True)
+    S.setup(dev(a), b)
+    L = S.levels
+    z = S.apply(dev(r)).cpu().numpy().astype(np.float64)
+    S.close()
+    for p in range(B):
+        O = osv.Solver(w, a[p], b[p], levels=L, form="nondiv")
+        rp = r[p].astype(np.float64)
+        exp = O.correction(rp)
+        mag = onet.vcycle({k: np.abs(v) for k, v in O.P.items()}, [np.abs(x) for x in O.s], np.abs(rp / O.D))
+        N = 12 * O.L + 3
+        bound = N * U_BF16 / (1.0 - N * U_BF16) * mag
+        err = np.abs(z[p] - exp)
+        say(f"  problem {p}: max |err| / bound {float(np.max(err / np.maximum(bound, 1e-300))):.3e}")
+        assert np.all(err <= bound + 1e-6 * np.max(np.abs(exp)))
+
+
 @pytest.mark.parametrize("state", ["f32", "bf16"])
 def test_pairs_forward_matches_unpacked(state):
     """Three fixed iterations u += B((f - A u) / D) on a ragged batch (odd B, n = 127): the packed
-    library against the unpacked one with the same weights, per problem (f32: the f32 tolerance;
-    bf16: the same tolerance scaled by 2^-8 / 2^-24 would be vacuous, so bf16 is held to 1e-2,
-    the size of one bf16 rounding of the state times the few layers between roundings)."""
+    library against the unpacked one with the same weights, per problem.  The two add the same
+    products in another order on the matrix cores (the other problem's weights are exact zeros
+    in the block-diagonal convs).  f32: the f32 tolerance.  bf16: an ulp of difference in an f32
+    sum can flip the bf16 rounding of a stored value (2^-8 relative) that later layers carry;
+    1e-2 of the largest value bounds a few such flips."""
     say("pairs forward vs unpacked", state)
     n, B, K = 127, 5, 3
     w = weights("trained")
@@ -138,5 +169,8 @@ def test_pairs_reject_wider_networks_and_training():
     u = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
     with pytest.raises(M.MGCNNError) as e:
         S.forward(dev(f), u, 1, record=True)
+    assert e.value.status == M.E_STATE
+    with pytest.raises(M.MGCNNError) as e:
+        S.get_setup_tensor(1)
     assert e.value.status == M.E_STATE
     S.close()
