@@ -861,6 +861,10 @@ void launch_tanh_levels(StateType t, const float* const* x, float* const* y, con
     if (v == 1) tanh_levels_launch<ST_F32X, 4>(x, y, m, B, L, W, bias, st);
     else if (v == 2) tanh_levels_launch<ST_F32X, 16>(x, y, m, B, L, W, bias, st);
     else tanh_levels_launch<ST_F32X, 8>(x, y, m, B, L, W, bias, st);
+  } else if (t == ST_F32X2) {
+    if (v == 1) tanh_levels_launch<ST_F32X2, 4>(x, y, m, B, L, W, bias, st);
+    else if (v == 2) tanh_levels_launch<ST_F32X2, 16>(x, y, m, B, L, W, bias, st);
+    else tanh_levels_launch<ST_F32X2, 8>(x, y, m, B, L, W, bias, st);
   } else {
     if (v == 1) tanh_levels_launch<ST_F32, 4>(x, y, m, B, L, W, bias, st);
     else if (v == 2) tanh_levels_launch<ST_F32, 16>(x, y, m, B, L, W, bias, st);

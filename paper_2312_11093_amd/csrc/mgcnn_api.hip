@@ -536,7 +536,10 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
                   c->nl[l], SL, nullptr, s);
   int bl[MAX_LEVELS];
   for (int l = 0; l < L; ++l) bl[l] = SL;
-  const StateType tanh_t = c->opts.f32_split ? ST_F32X : ST_F32;
+  // the tanh layers compute in f32 intermediates: float32-level products (three-way split), or,
+  // with bf16 state (the setup tensors then rounded to 2^-8), the two-way split (about 2^-16);
+  // s_bf16 with f32 state keeps the f32 tensors rounded once
+  const StateType tanh_t = !c->opts.f32_split ? ST_F32 : (c->st() == ST_BF16 ? ST_F32X2 : ST_F32X);
   float** src[NUM_SETUP_LAYERS] = {cl, za, zb, za};
   float** dst[NUM_SETUP_LAYERS] = {za, zb, za, zb};
   for (int k = 0; k < NUM_SETUP_LAYERS; ++k)

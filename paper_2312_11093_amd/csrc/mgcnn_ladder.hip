@@ -294,7 +294,8 @@ int ladder_setup(Ladder* L, const float* const* a, const float* b_host, const in
       launch_conv16(CM_RESTRICT, ST_F32, cl[j], nullptr, W(L->off.setup_restrict), nullptr, cl[j + 1], mj, kj,
                     nullptr, st);
   }
-  const StateType tanh_t = o.f32_split ? ST_F32X : ST_F32;
+  // float32-level products, or the two-way split with bf16 state (as mgcnn_setup)
+  const StateType tanh_t = !o.f32_split ? ST_F32 : (L->xbytes() == 2 ? ST_F32X2 : ST_F32X);
   float** src[NUM_SETUP_LAYERS] = {cl, za, zb, za};
   float** dst[NUM_SETUP_LAYERS] = {za, zb, za, zb};
   for (int kk = 0; kk < NUM_SETUP_LAYERS; ++kk)
