@@ -332,9 +332,11 @@ enum { MGCNN_TILE_SMOOTHER = 0,   /* down (coarser levels) and up smoothers (Alg
        MGCNN_TILE_SETUP = 2,      /* tanh layers of the setup network (Alg. 2; f32 only) */
        MGCNN_TILE_SMOOTH_IN = 3,  /* finest down smoother with the reChannel-in conv folded in */
        MGCNN_TILE_PROLONG = 4 };  /* transposed-conv prolongation (TCNN), keyed by the fine side */
-#define MGCNN_TILE_VARIANTS 3
+#define MGCNN_TILE_VARIANTS 5
 /* Select `variant` (0 .. MGCNN_TILE_VARIANTS - 1) for operation `op`, state_dtype MGCNN_F32 or
- * MGCNN_BF16 and level side m (1..4095); MGCNN_E_ARG on a bad argument. */
+ * MGCNN_BF16 and level side m (1..4095); MGCNN_E_ARG on a bad argument or a variant the operation
+ * does not have (the same-size convs and the finest down smoother have five: 8, 4, 16, 10, 12
+ * rows; the restriction and the prolongation three). */
 int mgcnn_set_tile_variant(int op, int state_dtype, int m, int variant);
 /* The selected variant, or MGCNN_E_ARG. */
 int mgcnn_tile_variant(int op, int state_dtype, int m);

@@ -31,7 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 OPS = {"smoother": 0, "restrict": 1, "setup": 2, "smooth_in": 3, "prolong": 4}
-VARIANTS = 3
+VARIANTS = 5          # the same-size convs and the finest down smoother; restriction and prolongation 3
 STATES = {"f32": 0, "bf16": 1}
 # profiled kernel kinds -> tuned operation (level 0 of the down smoother is the separate
 # reChannel-in kernel)
@@ -44,6 +44,10 @@ DEFAULT_FILE = os.path.join(HERE, "tuning", "gfx950.json")
 def device_arch() -> str:
     import torch
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def has_variant(L, op: str, state: str, variant: int) -> bool:
+    return L.mgcnn_tile_rows(OPS[op], STATES[state], variant) > 0
 
 
 def set_all(L, op: str, state: str, variant: int):
@@ -74,8 +78,9 @@ def tune(n: int = 1023, batch: int = 64, state: str = "f32", workload: str = "bl
         m = (m - 1) // 2
     times = {}                                        # (op, side, variant) -> ms per launch
     for v in range(VARIANTS):
+        ops_v = [op for op in TUNED if has_variant(L, op, state, v)]
         for op in TUNED:
-            set_all(L, op, state, v)
+            set_all(L, op, state, v if op in ops_v else 0)
         S.forward(df, u, 1)                           # warm-up of this variant's kernels
         best = {}
         for _ in range(reps):
@@ -84,7 +89,7 @@ def tune(n: int = 1023, batch: int = 64, state: str = "f32", workload: str = "bl
             S.forward(df, u, K)
             for st in S.profile_end():
                 op = KIND_OP.get(st["kind"])
-                if op is None or (st["kind"] == "smooth_down" and st["level"] == 0):
+                if op is None or op not in ops_v or (st["kind"] == "smooth_down" and st["level"] == 0):
                     continue
                 # the prolongation into level l is keyed by that level's (fine) side
                 key = (op, sides[st["level"]])
@@ -93,7 +98,7 @@ def tune(n: int = 1023, batch: int = 64, state: str = "f32", workload: str = "bl
         for (op, side), vals in best.items():
             times[(op, side, v)] = float(np.min(vals))
         log(json.dumps({"variant": v, "rows": {op: L.mgcnn_tile_rows(OPS[op], STATES[state], v)
-                                               for op in TUNED},
+                                               for op in ops_v},
                         "ms": {f"{op}@{side}": round(times[(op, side, v)], 4)
                                for (op, side, vv) in times if vv == v}}))
     S.close()

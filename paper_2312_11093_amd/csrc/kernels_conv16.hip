@@ -763,10 +763,12 @@ __global__ __launch_bounds__(256) void smooth_in_kernel(
 // (operation, storage, level side) are set through mgcnn_set_tile_variant (process-wide); the
 // per-pixel arithmetic and its order do not depend on the tile, so every variant gives the same
 // results bit for bit.
-constexpr int SAME_ROWS[TILE_VARIANTS] = {8, 4, 16};
-constexpr int PROLONG_ROWS[TILE_VARIANTS] = {8, 4, 16};   // fine rows (2 x coarse rows)
-constexpr int RS_ROWS_F32[TILE_VARIANTS] = {4, 2, 8};
-constexpr int RS_ROWS_BF16[TILE_VARIANTS] = {8, 4, 16};
+// The same-size convs (and the finest down smoother) have five variants; the restriction and the
+// prolongation three (rows 0 = no such variant).
+constexpr int SAME_ROWS[TILE_VARIANTS] = {8, 4, 16, 10, 12};
+constexpr int PROLONG_ROWS[TILE_VARIANTS] = {8, 4, 16, 0, 0};   // fine rows (2 x coarse rows)
+constexpr int RS_ROWS_F32[TILE_VARIANTS] = {4, 2, 8, 0, 0};
+constexpr int RS_ROWS_BF16[TILE_VARIANTS] = {8, 4, 16, 0, 0};
 static int g_tile_variant[TILE_OPS][2][13] = {};     // [op][bf16 storage][log2(m + 1)]
 
 static int lg2p1(int m) {
@@ -799,6 +801,8 @@ static void same_variant(int v, const void* x, const void* s, const float* W, co
                          int m, int B, const int* active, hipStream_t st) {
   if (v == 1) same_launch<ST, MODE, SBF, 4>(x, s, W, bias, y, m, B, active, st);
   else if (v == 2) same_launch<ST, MODE, SBF, 16>(x, s, W, bias, y, m, B, active, st);
+  else if (v == 3) same_launch<ST, MODE, SBF, 10>(x, s, W, bias, y, m, B, active, st);
+  else if (v == 4) same_launch<ST, MODE, SBF, 12>(x, s, W, bias, y, m, B, active, st);
   else same_launch<ST, MODE, SBF, 8>(x, s, W, bias, y, m, B, active, st);
 }
 
@@ -860,14 +864,20 @@ void launch_tanh_levels(StateType t, const float* const* x, float* const* y, con
   if (t == ST_F32X) {
     if (v == 1) tanh_levels_launch<ST_F32X, 4>(x, y, m, B, L, W, bias, st);
     else if (v == 2) tanh_levels_launch<ST_F32X, 16>(x, y, m, B, L, W, bias, st);
+    else if (v == 3) tanh_levels_launch<ST_F32X, 10>(x, y, m, B, L, W, bias, st);
+    else if (v == 4) tanh_levels_launch<ST_F32X, 12>(x, y, m, B, L, W, bias, st);
     else tanh_levels_launch<ST_F32X, 8>(x, y, m, B, L, W, bias, st);
   } else if (t == ST_F32X2) {
     if (v == 1) tanh_levels_launch<ST_F32X2, 4>(x, y, m, B, L, W, bias, st);
     else if (v == 2) tanh_levels_launch<ST_F32X2, 16>(x, y, m, B, L, W, bias, st);
+    else if (v == 3) tanh_levels_launch<ST_F32X2, 10>(x, y, m, B, L, W, bias, st);
+    else if (v == 4) tanh_levels_launch<ST_F32X2, 12>(x, y, m, B, L, W, bias, st);
     else tanh_levels_launch<ST_F32X2, 8>(x, y, m, B, L, W, bias, st);
   } else {
     if (v == 1) tanh_levels_launch<ST_F32, 4>(x, y, m, B, L, W, bias, st);
     else if (v == 2) tanh_levels_launch<ST_F32, 16>(x, y, m, B, L, W, bias, st);
+    else if (v == 3) tanh_levels_launch<ST_F32, 10>(x, y, m, B, L, W, bias, st);
+    else if (v == 4) tanh_levels_launch<ST_F32, 12>(x, y, m, B, L, W, bias, st);
     else tanh_levels_launch<ST_F32, 8>(x, y, m, B, L, W, bias, st);
   }
 }
@@ -906,6 +916,8 @@ static void smooth_in_launch(const float* rt, const void* s, const float* Win, c
   const int v = get_tile_variant(TILE_SMOOTH_IN, ST == ST_BF16, m);
   if (v == 1) smooth_in_launch_th<ST, SBF, 4, PAIR>(rt, s, Win, W, y, m, B, active, st);
   else if (v == 2) smooth_in_launch_th<ST, SBF, 16, PAIR>(rt, s, Win, W, y, m, B, active, st);
+  else if (v == 3) smooth_in_launch_th<ST, SBF, 10, PAIR>(rt, s, Win, W, y, m, B, active, st);
+  else if (v == 4) smooth_in_launch_th<ST, SBF, 12, PAIR>(rt, s, Win, W, y, m, B, active, st);
   else smooth_in_launch_th<ST, SBF, 8, PAIR>(rt, s, Win, W, y, m, B, active, st);
 }
 

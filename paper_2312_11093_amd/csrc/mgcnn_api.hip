@@ -763,7 +763,8 @@ static bool tile_args_ok(int op, int state_dtype) {
 }
 
 int mgcnn_set_tile_variant(int op, int state_dtype, int m, int variant) {
-  if (!tile_args_ok(op, state_dtype) || variant < 0 || variant >= TILE_VARIANTS || m < 1 || m > 4095)
+  if (!tile_args_ok(op, state_dtype) || variant < 0 || variant >= TILE_VARIANTS || m < 1 || m > 4095 ||
+      tile_variant_rows(op, state_dtype == MGCNN_BF16, variant) <= 0)
     return MGCNN_E_ARG;
   if (op == TILE_SETUP && state_dtype == MGCNN_BF16) return MGCNN_E_ARG;   // the setup runs in f32
   set_tile_variant(op, state_dtype == MGCNN_BF16, m, variant);

@@ -62,7 +62,7 @@ void launch_conv16(ConvMode mode, StateType t, const void* x, const void* s, con
 // smoother with reChannel-in), TILE_PROLONG (keyed by the fine side); variant 0 = the default.
 enum TileOp : int { TILE_SMOOTHER = 0, TILE_RESTRICT = 1, TILE_SETUP = 2, TILE_SMOOTH_IN = 3,
                     TILE_PROLONG = 4, TILE_OPS = 5 };
-constexpr int TILE_VARIANTS = 3;
+constexpr int TILE_VARIANTS = 5;
 int tile_variant_rows(int op, bool bf16, int variant);
 int get_tile_variant(int op, bool bf16, int m);
 void set_tile_variant(int op, bool bf16, int m, int variant);

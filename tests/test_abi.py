@@ -81,14 +81,19 @@ def test_tile_variant_table(lib):
     reports the rows of every variant."""
     for fn in ("mgcnn_set_tile_variant", "mgcnn_tile_variant", "mgcnn_tile_rows"):
         getattr(lib, fn).restype = ctypes.c_int
-    assert lib.mgcnn_tile_rows(0, 0, 0) == 8 and lib.mgcnn_tile_rows(0, 0, 1) == 4
+    assert [lib.mgcnn_tile_rows(0, 0, v) for v in range(5)] == [8, 4, 16, 10, 12]
+    assert [lib.mgcnn_tile_rows(3, 1, v) for v in range(5)] == [8, 4, 16, 10, 12]
     assert lib.mgcnn_tile_rows(1, 0, 0) == 4 and lib.mgcnn_tile_rows(1, 1, 0) == 8
-    assert lib.mgcnn_tile_rows(0, 0, 3) == -1 and lib.mgcnn_tile_rows(5, 0, 0) == -1
+    assert lib.mgcnn_tile_rows(1, 0, 3) == -1 and lib.mgcnn_tile_rows(4, 0, 4) == -1   # three variants
+    assert lib.mgcnn_tile_rows(0, 0, 5) == -1 and lib.mgcnn_tile_rows(5, 0, 0) == -1
     assert lib.mgcnn_tile_variant(0, 0, 255) == 0
     assert lib.mgcnn_set_tile_variant(0, 0, 255, 2) == 0
     assert lib.mgcnn_tile_variant(0, 0, 255) == 2 and lib.mgcnn_tile_variant(0, 0, 511) == 0
     assert lib.mgcnn_set_tile_variant(0, 0, 255, 0) == 0
-    assert lib.mgcnn_set_tile_variant(0, 0, 255, 3) == -1        # no such variant
+    assert lib.mgcnn_set_tile_variant(0, 0, 255, 5) == -1        # no such variant
+    assert lib.mgcnn_set_tile_variant(1, 0, 255, 3) == -1        # the restriction has three
+    assert lib.mgcnn_set_tile_variant(0, 0, 255, 4) == 0 and lib.mgcnn_tile_variant(0, 0, 255) == 4
+    assert lib.mgcnn_set_tile_variant(0, 0, 255, 0) == 0
     assert lib.mgcnn_set_tile_variant(0, 2, 255, 0) == -1        # bad storage
     assert lib.mgcnn_set_tile_variant(2, 1, 255, 0) == -1        # the setup runs in f32
     assert lib.mgcnn_set_tile_variant(0, 0, 0, 0) == -1          # bad side
