@@ -129,10 +129,12 @@ def save(entries, path: str, arch: str, workload: str):
     if data.get("arch") not in (None, arch):
         data = {}
     data["arch"] = arch
-    data["how"] = ("per-launch HIP events over profiled fixed-K iterations of " + workload +
-                   "; fastest variant per (op, state, side), the default unless another is 2 % faster")
     keep = [e for e in data.get("entries", []) if e["state"] not in {x["state"] for x in entries}]
     data["entries"] = keep + entries
+    states = sorted({e["state"] for e in data["entries"]})
+    data["how"] = ("per-launch HIP events over profiled fixed-K iterations of " + workload +
+                   f" (states tuned: {', '.join(states)}); fastest variant per (op, state, side), the "
+                   "default unless another is 2 % faster")
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     with open(path, "w") as fh:
         json.dump(data, fh, indent=1)
@@ -168,7 +170,7 @@ def main():
     t0 = time.time()
     entries = tune(args.n, args.batch, args.state, args.workload)
     arch = device_arch()
-    save(entries, args.out, arch, f"{args.workload} {args.batch} x {args.n}^2 ({args.state} state)")
+    save(entries, args.out, arch, f"{args.workload} {args.batch} x {args.n}^2")
     print(json.dumps({"saved": args.out, "arch": arch, "entries": len(entries),
                       "changed": [e for e in entries if e["variant"] != 0], "sec": round(time.time() - t0, 1)}))
 
