@@ -329,8 +329,8 @@ def leg_uneven256(weights, levels, count=256):
       - the paper's problem family (white-noise coefficients, Re = 1000, v = (sin 0.5, cos 0.5),
         f = 1, non-divergence form) with the network trained by the paper's protocol, stationary
         iteration to 1e-8 on the aligned levels (one stream, one launch per operation and level
-        size, one hipGraph-captured iteration per host check), f32 and bf16 state, f64 u; per-problem
-        completion times from device timestamps;
+        size, one hipGraph-captured iteration per host check), f32 and bf16 state (bf16 also in
+        packed pairs), f64 u; per-problem completion times from device timestamps;
       - the mixture (lognormal GRF, 8 x 8 checkerboards with contrast 1e3, 20 inclusions with
         contrast 1e2; random velocities; f ~ N(0, 1); divergence form) with the benchmark's
         weights as preconditioner of FGMRES(63) with deflated restarts (k = 8), per-size buckets
@@ -345,18 +345,19 @@ def leg_uneven256(weights, levels, count=256):
         pp = list(ex.map(lambda i: datagen.make_problem("paper_re1e3", sizes[i], i, 0), range(count)))
     nodes = float(sum(p.n * p.n for p in pp))
     wt = embed_channels(np.load(PAPER_WEIGHTS, allow_pickle=False))
-    for state in ("f32", "bf16"):
+    for state, pack in (("f32", False), ("bf16", False), ("bf16", True)):
         G = GroupSolver(wt, state=state, u="f64", method="stationary", check_every=1, levels=-1,
-                        use_graph=True, form="nondiv")
+                        use_graph=True, form="nondiv", pack_pairs=pack)
         out, u = _uneven_run(G, pp, 1e-8, 400)
         G.close()
         out["workload"] = f"paper_re1e3 family, {nodes / 1e6:.1f} M nodes, stationary, tol 1e-8"
-        res[f"paper_family_{state}_state"] = out
-        if state == "f32":
-            checks["paper_family_f32_state"] = (pp, u, "nondiv")
+        key = f"paper_family_{state}_" + ("pairs" if pack else "state")
+        res[key] = out
+        if state == "f32" or pack:
+            checks[key] = (pp, u, "nondiv")
         else:
             del u
-        print(f"[bench]   uneven paper family {state} done", file=sys.stderr, flush=True)
+        print(f"[bench]   uneven paper family {state}{' pairs' if pack else ''} done", file=sys.stderr, flush=True)
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
         pm = list(ex.map(lambda i: datagen.make_problem("mixture_var", sizes[i], i, 0), range(count)))
     G = GroupSolver(weights, state="f32", u="f64", method="fgmres", restart=63, gs_passes=1, deflate=8,

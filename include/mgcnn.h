@@ -165,7 +165,9 @@ typedef struct {
                        the summation order) at half the state bytes per problem.  An odd batch
                        leaves the second half of the last pair empty.  Training entry points and
                        mgcnn_get_setup_tensor return MGCNN_E_STATE; mgcnn_create rejects it with
-                       FGMRES, PCG, GMG or s_bf16, mgcnn_group_create rejects it (MGCNN_E_ARG) */
+                       FGMRES, PCG, GMG or s_bf16 (MGCNN_E_ARG).  Groups take it too: on aligned
+                       levels every size group is padded to an even count with phantom problems
+                       (zero right-hand side), so that a pair never mixes two sizes */
 } mgcnn_opts;
 
 /* Default options: 16 channels, f32 state (split-bf16 matrix arithmetic), f64 u, graphs off,

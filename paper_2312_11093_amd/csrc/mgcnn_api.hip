@@ -503,13 +503,14 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
   // restricted coefficient tensors exist): features and reChannel on the finest level, the
   // restriction chain c_1 -> c_2 -> ... -> c_L, then each of the four tanh layers as one launch
   // over all levels.  With f32 storage the level tensors hold the intermediates (c_l in xin_l,
-  // the layers ping-pong between xdn_l and s_l and end in s_l); bf16 storage uses f32 level
-  // pyramids kept in the context for the next setup of this size.
+  // the layers ping-pong between xdn_l and s_l and end in s_l); bf16 storage uses two f32 level
+  // pyramids kept in the context for the next setup of this size: the first holds c_l, then the
+  // outputs of the second and fourth layers, the second the outputs of the first and third.
   const int L = c->L, SL = c->slots;                   // SL: state slots (packed pairs: (B + 1) / 2)
   const bool f32_store = c->state_bytes() == 4 && !c->s16();
   size_t pyr = 0;                                      // floats of one f32 level pyramid
   for (int l = 0; l < L; ++l) pyr += (size_t)c->nl[l] * c->nl[l] * SL * C;
-  if (!c->setup_tmp && (r = alloc(c, &c->setup_tmp, nn * 16 + (f32_store ? 0 : 3 * pyr * 4)))) return r;
+  if (!c->setup_tmp && (r = alloc(c, &c->setup_tmp, nn * 16 + (f32_store ? 0 : 2 * pyr * 4)))) return r;
   float* F = (float*)c->setup_tmp;
   float *cl[MAX_LEVELS], *za[MAX_LEVELS], *zb[MAX_LEVELS];
   {
@@ -523,7 +524,7 @@ int mgcnn_setup(mgcnn_ctx* c, const float* a, const float* b_host, int n, int B)
       } else {
         cl[l] = p;
         za[l] = p + pyr;
-        zb[l] = p + 2 * pyr;
+        zb[l] = p;
         p += cnt;
       }
     }

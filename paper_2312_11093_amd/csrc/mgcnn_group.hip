@@ -89,7 +89,6 @@ int mgcnn_group_create(mgcnn_group** group, const mgcnn_opts* opts, const float*
   *group = nullptr;
   mgcnn_opts o;
   if (opts) o = *opts; else mgcnn_default_opts(&o);
-  if (o.pack_pairs) return MGCNN_E_ARG;       // groups keep one state slot per problem
   // validate the options once with a throw-away context
   mgcnn_ctx* probe = nullptr;
   int r = mgcnn_create(&probe, &o, weights_host, hip_stream);

@@ -2,6 +2,8 @@
 // Not part of the public interface (see include/mgcnn.h).
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
@@ -26,6 +28,11 @@ struct WeightOffsets {
   size_t solve_in, smooth_down, smooth_up, restrict_, prolong, solve_out, total;
 };
 WeightOffsets weight_offsets();
+namespace api {
+// Packed pairs: the weights of a network with at most 8 hidden channels (16-channel layout,
+// channels 8..15 unused) as block-diagonal 16-channel weights; false if channels 8..15 are used.
+bool pack_pair_weights(const WeightOffsets& off, const float* w, std::vector<float>& out);
+}  // namespace api
 
 // bf16 storage: raw 16-bit pattern.
 typedef uint16_t bf16_t;

@@ -10,6 +10,11 @@
 // reChannel-in down smoother, reChannel-out update, stopping test) are one launch per distinct
 // problem size over the problems whose finest grid it is.  One stream, no host threads; blocks
 // of iterations are captured in a hipGraph.
+//
+// Packed pairs (opts.pack_pairs, networks of at most 8 hidden channels): every size group is
+// padded to an even count with phantom problems (zero right-hand side, unit coefficient, never
+// copied back), so that sorted positions 2v and 2v + 1 always have the same finest size and share
+// state slot v on every level they have.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,8 +32,10 @@ struct Ladder {
   WeightOffsets off{};
   float* d_w = nullptr;
   hipStream_t stream = nullptr;      // private, default priority
-  int count = 0;                     // problems
-  std::vector<int> order;            // sorted position -> caller index (n descending, stable)
+  int count = 0;                     // sorted positions (problems, plus phantoms with packed pairs)
+  int real = 0;                      // the caller's problems
+  bool pairs = false;                // packed pairs: two sorted positions per state slot
+  std::vector<int> order;            // sorted position -> caller index (n descending, stable; -1 = phantom)
   std::vector<int> pos;              // caller index -> sorted position
   std::vector<int> nq;               // side of the problem at each sorted position
   int J = 0;                         // level sizes
@@ -52,9 +59,12 @@ struct Ladder {
   double g_tol = -1.0;
   int g_maxit = -1, g_chunk = 0;
   std::vector<double> completion_s;  // per caller index, seconds from the start of the last solve
+  float* tmp = nullptr;              // setup temporaries, kept across setups
+  size_t tmp_bytes = 0;
   std::string err;
 
   int c(int j) const { return k[j] - lo[j]; }
+  int sl(int q) const { return pairs ? q / 2 : q; }   // state slots of q sorted positions
   size_t sbytes() const;
   size_t xbytes() const;
 };

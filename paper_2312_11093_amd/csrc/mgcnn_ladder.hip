@@ -70,6 +70,7 @@ void free_arrays(Ladder* L) {
   L->clock = nullptr;
   L->ready = false;
   L->count = 0;
+  L->real = 0;
 }
 
 StateType state_of(const mgcnn_opts& o) {
@@ -100,31 +101,37 @@ void step(Ladder* L, double tol, int maxit) {
     launch_finalize(L->partial[j], residual_tiles(L->m[j]), L->nf2 + lo, tol, maxit, L->active + lo,
                     L->status + lo, L->iters + lo, L->relres + lo, cj, st, L->clock + lo);
   }
+  // state tensors are indexed by slot (sorted position, or position / 2 with packed pairs)
   for (int j = 0; j < L->J; ++j) {
     const int cj = L->c(j), lo = L->lo[j], mj = L->m[j];
     if (cj > 0)   // finest grid of the problems [lo, k_j): reChannel-in folded into the smoother
-      launch_smooth_in(t_in, L->rt[j], at(L->s, sbb, j, lo), W(L->off.solve_in), W(L->off.smooth_down),
-                       at(L->xdn, xb, j, lo), mj, cj, nullptr, st, sb);
+      launch_smooth_in(t_in, L->rt[j], at(L->s, sbb, j, L->sl(lo)), W(L->off.solve_in), W(L->off.smooth_down),
+                       at(L->xdn, xb, j, L->sl(lo)), mj, L->sl(cj), nullptr, st, sb, L->pairs);
     if (lo > 0)   // coarser level of the larger problems [0, lo)
-      launch_conv16(CM_SMOOTH, t, L->xin[j], L->s[j], W(L->off.smooth_down), nullptr, L->xdn[j], mj, lo,
+      launch_conv16(CM_SMOOTH, t, L->xin[j], L->s[j], W(L->off.smooth_down), nullptr, L->xdn[j], mj, L->sl(lo),
                     nullptr, st, sb);
     if (j < L->J - 1)
       launch_conv16(CM_RESTRICT, t, L->xdn[j], nullptr, W(L->off.restrict_), nullptr, L->xin[j + 1], mj,
-                    L->k[j], nullptr, st);
+                    L->sl(L->k[j]), nullptr, st);
   }
   const int jc = L->J - 1;
   launch_conv16(up_mode, t, L->xdn[jc], L->s[jc], W(L->off.smooth_up), nullptr, L->xin[jc], L->m[jc],
-                L->k[jc], nullptr, st, sb);
+                L->sl(L->k[jc]), nullptr, st, sb);
   for (int j = L->J - 2; j >= 0; --j) {
-    launch_prolong_add(t, L->xin[j + 1], W(L->off.prolong), L->xdn[j], L->m[j + 1], L->k[j], nullptr, st);
+    launch_prolong_add(t, L->xin[j + 1], W(L->off.prolong), L->xdn[j], L->m[j + 1], L->sl(L->k[j]), nullptr,
+                       st);
     launch_conv16(up_mode, t, L->xdn[j], L->s[j], W(L->off.smooth_up), nullptr, L->xin[j], L->m[j],
-                  L->k[j], nullptr, st, sb);
+                  L->sl(L->k[j]), nullptr, st, sb);
   }
   for (int j = 0; j < L->J; ++j) {
     const int cj = L->c(j), lo = L->lo[j];
     if (cj == 0) continue;
-    launch_out_update(t, at(L->xin, xb, j, lo), W(L->off.solve_out), L->u[j], u64, L->m[j], cj, nullptr,
-                      st, true, L->active + lo);
+    if (L->pairs)
+      launch_out_update_pairs(t, at(L->xin, xb, j, lo / 2), W(L->off.solve_out), L->u[j], u64, L->m[j], cj / 2,
+                              cj, nullptr, st, true, L->active + lo);
+    else
+      launch_out_update(t, at(L->xin, xb, j, lo), W(L->off.solve_out), L->u[j], u64, L->m[j], cj, nullptr,
+                        st, true, L->active + lo);
   }
 }
 
@@ -137,6 +144,13 @@ bool ladder_supported(const mgcnn_opts& o) {
 int ladder_create(Ladder* L, const mgcnn_opts& o, const float* weights_host) {
   L->opts = o;
   L->off = weight_offsets();
+  L->pairs = o.pack_pairs != 0;
+  std::vector<float> packed;
+  if (L->pairs && weights_host) {
+    if (!api::pack_pair_weights(L->off, weights_host, packed))
+      return lfail(L, MGCNN_E_ARG, "group: pack_pairs needs a network of at most 8 hidden channels");
+    weights_host = packed.data();
+  }
   if (int r = lalloc(L, (void**)&L->d_w, L->off.total * 4)) return r;
   if (weights_host)
     LTRY(hipMemcpy(L->d_w, weights_host, L->off.total * 4, hipMemcpyHostToDevice));
@@ -152,6 +166,9 @@ int ladder_create(Ladder* L, const mgcnn_opts& o, const float* weights_host) {
 void ladder_free(Ladder* L) {
   if (L->stream) (void)hipStreamSynchronize(L->stream);
   free_arrays(L);
+  if (L->tmp) (void)hipFree(L->tmp);
+  L->tmp = nullptr;
+  L->tmp_bytes = 0;
   if (L->d_w) (void)hipFree(L->d_w);
   L->d_w = nullptr;
   if (L->stream) (void)hipStreamDestroy(L->stream);
@@ -183,18 +200,37 @@ int ladder_setup(Ladder* L, const float* const* a, const float* b_host, const in
   for (int i = 0; i < count; ++i)
     if (n_host[i] < coarsest)
       return lfail(L, MGCNN_E_ARG, "group_setup: levels out of range for a problem size");
-  free_arrays(L);
   if (int r = wait_on(L, user)) return r;
-  L->count = count;
-  L->order.resize(count);
-  std::iota(L->order.begin(), L->order.end(), 0);
-  std::stable_sort(L->order.begin(), L->order.end(), [&](int x, int y) { return n_host[x] > n_host[y]; });
-  L->pos.assign(count, 0);
-  L->nq.assign(count, 0);
-  for (int q = 0; q < count; ++q) {
-    L->pos[L->order[q]] = q;
-    L->nq[q] = n_host[L->order[q]];
+  std::vector<int> sorted(count);
+  std::iota(sorted.begin(), sorted.end(), 0);
+  std::stable_sort(sorted.begin(), sorted.end(), [&](int x, int y) { return n_host[x] > n_host[y]; });
+  // sorted positions; with packed pairs a phantom (-1) closes every size group of odd count
+  std::vector<int> order, nq;
+  for (int i = 0; i < count; ++i) {
+    const int n = n_host[sorted[i]];
+    order.push_back(sorted[i]);
+    nq.push_back(n);
+    const bool group_end = i + 1 == count || n_host[sorted[i + 1]] != n;
+    if (L->pairs && group_end && order.size() % 2 == 1) {
+      order.push_back(-1);
+      nq.push_back(n);
+    }
   }
+  // the device arrays depend only on the sorted sizes: a setup with the same sizes keeps them
+  // (freeing and reallocating tens of GB at every setup costs more than the setup itself)
+  const bool same_layout = L->ready && !L->s.empty() && nq == L->nq;   // the last setup completed
+  if (!same_layout) free_arrays(L);
+  drop_graph(L);
+  L->ready = false;
+  const int real = count;
+  L->order = order;
+  L->nq = nq;
+  L->real = real;
+  count = (int)L->order.size();
+  L->count = count;
+  L->pos.assign(L->real, 0);
+  for (int q = 0; q < count; ++q)
+    if (L->order[q] >= 0) L->pos[L->order[q]] = q;
   L->J = log2p1(L->nq[0]) - log2p1(coarsest) + 1;
   L->m.assign(L->J, 0); L->k.assign(L->J, 0); L->lo.assign(L->J, 0);
   for (int j = 0, mj = L->nq[0]; j < L->J; ++j, mj = (mj - 1) / 2) {
@@ -208,38 +244,41 @@ int ladder_setup(Ladder* L, const float* const* a, const float* b_host, const in
     L->lo[j] = lj;
   }
   const size_t xb = L->xbytes(), sbb = L->sbytes(), ub = o.u_dtype == MGCNN_U_F64 ? 8 : 4;
-  L->s.assign(L->J, nullptr); L->xin.assign(L->J, nullptr); L->xdn.assign(L->J, nullptr);
-  L->u.assign(L->J, nullptr); L->a.assign(L->J, nullptr); L->f.assign(L->J, nullptr);
-  L->rt.assign(L->J, nullptr); L->partial.assign(L->J, nullptr);
   int r;
-  size_t max_fine = 0, max_level = 0;
-  for (int j = 0; j < L->J; ++j) {
-    const size_t mm = (size_t)L->m[j] * L->m[j];
-    const size_t cnt = mm * L->k[j] * C;
-    max_level = std::max(max_level, cnt);
-    if ((r = lalloc(L, &L->s[j], cnt * sbb)) || (r = lalloc(L, &L->xin[j], cnt * xb)) ||
-        (r = lalloc(L, &L->xdn[j], cnt * xb)))
-      return r;
-    const int cj = L->c(j);
-    if (cj == 0) continue;
-    max_fine = std::max(max_fine, mm * cj);
-    if ((r = lalloc(L, (void**)&L->a[j], mm * cj * 4)) || (r = lalloc(L, (void**)&L->f[j], mm * cj * 4)) ||
-        (r = lalloc(L, (void**)&L->rt[j], mm * cj * 4)) || (r = lalloc(L, &L->u[j], mm * cj * ub)) ||
-        (r = lalloc(L, (void**)&L->partial[j], (size_t)residual_tiles(L->m[j]) * cj * 8)))
+  size_t max_fine = 0;
+  for (int j = 0; j < L->J; ++j)
+    if (L->c(j) > 0) max_fine = std::max(max_fine, (size_t)L->m[j] * L->m[j] * L->c(j));
+  if (!same_layout) {
+    L->s.assign(L->J, nullptr); L->xin.assign(L->J, nullptr); L->xdn.assign(L->J, nullptr);
+    L->u.assign(L->J, nullptr); L->a.assign(L->J, nullptr); L->f.assign(L->J, nullptr);
+    L->rt.assign(L->J, nullptr); L->partial.assign(L->J, nullptr);
+    for (int j = 0; j < L->J; ++j) {
+      const size_t mm = (size_t)L->m[j] * L->m[j];
+      const size_t cnt = mm * L->sl(L->k[j]) * C;
+      if ((r = lalloc(L, &L->s[j], cnt * sbb)) || (r = lalloc(L, &L->xin[j], cnt * xb)) ||
+          (r = lalloc(L, &L->xdn[j], cnt * xb)))
+        return r;
+      const int cj = L->c(j);
+      if (cj == 0) continue;
+      if ((r = lalloc(L, (void**)&L->a[j], mm * cj * 4)) || (r = lalloc(L, (void**)&L->f[j], mm * cj * 4)) ||
+          (r = lalloc(L, (void**)&L->rt[j], mm * cj * 4)) || (r = lalloc(L, &L->u[j], mm * cj * ub)) ||
+          (r = lalloc(L, (void**)&L->partial[j], (size_t)residual_tiles(L->m[j]) * cj * 8)))
+        return r;
+    }
+    if ((r = lalloc(L, (void**)&L->d_b, (size_t)count * 8)) || (r = lalloc(L, (void**)&L->nf2, (size_t)count * 8)) ||
+        (r = lalloc(L, (void**)&L->relres, (size_t)count * 8)) ||
+        (r = lalloc(L, (void**)&L->active, (size_t)count * 4)) ||
+        (r = lalloc(L, (void**)&L->status, (size_t)count * 4)) ||
+        (r = lalloc(L, (void**)&L->iters, (size_t)count * 4)) ||
+        (r = lalloc(L, (void**)&L->clock, (size_t)(count + 1) * 8)))
       return r;
   }
-  if ((r = lalloc(L, (void**)&L->d_b, (size_t)count * 8)) || (r = lalloc(L, (void**)&L->nf2, (size_t)count * 8)) ||
-      (r = lalloc(L, (void**)&L->relres, (size_t)count * 8)) ||
-      (r = lalloc(L, (void**)&L->active, (size_t)count * 4)) ||
-      (r = lalloc(L, (void**)&L->status, (size_t)count * 4)) ||
-      (r = lalloc(L, (void**)&L->iters, (size_t)count * 4)) ||
-      (r = lalloc(L, (void**)&L->clock, (size_t)(count + 1) * 8)))
-    return r;
   hipStream_t st = L->stream;
   // coefficients and velocities in sorted order
-  std::vector<float> bs((size_t)2 * count);
+  std::vector<float> bs((size_t)2 * count, 0.f);     // phantoms: b = 0
   for (int q = 0; q < count; ++q) {
     const int i = L->order[q];
+    if (i < 0) continue;
     bs[2 * q] = b_host[2 * i];
     bs[2 * q + 1] = b_host[2 * i + 1];
   }
@@ -248,8 +287,11 @@ int ladder_setup(Ladder* L, const float* const* a, const float* b_host, const in
     const int n = L->nq[q];
     int j = 0;
     while (L->m[j] != n) ++j;
-    LTRY(hipMemcpyAsync(L->a[j] + (size_t)(q - L->lo[j]) * n * n, a[L->order[q]], (size_t)n * n * 4,
-                        hipMemcpyDeviceToDevice, st));
+    float* dst = L->a[j] + (size_t)(q - L->lo[j]) * n * n;
+    if (L->order[q] >= 0)
+      LTRY(hipMemcpyAsync(dst, a[L->order[q]], (size_t)n * n * 4, hipMemcpyDeviceToDevice, st));
+    else   // phantom: a = 1 everywhere (bit pattern of 1.0f)
+      LTRY(hipMemsetD32Async((hipDeviceptr_t)dst, (int)0x3f800000, (size_t)n * n, st));
   }
   // setup network (Alg. 2) over the aligned levels: reChannel of the features at each problem's
   // finest size, the restriction chain of the coefficient tensors down the sizes, then each tanh
@@ -258,14 +300,19 @@ int ladder_setup(Ladder* L, const float* const* a, const float* b_host, const in
   // xdn_j and s_j and end in s_j); bf16 storage uses f32 level pyramids.
   const bool f32_store = L->xbytes() == 4 && sbb == 4;
   size_t pyr = 0;
-  for (int j = 0; j < L->J; ++j) pyr += (size_t)L->m[j] * L->m[j] * L->k[j] * C;
-  float *F = nullptr, *tmp = nullptr;
-  auto cleanup = [&]() {
-    for (float* p : {F, tmp}) if (p) (void)hipFree(p);
-  };
-  if ((r = lalloc(L, (void**)&F, max_fine * 4 * 4))) { cleanup(); return r; }
-  if (!f32_store && (r = lalloc(L, (void**)&tmp, 3 * pyr * 4))) { cleanup(); return r; }
-  (void)max_level;
+  for (int j = 0; j < L->J; ++j) pyr += (size_t)L->m[j] * L->m[j] * L->sl(L->k[j]) * C;
+  // temporaries (features of the largest finest group; with bf16 storage two f32 level pyramids)
+  // are kept for the next setup and grown when a setup needs more
+  const size_t need = max_fine * 4 * 4 + (f32_store ? 0 : 2 * pyr * 4);
+  if (L->tmp_bytes < need) {
+    if (L->tmp) (void)hipFree(L->tmp);
+    L->tmp = nullptr;
+    L->tmp_bytes = 0;
+    if ((r = lalloc(L, (void**)&L->tmp, need))) return r;
+    L->tmp_bytes = need;
+  }
+  float* F = L->tmp;
+  float* tmp = L->tmp + max_fine * 4;
   auto W = [&](size_t off) { return (const float*)(L->d_w + off); };
   float *cl[MAX_LEVELS], *za[MAX_LEVELS], *zb[MAX_LEVELS];
   {
@@ -276,10 +323,10 @@ int ladder_setup(Ladder* L, const float* const* a, const float* b_host, const in
         za[j] = (float*)L->xdn[j];
         zb[j] = (float*)L->s[j];
       } else {
-        cl[j] = p;
+        cl[j] = p;            // c_j, then the second and fourth layers' output
         za[j] = p + pyr;
-        zb[j] = p + 2 * pyr;
-        p += (size_t)L->m[j] * L->m[j] * L->k[j] * C;
+        zb[j] = p;
+        p += (size_t)L->m[j] * L->m[j] * L->sl(L->k[j]) * C;
       }
     }
   }
@@ -288,25 +335,27 @@ int ladder_setup(Ladder* L, const float* const* a, const float* b_host, const in
     const size_t mm = (size_t)mj * mj;
     if (cj > 0) {
       launch_features(L->a[j], L->d_b + 2 * lo, F, mj, cj, o.op_form, st);
-      launch_conv_in(4, F, W(L->off.setup_in), cl[j] + mm * lo * C, ST_F32, mj, cj, nullptr, st);
+      if (L->pairs) launch_conv_in_pairs(F, W(L->off.setup_in), cl[j] + mm * (lo / 2) * C, mj, cj, st);
+      else launch_conv_in(4, F, W(L->off.setup_in), cl[j] + mm * lo * C, ST_F32, mj, cj, nullptr, st);
     }
     if (j + 1 < L->J)
-      launch_conv16(CM_RESTRICT, ST_F32, cl[j], nullptr, W(L->off.setup_restrict), nullptr, cl[j + 1], mj, kj,
-                    nullptr, st);
+      launch_conv16(CM_RESTRICT, ST_F32, cl[j], nullptr, W(L->off.setup_restrict), nullptr, cl[j + 1], mj,
+                    L->sl(kj), nullptr, st);
   }
+  std::vector<int> slots_per_level(L->J);
+  for (int j = 0; j < L->J; ++j) slots_per_level[j] = L->sl(L->k[j]);
   // float32-level products, or the two-way split with bf16 state (as mgcnn_setup)
   const StateType tanh_t = !o.f32_split ? ST_F32 : (L->xbytes() == 2 ? ST_F32X2 : ST_F32X);
   float** src[NUM_SETUP_LAYERS] = {cl, za, zb, za};
   float** dst[NUM_SETUP_LAYERS] = {za, zb, za, zb};
   for (int kk = 0; kk < NUM_SETUP_LAYERS; ++kk)
-    launch_tanh_levels(tanh_t, src[kk], dst[kk], L->m.data(), L->k.data(), L->J, W(L->off.res_w[kk]),
+    launch_tanh_levels(tanh_t, src[kk], dst[kk], L->m.data(), slots_per_level.data(), L->J, W(L->off.res_w[kk]),
                        W(L->off.res_b[kk]), st);
   if (!f32_store)
     for (int j = 0; j < L->J; ++j)
-      launch_f32_to_bf16(zb[j], (bf16_t*)L->s[j], (size_t)L->m[j] * L->m[j] * L->k[j] * C, st);
+      launch_f32_to_bf16(zb[j], (bf16_t*)L->s[j], (size_t)L->m[j] * L->m[j] * L->sl(L->k[j]) * C, st);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  cleanup();
   if (e != hipSuccess) return lfail(L, MGCNN_E_HIP, std::string("group_setup: ") + hipGetErrorString(e));
   L->ready = true;
   return MGCNN_OK;
@@ -359,6 +408,10 @@ int ladder_solve(Ladder* L, const float* const* f, void* const* u, double tol, i
     const size_t off = slot(q, &j);
     const size_t nn = (size_t)L->m[j] * L->m[j];
     const int i = L->order[q];
+    if (i < 0) {   // phantom: f = 0 (so u = 0 and the problem is done before the first step)
+      LTRY(hipMemsetAsync(L->f[j] + off, 0, nn * 4, st));
+      continue;
+    }
     LTRY(hipMemcpyAsync(L->f[j] + off, f[i], nn * 4, hipMemcpyDeviceToDevice, st));
     LTRY(hipMemcpyAsync((char*)L->u[j] + off * ub, u[i], nn * ub, hipMemcpyDeviceToDevice, st));
   }
@@ -399,13 +452,15 @@ int ladder_solve(Ladder* L, const float* const* f, void* const* u, double tol, i
     int j;
     const size_t off = slot(q, &j);
     const size_t nn = (size_t)L->m[j] * L->m[j];
+    if (L->order[q] < 0) continue;
     LTRY(hipMemcpyAsync(u[L->order[q]], (const char*)L->u[j] + off * ub, nn * ub, hipMemcpyDeviceToDevice, st));
   }
   LTRY(hipStreamSynchronize(st));
-  L->completion_s.assign(count, 0.0);
+  L->completion_s.assign(L->real, 0.0);
   bool diverged = false, notconv = false;
   for (int q = 0; q < count; ++q) {
     const int i = L->order[q];
+    if (i < 0) continue;
     if (iters_host) iters_host[i] = iv[q];
     if (relres_host) relres_host[i] = rv[q];
     if (status_host) status_host[i] = sv[q];

@@ -382,7 +382,7 @@ class GroupSolver:
                  inner_steps: int = 1, gs_passes: int = 2, stream=None, precond: str = "network",
                  gmg_levels: int = 0, gmg_sweeps: int = 3, gmg_omega: float = 0.67,
                  form: str = "div", deflate: int = 0, levels: int = 0, up_post: bool = False,
-                 use_graph: bool = False):
+                 use_graph: bool = False, pack_pairs: bool = False):
         import torch
         self._L = lib()
         o = mgcnn_opts()
@@ -402,6 +402,7 @@ class GroupSolver:
         o.levels = int(levels)
         o.up_post = int(bool(up_post))
         o.use_graph = int(bool(use_graph))
+        o.pack_pairs = int(bool(pack_pairs))
         self.u_dtype = torch.float64 if o.u_dtype == U_F64 else torch.float32
         wp = _weights_ptr(self, weights, self._L.mgcnn_num_weights(16))
         self._stream = stream if stream is not None else torch.cuda.current_stream()

@@ -133,7 +133,7 @@ def test_default_options_and_option_checks(lib):
 def test_create_checks_the_pack_pairs_options(lib):
     """Packed pairs run the stationary method with the network preconditioner and f32 or bf16
     setup tensors in the state's type: FGMRES, PCG, GMG and s_bf16 are rejected before any
-    device call; a group with packed pairs is rejected too."""
+    device call, for a context and for a group."""
     from paper_2312_11093_amd import mgcnn
     h = ctypes.c_void_p()
     for changes in ({"method": 1, "restart": 30}, {"method": 2, "up_post": 1}, {"precond": 1}, {"s_bf16": 1}):
@@ -143,11 +143,14 @@ def test_create_checks_the_pack_pairs_options(lib):
         for k, v in changes.items():
             setattr(bad, k, v)
         assert lib.mgcnn_create(ctypes.byref(h), ctypes.byref(bad), None, None) == -1, changes
-    o = mgcnn.mgcnn_opts()
-    lib.mgcnn_default_opts(ctypes.byref(o))
-    o.pack_pairs = 1
     g = ctypes.c_void_p()
-    assert lib.mgcnn_group_create(ctypes.byref(g), ctypes.byref(o), None, None) == -1
+    for changes in ({"method": 1, "restart": 30}, {"precond": 1}, {"s_bf16": 1}):
+        bad = mgcnn.mgcnn_opts()
+        lib.mgcnn_default_opts(ctypes.byref(bad))
+        bad.pack_pairs = 1
+        for k, v in changes.items():
+            setattr(bad, k, v)
+        assert lib.mgcnn_group_create(ctypes.byref(g), ctypes.byref(bad), None, None) == -1, changes
 
 
 def test_create_rejects_deflation_beyond_half_the_restart(lib):

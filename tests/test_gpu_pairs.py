@@ -174,3 +174,43 @@ def test_pairs_reject_wider_networks_and_training():
         S.get_setup_tensor(1)
     assert e.value.status == M.E_STATE
     S.close()
+
+
+@pytest.mark.parametrize("state", ["f32", "bf16"])
+def test_pairs_group_on_aligned_levels(state):
+    """Uneven sizes in one group call with packed pairs: every size group of odd count gets a
+    phantom partner, so that pairs never mix sizes.  Nine paper problems (three of 127^2, one
+    each of 15^2 and 7^2, one with f = 0) solved to 1e-8 with the trained network: the oracle's
+    residual of every returned solution is <= tol, u = 0 for the zero right-hand side, the
+    iteration counts are those of the unpacked group within one, and the device completion times
+    are positive for the problems that iterated."""
+    from paper_2312_11093_amd import GroupSolver
+    sizes = [31, 127, 15, 63, 127, 7, 31, 63, 127]
+    say("pairs group", state, sizes)
+    ps = [datagen.make_problem("paper_re1e3", n, i, 8) for i, n in enumerate(sizes)]
+    ps[4].f[:] = 0.0
+    w = weights("trained")
+    a = [dev(p.a) for p in ps]
+    f = [dev(p.f) for p in ps]
+    b = np.stack([p.b for p in ps])
+    its = {}
+    for pack in (False, True):
+        G = GroupSolver(w, state=state, u="f64", method="stationary", check_every=2, levels=-1, form="nondiv",
+                        use_graph=True, pack_pairs=pack)
+        assert G.aligned
+        G.setup(a, b)
+        u = [torch.zeros((p.n, p.n), dtype=torch.float64, device="cuda") for p in ps]
+        st, it, rr, stat = G.solve(f, u, 1e-8, 60)
+        ct = G.completion_times()
+        G.close()
+        say("  pack" if pack else "  unpacked", "iters", list(map(int, it)))
+        assert st == M.OK and (stat == 0).all()
+        for i, p in enumerate(ps):
+            x = u[i].cpu().numpy()
+            if i == 4:
+                assert not x.any() and int(it[i]) == 0 and ct[i] == 0.0
+                continue
+            assert osv.relres(p.a, p.b, p.f, x, "nondiv") <= 1e-8 * (1 + 1e-6), i
+            assert ct[i] > 0.0
+        its[pack] = np.asarray(it)
+    assert (np.abs(its[True] - its[False]) <= 1).all()
