@@ -111,14 +111,22 @@ def test_aligned_levels_match_individual_solves(state, levels, graph):
     G.close()
 
 
-def test_aligned_levels_solve_twice_and_resetup():
+@pytest.mark.parametrize("state,pack", [("f32", False), ("bf16", True)])
+def test_aligned_levels_solve_twice_and_resetup(state, pack):
     """Two solves on one setup (the captured graph is replayed with eager work between) give the
-    same result; a new setup with other sizes gives the individual results again."""
-    say("aligned: repeat and re-setup")
-    w = vcycle_weights()
-    G = GroupSolver(w, state="f32", u="f64", method="stationary", check_every=4, use_graph=True)
-    for sizes in ([63, 15, 31, 63], [127, 7, 255]):
-        ps = problems(sizes, seed=9)
+    same result; new setups give the individual results again: first with other coefficients and
+    the same sizes in another caller order (the device arrays of the previous setup are kept),
+    then with other sizes (they are reallocated).  bf16 state in packed pairs takes the setup's
+    f32 pyramids and the phantom partners of odd size groups."""
+    say("aligned: repeat and re-setup", state, "pairs" if pack else "")
+    w = vcycle_weights() if not pack else None
+    if pack:
+        from paper_2312_11093_amd.weights import embed_channels
+        w = embed_channels(datagen.xavier_weights(8, 4))
+    G = GroupSolver(w, state=state, u="f64", method="stationary", check_every=4, use_graph=True,
+                    pack_pairs=pack)
+    for sizes, seed in (([63, 15, 31, 63], 9), ([15, 63, 31, 63], 10), ([127, 7, 255], 9)):
+        ps = problems(sizes, seed=seed)
         a = [dev(p.a) for p in ps]
         f = [dev(p.f) for p in ps]
         b = np.stack([p.b for p in ps])
@@ -133,12 +141,12 @@ def test_aligned_levels_solve_twice_and_resetup():
         assert (outs[0][0] == outs[1][0]).all() and (outs[0][1] == outs[1][1]).all()
         assert all(torch.equal(x, y) for x, y in zip(outs[0][2], outs[1][2]))
         for i, p in enumerate(ps):
-            S = Solver(w, state="f32", u="f64", method="stationary", check_every=4)
+            S = Solver(w, state=state, u="f64", method="stationary", check_every=4, pack_pairs=pack)
             S.setup(a[i].view(1, p.n, p.n), b[i:i + 1])
             ui = torch.zeros((1, p.n, p.n), dtype=torch.float64, device="cuda")
             _, it1, _, _ = S.solve(f[i].view(1, p.n, p.n), ui, 1e-8, 12)
             S.close()
-            assert int(it1[0]) == int(outs[0][0][i]) and torch.equal(ui[0], outs[0][2][i])
+            assert int(it1[0]) == int(outs[0][0][i]) and torch.equal(ui[0], outs[0][2][i]), (sizes, i)
     G.close()
 
 
