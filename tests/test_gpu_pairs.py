@@ -214,3 +214,51 @@ def test_pairs_group_on_aligned_levels(state):
             assert ct[i] > 0.0
         its[pack] = np.asarray(it)
     assert (np.abs(its[True] - its[False]) <= 1).all()
+
+
+def test_pairs_full_size_paper_batch_sampled():
+    """The benchmark's packed-pair launch at its real size: 64 paper problems at 1023^2 (32 state
+    slots), f32 state with the two-way split in the finest down smoother, one application of the
+    trained network to a random residual.  Both halves of the first and the last slot (problems
+    0, 1, 62, 63) against the oracle element by element (the two-way split's tolerance)."""
+    n, B = 1023, 64
+    say("pairs full size", n, B)
+    w = weights("trained")
+    a, b, _ = datagen.make_batch("paper_re1e3", n, B, seed=2)
+    r = np.random.default_rng(17).standard_normal((B, n, n)).astype(np.float32)
+    S = Solver(w, state="f32", f32_split=2, form="nondiv", levels=-1, pack_pairs=True)
+    S.setup(dev(a), b)
+    L = S.levels
+    z = S.apply(dev(r))
+    picks = [0, 1, B - 2, B - 1]
+    got = {p: z[p].cpu().numpy() for p in picks}
+    S.close()
+    del z
+    for p in picks:
+        exp = osv.Solver(w, a[p], b[p], levels=L, form="nondiv").correction(r[p].astype(np.float64))
+        assert_close(got[p], exp, SPLIT2_TOL, f"problem {p}", say)
+
+
+def test_pairs_uneven_full_sizes_converge():
+    """Uneven sizes at their real range (63..2047) in one group call with packed pairs and bf16
+    state: 24 paper problems solved to 1e-8 by the stationary iteration with the trained
+    network; every problem converges, and the oracle's residual of one problem of each size is
+    <= tol."""
+    from paper_2312_11093_amd import GroupSolver
+    sizes = datagen.var_sizes(24, seed=1, workload="paper_re1e3")
+    say("pairs uneven full sizes", sizes)
+    ps = [datagen.make_problem("paper_re1e3", n, i, 4) for i, n in enumerate(sizes)]
+    G = GroupSolver(weights("trained"), state="bf16", u="f64", method="stationary", check_every=2,
+                    levels=-1, form="nondiv", use_graph=True, pack_pairs=True)
+    assert G.aligned
+    G.setup([dev(p.a) for p in ps], np.stack([p.b for p in ps]))
+    u = [torch.zeros((p.n, p.n), dtype=torch.float64, device="cuda") for p in ps]
+    st, it, rr, stat = G.solve([dev(p.f) for p in ps], u, 1e-8, 60)
+    G.close()
+    say("  iters", list(map(int, it)))
+    assert st == M.OK and (stat == 0).all()
+    for n in sorted(set(sizes)):
+        i = sizes.index(n)
+        rho = osv.relres(ps[i].a, ps[i].b, ps[i].f, u[i].cpu().numpy(), "nondiv")
+        say("  n", n, "oracle relres", rho)
+        assert rho <= 1e-8 * (1 + 1e-6)
