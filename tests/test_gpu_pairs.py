@@ -262,3 +262,29 @@ def test_pairs_uneven_full_sizes_converge():
         rho = osv.relres(ps[i].a, ps[i].b, ps[i].f, u[i].cpu().numpy(), "nondiv")
         say("  n", n, "oracle relres", rho)
         assert rho <= 1e-8 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("sizes", [[63], [7, 15, 31, 63], [31, 31]])
+def test_pairs_group_edge_layouts(sizes):
+    """Pair groups whose every size group needs a phantom partner (one problem; four distinct
+    sizes) and one without any (two problems of one size): bf16 state, the trained network, every
+    problem to 1e-8 on the oracle's residual, iteration counts of the unpacked group within one."""
+    from paper_2312_11093_amd import GroupSolver
+    say("pairs group edge layout", sizes)
+    ps = [datagen.make_problem("paper_re1e3", n, i, 12) for i, n in enumerate(sizes)]
+    w = weights("trained")
+    its = {}
+    for pack in (False, True):
+        G = GroupSolver(w, state="bf16", u="f64", method="stationary", check_every=1, levels=-1, form="nondiv",
+                        use_graph=True, pack_pairs=pack)
+        assert G.aligned
+        G.setup([dev(p.a) for p in ps], np.stack([p.b for p in ps]))
+        u = [torch.zeros((p.n, p.n), dtype=torch.float64, device="cuda") for p in ps]
+        st, it, rr, stat = G.solve([dev(p.f) for p in ps], u, 1e-8, 60)
+        G.close()
+        assert st == M.OK and (stat == 0).all()
+        for i, p in enumerate(ps):
+            assert osv.relres(p.a, p.b, p.f, u[i].cpu().numpy(), "nondiv") <= 1e-8 * (1 + 1e-6), (pack, i)
+        its[pack] = np.asarray(it)
+    say("  iters", list(map(int, its[False])), list(map(int, its[True])))
+    assert (np.abs(its[True] - its[False]) <= 1).all()
