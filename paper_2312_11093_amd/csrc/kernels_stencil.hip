@@ -377,7 +377,9 @@ __global__ __launch_bounds__(256) void out_update_kernel(const XT* __restrict__ 
                                                          const int* __restrict__ flags,
                                                          int accumulate, int nprob) {
   constexpr int NO = PAIR ? 2 : 1;            // outputs per slot
-  __shared__ float Y[NO][9][OU_SH * OU_SW];
+  // tap partials of one problem at a time (packed pairs: the two problems of the slot in turn,
+  // from the same staged values, so the LDS of a tile is that of one problem)
+  __shared__ float Y[1][9][OU_SH * OU_SW];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   const int slot = t / tiles_per_prob, tile = t % tiles_per_prob;
   const int b = active != nullptr ? active[slot] : slot;   // compact list of the live problems
@@ -392,45 +394,79 @@ __global__ __launch_bounds__(256) void out_update_kernel(const XT* __restrict__ 
   if (!any) return;
   const int i0 = (tile / tiles_x) * OU_TH - 1, j0 = (tile % tiles_x) * OU_TW - 1;
   const XT* X = x + (size_t)b * n * n * C;
-  for (int q = threadIdx.x; q < OU_SH * OU_SW; q += 256) {
-    const int ii = i0 + q / OU_SW, jj = j0 + q % OU_SW;
-    float y[NO][9];
-#pragma unroll
-    for (int h = 0; h < NO; ++h)
-#pragma unroll
-      for (int k = 0; k < 9; ++k) y[h][k] = 0.f;
-    if (ii >= 0 && ii < n && jj >= 0 && jj < n) {
-      float v[C];
-      load16(X + ((size_t)ii * n + jj) * C, v);
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const int h = PAIR ? c / 8 : 0, cc = PAIR ? c % 8 : c;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) y[h][k] = fmaf(W[cc * 9 + k], v[c], y[h][k]);
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < NO; ++h)
-#pragma unroll
-      for (int k = 0; k < 9; ++k) Y[h][k][q] = y[h][k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int h = 0; h < NO; ++h) {
-    if (!live[h]) continue;
+  // output (r, cc) sits at staged (r + 1, cc + 1); tap (p, q) reads staged (r + p, cc + q)
+  auto outputs = [&](int h) {
     const size_t ubase = (size_t)(PAIR ? 2 * b + h : b) * n * n;
     for (int o = threadIdx.x; o < OU_TH * OU_TW; o += 256) {
       const int r = o / OU_TW, cc = o % OU_TW;
       const int i = i0 + 1 + r, j = j0 + 1 + cc;
       if (i >= n || j >= n) continue;
-      // output (r, cc) sits at staged (r + 1, cc + 1); tap (p, q) reads staged (r + p, cc + q)
       float acc = 0.f;
 #pragma unroll
       for (int p = 0; p < 3; ++p)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) acc += Y[h][p * 3 + q][(r + p) * OU_SW + cc + q];
+        for (int q = 0; q < 3; ++q) acc += Y[0][p * 3 + q][(r + p) * OU_SW + cc + q];
       UT* U = u + ubase + (size_t)i * n + j;
       *U = accumulate ? *U + (UT)acc : (UT)acc;
+    }
+  };
+  if constexpr (!PAIR) {
+    for (int q = threadIdx.x; q < OU_SH * OU_SW; q += 256) {
+      const int ii = i0 + q / OU_SW, jj = j0 + q % OU_SW;
+      float y[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) y[k] = 0.f;
+      if (ii >= 0 && ii < n && jj >= 0 && jj < n) {
+        float v[C];
+        load16(X + ((size_t)ii * n + jj) * C, v);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int k = 0; k < 9; ++k) y[k] = fmaf(W[c * 9 + k], v[c], y[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Y[0][k][q] = y[k];
+    }
+    __syncthreads();
+    if (live[0]) outputs(0);
+  } else {
+    // every staged pixel's sixteen channels are loaded once; the two halves then produce their
+    // tap partials in turn
+    constexpr int QPT = (OU_SH * OU_SW + 255) / 256;   // staged pixels per thread
+    float v[QPT][C];
+#pragma unroll
+    for (int r = 0; r < QPT; ++r) {
+      const int q = threadIdx.x + 256 * r;
+      const int ii = i0 + q / OU_SW, jj = j0 + q % OU_SW;
+      if (q < OU_SH * OU_SW && ii >= 0 && ii < n && jj >= 0 && jj < n) {
+        load16(X + ((size_t)ii * n + jj) * C, v[r]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[r][c] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < NO; ++h) {
+      if (h > 0) __syncthreads();   // the previous problem's outputs have read Y
+#pragma unroll
+      for (int r = 0; r < QPT; ++r) {
+        const int q = threadIdx.x + 256 * r;
+        if (q >= OU_SH * OU_SW) continue;
+        const int ii = i0 + q / OU_SW, jj = j0 + q % OU_SW;
+        float y[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) y[k] = 0.f;
+        if (ii >= 0 && ii < n && jj >= 0 && jj < n) {
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) y[k] = fmaf(W[cc * 9 + k], v[r][8 * h + cc], y[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Y[0][k][q] = y[k];
+      }
+      __syncthreads();
+      if (live[h]) outputs(h);
     }
   }
 }
