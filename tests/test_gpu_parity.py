@@ -399,6 +399,30 @@ def test_full_size_blocks1023_sampled(split):
     S.close()
 
 
+def test_full_size_4095_linearity():
+    """The largest grid the library takes (4095^2, 12 levels, the 4095^2 workload's coefficients),
+    where the oracle cannot evaluate the network in a test's time: a property that holds at any
+    size instead.  The network is linear in its input, so B((r1 + 2 r2)/D) = B(r1/D) + 2 B(r2/D)
+    element by element to float32 rounding (f32 state, both split paths)."""
+    n = 4095
+    say("full-size 4095 linearity")
+    p = datagen.make_problem("grf4095", n, 0, 0)
+    w = datagen.xavier_weights(16, 0)
+    rng = np.random.default_rng(4)
+    r1 = rng.standard_normal((1, n, n)).astype(np.float32)
+    r2 = rng.standard_normal((1, n, n)).astype(np.float32)
+    r3 = (r1.astype(np.float64) + 2.0 * r2).astype(np.float32)
+    for split in (1, 2):
+        S = Solver(w, state="f32", u="f64", f32_split=split)
+        S.setup(dev(p.a).view(1, n, n), p.b.reshape(1, 2))
+        z1 = S.apply(dev(r1)).cpu().numpy().astype(np.float64)
+        z2 = S.apply(dev(r2)).cpu().numpy().astype(np.float64)
+        z3 = S.apply(dev(r3)).cpu().numpy().astype(np.float64)
+        S.close()
+        assert np.isfinite(z3).all()
+        assert_close(z1[0] + 2.0 * z2[0], z3[0], F32_TOL if split == 1 else SPLIT2_TOL, f"split {split}", say)
+
+
 def test_graph_solve_matches_eager():
     """Iterations replayed from a captured hipGraph give bitwise the same iterate, iteration
     counts and residuals as eager launches; the graph is replayed over several solves with
