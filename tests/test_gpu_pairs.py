@@ -288,3 +288,30 @@ def test_pairs_group_edge_layouts(sizes):
         its[pack] = np.asarray(it)
     say("  iters", list(map(int, its[False])), list(map(int, its[True])))
     assert (np.abs(its[True] - its[False]) <= 1).all()
+
+
+def test_pairs_largest_grid_solve():
+    """Packed pairs at the largest grid (two 4095^2 paper problems in one state slot, bf16 state,
+    the paper's level count) solved to 1e-10: the oracle's residual of both solutions <= tol and
+    the unpacked library's iteration counts within one."""
+    n, B, tol = 4095, 2, 1e-10
+    say("pairs 4095^2 x 2 to", tol)
+    w = weights("trained")
+    a, b, f = datagen.make_batch("paper_re1e3", n, B, seed=13)
+    its = {}
+    for pack in (False, True):
+        S = Solver(w, state="bf16", u="f64", form="nondiv", levels=-1, use_graph=True, check_every=1,
+                   pack_pairs=pack)
+        S.setup(dev(a), b)
+        u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+        st, it, rr, ps = S.solve(dev(f), u, tol, 100)
+        S.close()
+        assert st == M.OK and (ps == 0).all()
+        un = u.cpu().numpy()
+        del u
+        for p in range(B):
+            rho = osv.relres(a[p], b[p], f[p], un[p], "nondiv")
+            say("  pack" if pack else "  unpacked", "problem", p, "iters", int(it[p]), "oracle relres", rho)
+            assert rho <= tol * (1 + 1e-6)
+        its[pack] = np.asarray(it)
+    assert (np.abs(its[True] - its[False]) <= 1).all()
