@@ -99,25 +99,25 @@ def test_pairs_bf16_apply_within_derived_bound(n, B):
         assert np.all(err <= bound + 1e-6 * np.max(np.abs(exp)))
 
 
-@pytest.mark.parametrize("state", ["f32", "bf16"])
-def test_pairs_forward_matches_unpacked(state):
-    """Three fixed iterations u += B((f - A u) / D) on a ragged batch (odd B, n = 127): the packed
-    library against the unpacked one with the same weights, per problem.  The two add the same
+@pytest.mark.parametrize("state,udt", [("f32", "f64"), ("bf16", "f64"), ("f32", "f32"), ("bf16", "f32")])
+def test_pairs_forward_matches_unpacked(state, udt):
+    """Three fixed iterations u += B((f - A u) / D) on a ragged batch (odd B, n = 127), u in f64 and
+    in f32: the packed library against the unpacked one with the same weights, per problem.  The two add the same
     products in another order on the matrix cores (the other problem's weights are exact zeros
     in the block-diagonal convs).  f32: the f32 tolerance.  bf16: an ulp of difference in an f32
     sum can flip the bf16 rounding of a stored value (2^-8 relative) that later layers carry;
     1e-2 of the largest value bounds a few such flips."""
-    say("pairs forward vs unpacked", state)
+    say("pairs forward vs unpacked", state, "u", udt)
     n, B, K = 127, 5, 3
     w = weights("trained")
     a, b, f = datagen.make_batch("paper_re1e3", n, B, seed=11)
     out = {}
     for pack in (False, True):
-        S = Solver(w, state=state, u="f64", form="nondiv", levels=-1, pack_pairs=pack)
+        S = Solver(w, state=state, u=udt, form="nondiv", levels=-1, pack_pairs=pack)
         S.setup(dev(a), b)
-        u = torch.zeros((B, n, n), dtype=torch.float64, device="cuda")
+        u = torch.zeros((B, n, n), dtype=S.u_dtype, device="cuda")
         S.forward(dev(f), u, K)
-        out[pack] = u.cpu().numpy()
+        out[pack] = u.cpu().numpy().astype(np.float64)
         S.close()
     tol = F32_TOL if state == "f32" else 1e-2
     for p in range(B):
